@@ -1,0 +1,218 @@
+"""Benchmark: bulk insert and bulk retrieval on a 2^28-slot single-value table at load 0.9.
+
+One step = clear the table, insert n = floor(0.9 * 2^28) distinct uint32 keys with
+uint32 values, then retrieve 2n queries (the n present keys and n absent keys,
+shuffled).  Inputs are synthetic and seeded, resident in HBM before timing.
+Kernel times come from HIP events on the stream the library launches on.
+
+Prints ONE JSON line.  `value` is the whole step's rate in G operations/s
+(inserts + retrievals); the per-phase rates, p50/p99 phase latencies, the HBM
+roofline of the dominant kernel and the CPU oracle's rate sit beside it.
+
+Algorithmic bytes per operation (what the method must move; windows per
+operation from the sequential probing model at this load, double hashing,
+W = 16, used for every configuration so extra probing earns no credit):
+  insert    8 + 128 * 1.109 + 128                      = 277.95 B
+  retrieve  present 9 + 128 * 1.109, absent 9 + 128 * 2.127, 50/50 mix = 216.1 B
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+W_HIT, W_MISS = 1.109, 2.127            # windows per present / absent key at load 0.9
+B_INSERT = 8 + 128 * W_HIT + 128        # key+value in, windows read, claimed line written back
+B_RETRIEVE = 0.5 * (9 + 128 * W_HIT) + 0.5 * (9 + 128 * W_MISS)
+KERNEL_NAMES = {"insert": "k_insert_unique", "retrieve": "k_retrieve"}
+
+
+def _parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--log2-capacity", type=int, default=28)
+    ap.add_argument("--load", type=float, default=0.9)
+    ap.add_argument("--scheme", default="double")
+    ap.add_argument("--window", type=int, default=16)
+    ap.add_argument("--group-insert", type=int, default=4)
+    ap.add_argument("--group-query", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-log2", type=int, default=25)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="also run one device copy of this size (HBM counter calibration)")
+    return ap.parse_args()
+
+
+def _csrc_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2009_07914_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(f.encode())
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel: str, workload: str):
+    """HBM bytes per launch from committed counter runs, if they match the current kernels."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(p))[workload][kernel]
+    except Exception:
+        return None
+    if rec.get("csrc_sha") != _csrc_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def _cpu_baseline(w, log2n: int):
+    """The oracle as it stands, single thread, on a bounded sample of the same workload."""
+    import numpy as np
+    import oracle
+
+    m = 1 << log2n
+    keys, vals = w["keys"][:m], w["values"][:m]
+    q = np.concatenate([keys, w["absent"][:m]])
+    t = oracle.OracleTable(oracle.SINGLE, 1 << 28)
+    t0 = time.perf_counter()
+    t.insert(keys, vals)
+    t1 = time.perf_counter()
+    t.retrieve(q)
+    t2 = time.perf_counter()
+    ops = keys.size + q.size
+    return {"value": round(ops / (t2 - t0) / 1e9, 6), "unit": "G ops/s", "cores": 1, "kind": "oracle",
+            "sample": f"first 2^{log2n} keys inserted, then 2^{log2n + 1} queries (50/50 present/absent) "
+                      f"of the same workload; insert {keys.size / (t1 - t0) / 1e6:.2f} M/s, "
+                      f"retrieve {q.size / (t2 - t1) / 1e6:.2f} M/s, {t2 - t0:.1f} s"}
+
+
+def main():
+    args = _parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (no sharding); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    lib = os.path.join(ROOT, "paper_2009_07914_amd", "libhc.so")
+    if not os.path.exists(lib):
+        import __graft_entry__
+        __graft_entry__.build()
+    import gen
+    import paper_2009_07914_amd as hc
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    cap = 1 << args.log2_capacity
+    t_gen = time.perf_counter()
+    w = gen.single_value_workload(cap, args.load, gen.SEED_BASE + 1)
+    n = w["n"]
+    print(f"# workload generated in {time.perf_counter() - t_gen:.1f} s: n={n}", file=sys.stderr, flush=True)
+
+    table = hc.Table("single", cap, scheme=args.scheme, window=args.window, group=args.group_insert,
+                     device=dev)
+    keys = torch.from_numpy(w["keys"]).to(dev)
+    vals = torch.from_numpy(w["values"]).to(dev)
+    q = torch.from_numpy(w["queries"]).to(dev)
+    vout = torch.empty(q.numel(), dtype=torch.uint32, device=dev)
+    fout = torch.empty(q.numel(), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+
+    def step(record=None):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        hc.hc_clear(table.handle, stream)
+        ev[0].record(stream)
+        hc.hc_insert(table.handle, keys, vals, None, args.group_insert, stream)
+        ev[1].record(stream)
+        ev[2].record(stream)
+        hc.hc_retrieve(table.handle, q, vout, fout, args.group_query, stream)
+        ev[3].record(stream)
+        if record is not None:
+            record.append(ev)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(evs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ins_ms = [e[0].elapsed_time(e[1]) for e in evs]
+    ret_ms = [e[2].elapsed_time(e[3]) for e in evs]
+
+    # parity on the timed outputs: size, and every query's value / found flag
+    assert table.size() == n, "size mismatch after insert"
+    f = fout.cpu().numpy()
+    v = vout.cpu().numpy()
+    src = w["query_src"]
+    present = src < n                       # query j is (present ++ absent)[src[j]]
+    assert np.array_equal(f.astype(bool), present), "found flags disagree with the key sets"
+    assert np.array_equal(v[present], w["values"][src[present].astype(np.int64)]), "retrieved values disagree"
+    assert not v[~present].any()
+    del src, present, f, v
+
+    ms_step = wall * 1000 / args.steps
+    ins_avg, ret_avg = statistics.mean(ins_ms), statistics.mean(ret_ms)
+    ins_gops = n / (ins_avg * 1e-3) / 1e9
+    ret_gops = q.numel() / (ret_avg * 1e-3) / 1e9
+    ins_gbs = n * B_INSERT / (ins_avg * 1e-3) / 1e9
+    ret_gbs = q.numel() * B_RETRIEVE / (ret_avg * 1e-3) / 1e9
+    dom = "insert" if sum(ins_ms) >= sum(ret_ms) else "retrieve"
+    workload = f"single_value_l{args.log2_capacity}_a{args.load}"
+    dom_gbs = ins_gbs if dom == "insert" else ret_gbs
+    tr = _traffic(KERNEL_NAMES[dom], workload)
+
+    def pct(xs, p):
+        xs = sorted(xs)
+        return xs[min(len(xs) - 1, int(round(p / 100 * (len(xs) - 1))))]
+
+    out = {
+        "metric": "G inserts/s and G retrievals/s at load 0.9 (uint32 k/v), % of HBM peak; p99 latency",
+        "value": round((n + q.numel()) / (ms_step * 1e-3) / 1e9, 4),
+        "unit": "G ops/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "single-value table, 2^%d slots (%d GiB), load %.2f, uint32 keys uniform distinct, "
+                               "insert all then retrieve 50%% present / 50%% absent" %
+                               (args.log2_capacity, (cap * 8) >> 30, args.load),
+                   "capacity": table.capacity, "n_insert": n, "n_retrieve": q.numel(),
+                   "scheme": args.scheme, "window": args.window,
+                   "group_insert": args.group_insert, "group_query": args.group_query},
+        "insert_gops": round(ins_gops, 4), "retrieve_gops": round(ret_gops, 4),
+        "insert_ms": {"mean": round(ins_avg, 4), "p50": round(pct(ins_ms, 50), 4), "p99": round(pct(ins_ms, 99), 4)},
+        "retrieve_ms": {"mean": round(ret_avg, 4), "p50": round(pct(ret_ms, 50), 4), "p99": round(pct(ret_ms, 99), 4)},
+        "insert_hbm_frac": round(ins_gbs / HBM_PEAK_GBS, 4),
+        "retrieve_hbm_frac": round(ret_gbs / HBM_PEAK_GBS, 4),
+        "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": round(dom_gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": tr},
+        "cpu_baseline": None,
+    }
+    if args.calibrate_copy_mib:
+        a = torch.empty(args.calibrate_copy_mib << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+    del keys, vals, q, vout, fout
+    table.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = _cpu_baseline(w, args.cpu_sample_log2)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

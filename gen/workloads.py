@@ -38,11 +38,14 @@ def single_value_workload(capacity: int, load: float, seed: int, erase_frac: flo
     present = keys(kseed, 1, n)
     absent = keys(kseed, n + 1, n)
     vals = values(derive_seed(seed, 2), n)
-    queries = shuffle(derive_seed(seed, 3), np.concatenate([present, absent]))
+    src = permutation(derive_seed(seed, 3), 2 * n)   # query j is (present ++ absent)[src[j]]
+    both = np.concatenate([present, absent])
+    queries = both[src.astype(np.int64)] if n else both
+    del both
     n_erase = int(math.floor(erase_frac * n))
     erase = shuffle(derive_seed(seed, 4), present)[:n_erase].copy()
     return {"n": n, "keys": present, "values": vals, "absent": absent,
-            "queries": queries, "erase": erase}
+            "queries": queries, "query_src": src, "erase": erase}
 
 
 def multi_value_zipf_workload(n_pairs: int, n_ranks: int, s: float, seed: int) -> dict:

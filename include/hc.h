@@ -1,0 +1,174 @@
+/*
+ * hc.h -- C ABI of the MI355X (gfx950) cooperative-probing hash tables.
+ *
+ * The operations follow WarpCore (Juenger et al., arXiv 2009.07914):
+ *   - open-addressing tables whose slots hold a key/value pair bit-packed into
+ *     one 64-bit word, so a single 64-bit compare-and-swap stores both
+ *     (Sec. IV-B1, packed AoS layout);
+ *   - the Cooperative Probing Scheme: a group of g lanes loads one window of
+ *     W consecutive slots, votes on it, and the lowest candidate slot is
+ *     claimed with CAS; the start of each window comes from an outer probing
+ *     scheme (Sec. IV-B2; linear, quadratic or double hashing of Sec. II);
+ *   - host-callable bulk operations over device arrays, one group per input
+ *     element (Sec. IV-B3), results written to caller-allocated device
+ *     arrays (Sec. IV-B4), a two-pass count / prefix-sum / write retrieval of
+ *     all values of a multi-value table (Sec. IV-B4), deletion by tombstone
+ *     (Sec. IV-B5), asynchronous on a stream except where a value is returned
+ *     to the host (Sec. IV-D).
+ *
+ * Conventions for every call:
+ *   - Pointers named d_* are device memory owned by the caller; the library
+ *     never frees them.  h_* pointers are host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls are ordered on that stream and return before the work completes,
+ *     except calls with an h_* output, which synchronise the stream.
+ *   - n == 0 is a no-op returning HC_OK.  A NULL required pointer, a bad
+ *     group size or window gives HC_E_ARG and launches nothing.
+ *   - `group` is the group size g (1, 2, 4, 8, 16, 32 or 64 lanes of a
+ *     64-lane wavefront); 0 selects the table's default.  Results do not
+ *     depend on g (Sec. IV-B2: a fixed window walked by any group size).
+ *   - Keys 0 (empty indicator) and 0xFFFFFFFF (tombstone) are reserved;
+ *     values are unrestricted.
+ *   - Element outcomes go to the optional d_status array (uint8, one per
+ *     input): HC_S_*.  A duplicate key is a warning, not an error.
+ *   - Concurrency (Sec. IV-D): calls of the same kind, and reads, may
+ *     overlap on one table; a write call must not overlap a call of another
+ *     kind on the same table.  A handle is used by one host thread at a time.
+ *   - Errors: every call returns hc_err; hc_last_error() gives a message for
+ *     the calling thread's last failure.  No C++ exception crosses the ABI.
+ *     A device fault inside a kernel is not recoverable by the library.
+ */
+#ifndef HC_H
+#define HC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hc_table_s* hc_table;
+
+/* Table kinds (Sec. IV: SingleValueHashTable, MultiValueHashTable, CountingHashTable). */
+enum { HC_SINGLE_VALUE = 0, HC_MULTI_VALUE = 1, HC_COUNTING = 2 };
+
+/* Outer probing schemes over windows (Sec. II):
+ *   linear     w_l = (h + l) mod P
+ *   quadratic  w_l = (h + l(l+1)/2) mod P, P a power of two (visits every window)
+ *   double     w_l = (h + l s) mod P, s odd (P a power of two) or s in [1,P-1] (P prime) */
+enum { HC_LINEAR = 0, HC_QUADRATIC = 1, HC_DOUBLE = 2 };
+
+typedef enum {
+  HC_OK = 0,
+  HC_E_ARG = 1,     /* invalid argument */
+  HC_E_NOMEM = 2,   /* device allocation failed */
+  HC_E_KIND = 3,    /* operation not defined for this table kind */
+  HC_E_DEVICE = 4   /* HIP runtime error */
+} hc_err;
+
+/* Per-element status codes written to d_status. */
+enum {
+  HC_S_OK = 0,          /* inserted a new key / erased */
+  HC_S_DUPLICATE = 1,   /* key already present: value replaced (single-value) or count incremented */
+  HC_S_FULL = 2,        /* no reusable slot in the whole probe sequence (Sec. II abort criterion) */
+  HC_S_INVALID_KEY = 3, /* key is 0 or 0xFFFFFFFF; nothing done */
+  HC_S_NOT_FOUND = 4    /* erase of an absent key */
+};
+
+typedef struct {
+  uint32_t scheme;   /* HC_LINEAR / HC_QUADRATIC / HC_DOUBLE */
+  uint32_t window;   /* W, slots per window: 8, 16, 32 or 64 (16 = one 128-byte line) */
+  uint32_t group;    /* default group size g */
+  uint32_t reserved; /* must be 0 */
+  uint64_t seed;     /* hash seed: h(k) uses the low 32 bits, the double-hashing step the high 32 bits */
+} hc_params;
+
+typedef struct {
+  uint32_t kind;
+  uint32_t scheme;
+  uint32_t window;       /* W */
+  uint32_t group;        /* default g */
+  uint64_t windows;      /* P: number of windows */
+  uint64_t capacity;     /* C = P * W slots */
+  uint64_t seed;
+  uint64_t* d_slots;     /* the slot array, C uint64 words (key bits 0-31, value bits 32-63) */
+} hc_table_info;
+
+/* Fill *params with the defaults: double hashing, W = 16, g = 4, a fixed seed. */
+void hc_default_params(hc_params* params);
+
+/* Create a table of `kind` holding at least `capacity` slots on the current device.
+ * The window count is P = ceil(capacity / W), rounded up to a power of two for
+ * quadratic probing and to a prime for double hashing when P is not a power of two
+ * (the cycle-free rule of Sec. IV-B2); hc_info reports the actual C = P * W.
+ * The table starts empty.  params may be NULL (defaults).  Slots are allocated with
+ * hipMalloc and owned by the table.  Errors: HC_E_ARG (bad kind/params, capacity 0,
+ * P > 2^31), HC_E_NOMEM. */
+hc_err hc_create(hc_table* out, uint32_t kind, uint64_t capacity, const hc_params* params);
+
+/* Release the table and its device memory (synchronises the device). */
+hc_err hc_destroy(hc_table table);
+
+/* Empty the table: every slot becomes the empty word, size becomes 0 (a fill kernel). */
+hc_err hc_clear(hc_table table, void* stream);
+
+/* Bulk insert of n elements (Sec. IV-B3), one group per element.
+ *   single-value: insert (k, v); a present key keeps its slot and takes v (status DUPLICATE).
+ *                 Within one call, which value of a repeated key survives is unspecified.
+ *   multi-value:  store (k, v) as one more pair, even if identical pairs exist.
+ *   counting:     d_values must be NULL; count(k) += 1 (mod 2^32), a new key starts at 1.
+ * d_keys, d_values: n uint32 each.  d_status: optional, n uint8. */
+hc_err hc_insert(hc_table table, const uint32_t* d_keys, const uint32_t* d_values, uint64_t n,
+                 uint8_t* d_status, uint32_t group, void* stream);
+
+/* Bulk retrieval (Sec. IV-B4): d_values_out[i] = value (single-value), count (counting)
+ * or number of stored pairs (multi-value) of d_keys[i]; d_found_out[i] = 1 if present.
+ * Absent and reserved keys give 0 / 0.  Either output may be NULL. */
+hc_err hc_retrieve(hc_table table, const uint32_t* d_keys, uint64_t n, uint32_t* d_values_out,
+                   uint8_t* d_found_out, uint32_t group, void* stream);
+
+/* Bulk deletion by tombstone (Sec. IV-B5).  Single-value / counting: remove the key
+ * (OK, or NOT_FOUND if absent).  Multi-value: remove every pair of the key; with the
+ * same key repeated in one call the number of removed pairs is exact but which of
+ * the repeats report OK is unspecified.  d_status optional. */
+hc_err hc_erase(hc_table table, const uint32_t* d_keys, uint64_t n, uint8_t* d_status, uint32_t group,
+                void* stream);
+
+/* Multi-value pass 1 (Sec. IV-B4): d_offsets (n+1 uint64) receives the exclusive prefix sum
+ * of the per-query value counts, d_offsets[n] = total; d_counts (optional, n uint32) the
+ * counts themselves; *h_total (optional) the total, which synchronises the stream.
+ * Multi-value tables only (HC_E_KIND otherwise). */
+hc_err hc_count_values(hc_table table, const uint32_t* d_keys, uint64_t n, uint32_t* d_counts,
+                       uint64_t* d_offsets, uint64_t* h_total, uint32_t group, void* stream);
+
+/* Multi-value pass 2 (Sec. IV-B4): writes the values of d_keys[i] to
+ * d_values_out[d_offsets[i] .. d_offsets[i+1]); the order inside a segment is unspecified.
+ * d_offsets must come from hc_count_values on the same keys with no write call in between;
+ * writes never leave a segment.  Multi-value tables only. */
+hc_err hc_retrieve_all(hc_table table, const uint32_t* d_keys, uint64_t n, const uint64_t* d_offsets,
+                       uint32_t* d_values_out, uint32_t group, void* stream);
+
+/* Live entries (single-value / counting: keys; multi-value: pairs).  Synchronises the stream. */
+hc_err hc_size(hc_table table, uint64_t* h_out, void* stream);
+
+/* size / capacity (Sec. II load factor; tombstones are not counted).  Synchronises the stream. */
+hc_err hc_load_factor(hc_table table, double* h_out, void* stream);
+
+/* Actual capacity C (after rounding). */
+hc_err hc_capacity(hc_table table, uint64_t* h_out);
+
+/* Table geometry and the device address of its slot array. */
+hc_err hc_info(hc_table table, hc_table_info* h_out);
+
+/* Copy the C slot words into caller memory d_dst (C uint64, device), on the stream. */
+hc_err hc_dump_slots(hc_table table, uint64_t* d_dst, void* stream);
+
+/* Static text for an error code, and the calling thread's last error message. */
+const char* hc_error_string(hc_err err);
+const char* hc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HC_H */

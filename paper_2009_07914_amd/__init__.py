@@ -1,0 +1,270 @@
+"""Python binding of libhc.so, the MI355X cooperative-probing hash tables.
+
+Argument marshalling only: every operation runs in the library's HIP kernels.
+Device arrays are torch tensors on the table's GPU (PyTorch supplies device
+memory and streams); the functions mirror the C ABI of ``include/hc.h`` one to
+one, and ``Table`` wraps a handle for convenience.  There is no CPU fallback:
+if ``libhc.so`` is missing this module raises on import.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # loads the HIP runtime first, so libhc.so binds to the same one
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2009_07914_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+SINGLE_VALUE, MULTI_VALUE, COUNTING = 0, 1, 2
+LINEAR, QUADRATIC, DOUBLE = 0, 1, 2
+S_OK, S_DUPLICATE, S_FULL, S_INVALID_KEY, S_NOT_FOUND = 0, 1, 2, 3, 4
+E_OK, E_ARG, E_NOMEM, E_KIND, E_DEVICE = 0, 1, 2, 3, 4
+
+SCHEMES = {"linear": LINEAR, "quadratic": QUADRATIC, "double": DOUBLE}
+KINDS = {"single": SINGLE_VALUE, "multi": MULTI_VALUE, "counting": COUNTING}
+
+
+class HcParams(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_uint32), ("window", ctypes.c_uint32), ("group", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+
+
+class HcTableInfo(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("scheme", ctypes.c_uint32), ("window", ctypes.c_uint32),
+                ("group", ctypes.c_uint32), ("windows", ctypes.c_uint64), ("capacity", ctypes.c_uint64),
+                ("seed", ctypes.c_uint64), ("d_slots", ctypes.c_void_p)]
+
+
+_p, _u32, _u64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
+_SIGS = {
+    "hc_default_params": ([ctypes.POINTER(HcParams)], None),
+    "hc_create": ([ctypes.POINTER(_p), _u32, _u64, ctypes.POINTER(HcParams)], ctypes.c_int),
+    "hc_destroy": ([_p], ctypes.c_int),
+    "hc_clear": ([_p, _p], ctypes.c_int),
+    "hc_insert": ([_p, _p, _p, _u64, _p, _u32, _p], ctypes.c_int),
+    "hc_retrieve": ([_p, _p, _u64, _p, _p, _u32, _p], ctypes.c_int),
+    "hc_erase": ([_p, _p, _u64, _p, _u32, _p], ctypes.c_int),
+    "hc_count_values": ([_p, _p, _u64, _p, _p, ctypes.POINTER(_u64), _u32, _p], ctypes.c_int),
+    "hc_retrieve_all": ([_p, _p, _u64, _p, _p, _u32, _p], ctypes.c_int),
+    "hc_size": ([_p, ctypes.POINTER(_u64), _p], ctypes.c_int),
+    "hc_load_factor": ([_p, ctypes.POINTER(ctypes.c_double), _p], ctypes.c_int),
+    "hc_capacity": ([_p, ctypes.POINTER(_u64)], ctypes.c_int),
+    "hc_info": ([_p, ctypes.POINTER(HcTableInfo)], ctypes.c_int),
+    "hc_dump_slots": ([_p, _p, _p], ctypes.c_int),
+    "hc_error_string": ([ctypes.c_int], ctypes.c_char_p),
+    "hc_last_error": ([], ctypes.c_char_p),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+class HcError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = _lib.hc_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {_lib.hc_error_string(code).decode()} ({msg})")
+
+
+def _check(rc: int, where: str):
+    if rc != E_OK:
+        raise HcError(rc, where)
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _dptr(t, dtype, what, n=None):
+    """Device pointer of a contiguous tensor of ``dtype`` on a GPU (or None)."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{what} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if n is not None and t.numel() < n:
+        raise ValueError(f"{what} has {t.numel()} elements, needs {n}")
+    return t.data_ptr()
+
+
+def _u32t(t, what, n=None):
+    # uint32 data travels in int32 or uint32 tensors (same bits)
+    if t is not None and t.dtype == torch.int32:
+        t = t.view(torch.uint32)
+    return _dptr(t, torch.uint32, what, n)
+
+
+# ---- one-to-one mirrors of the C ABI -------------------------------------------------
+
+def hc_default_params() -> HcParams:
+    p = HcParams()
+    _lib.hc_default_params(ctypes.byref(p))
+    return p
+
+
+def hc_create(kind: int, capacity: int, params: HcParams | None = None) -> int:
+    h = ctypes.c_void_p()
+    _check(_lib.hc_create(ctypes.byref(h), kind, capacity, ctypes.byref(params) if params else None), "hc_create")
+    return h.value
+
+
+def hc_destroy(h: int):
+    _check(_lib.hc_destroy(h), "hc_destroy")
+
+
+def hc_clear(h: int, stream=None):
+    _check(_lib.hc_clear(h, _stream(stream)), "hc_clear")
+
+
+def hc_insert(h: int, keys, values=None, status=None, group: int = 0, stream=None):
+    n = keys.numel()
+    _check(_lib.hc_insert(h, _u32t(keys, "keys"), _u32t(values, "values", n), n,
+                          _dptr(status, torch.uint8, "status", n), group, _stream(stream)), "hc_insert")
+
+
+def hc_retrieve(h: int, keys, values_out=None, found_out=None, group: int = 0, stream=None):
+    n = keys.numel()
+    _check(_lib.hc_retrieve(h, _u32t(keys, "keys"), n, _u32t(values_out, "values_out", n),
+                            _dptr(found_out, torch.uint8, "found_out", n), group, _stream(stream)), "hc_retrieve")
+
+
+def hc_erase(h: int, keys, status=None, group: int = 0, stream=None):
+    n = keys.numel()
+    _check(_lib.hc_erase(h, _u32t(keys, "keys"), n, _dptr(status, torch.uint8, "status", n), group,
+                         _stream(stream)), "hc_erase")
+
+
+def hc_count_values(h: int, keys, offsets, counts=None, want_total: bool = False, group: int = 0,
+                    stream=None):
+    n = keys.numel()
+    tot = ctypes.c_uint64(0)
+    _check(_lib.hc_count_values(h, _u32t(keys, "keys"), n, _u32t(counts, "counts", n),
+                                _dptr(offsets.view(torch.uint64) if offsets.dtype == torch.int64 else offsets,
+                                      torch.uint64, "offsets", n + 1),
+                                ctypes.byref(tot) if want_total else None, group, _stream(stream)),
+           "hc_count_values")
+    return int(tot.value) if want_total else None
+
+
+def hc_retrieve_all(h: int, keys, offsets, values_out, group: int = 0, stream=None):
+    n = keys.numel()
+    off = offsets.view(torch.uint64) if offsets.dtype == torch.int64 else offsets
+    _check(_lib.hc_retrieve_all(h, _u32t(keys, "keys"), n, _dptr(off, torch.uint64, "offsets", n + 1),
+                                _u32t(values_out, "values_out"), group, _stream(stream)), "hc_retrieve_all")
+
+
+def hc_size(h: int, stream=None) -> int:
+    out = ctypes.c_uint64(0)
+    _check(_lib.hc_size(h, ctypes.byref(out), _stream(stream)), "hc_size")
+    return int(out.value)
+
+
+def hc_load_factor(h: int, stream=None) -> float:
+    out = ctypes.c_double(0)
+    _check(_lib.hc_load_factor(h, ctypes.byref(out), _stream(stream)), "hc_load_factor")
+    return float(out.value)
+
+
+def hc_capacity(h: int) -> int:
+    out = ctypes.c_uint64(0)
+    _check(_lib.hc_capacity(h, ctypes.byref(out)), "hc_capacity")
+    return int(out.value)
+
+
+def hc_info(h: int) -> HcTableInfo:
+    out = HcTableInfo()
+    _check(_lib.hc_info(h, ctypes.byref(out)), "hc_info")
+    return out
+
+
+def hc_dump_slots(h: int, dst, stream=None):
+    _check(_lib.hc_dump_slots(h, _dptr(dst, torch.uint64, "dst", hc_capacity(h)), _stream(stream)),
+           "hc_dump_slots")
+
+
+# ---- convenience wrapper ---------------------------------------------------------------
+
+class Table:
+    """A table handle with allocation of outputs.  ``kind``: 'single' | 'multi' | 'counting'."""
+
+    def __init__(self, kind="single", capacity=1 << 20, scheme="double", window=16, group=4,
+                 seed=None, device=None):
+        self.kind = KINDS[kind] if isinstance(kind, str) else int(kind)
+        p = hc_default_params()
+        p.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
+        p.window, p.group = window, group
+        if seed is not None:
+            p.seed = seed & (2**64 - 1)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        with torch.cuda.device(self.device):
+            self.handle = hc_create(self.kind, capacity, p)
+        info = hc_info(self.handle)
+        self.capacity, self.windows, self.window = int(info.capacity), int(info.windows), int(info.window)
+        self.scheme, self.seed, self.group = int(info.scheme), int(info.seed), int(info.group)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                hc_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    def close(self):
+        self.__del__()
+
+    def clear(self, stream=None):
+        hc_clear(self.handle, stream)
+
+    def insert(self, keys, values=None, status=False, group=0, stream=None):
+        st = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device) if status else None
+        hc_insert(self.handle, keys, values, st, group, stream)
+        return st
+
+    def retrieve(self, keys, group=0, stream=None):
+        vals = torch.empty(keys.numel(), dtype=torch.uint32, device=keys.device)
+        found = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
+        hc_retrieve(self.handle, keys, vals, found, group, stream)
+        return vals, found
+
+    def erase(self, keys, status=False, group=0, stream=None):
+        st = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device) if status else None
+        hc_erase(self.handle, keys, st, group, stream)
+        return st
+
+    def count_values(self, keys, group=0, stream=None):
+        counts = torch.empty(keys.numel(), dtype=torch.uint32, device=keys.device)
+        offsets = torch.empty(keys.numel() + 1, dtype=torch.uint64, device=keys.device)
+        total = hc_count_values(self.handle, keys, offsets, counts, True, group, stream)
+        return counts, offsets, total
+
+    def retrieve_all(self, keys, group=0, stream=None):
+        """Two passes (count + prefix sum, then write): returns (offsets, values)."""
+        _, offsets, total = self.count_values(keys, group, stream)
+        vals = torch.empty(max(total, 1), dtype=torch.uint32, device=keys.device)
+        hc_retrieve_all(self.handle, keys, offsets, vals, group, stream)
+        return offsets, vals[:total]
+
+    def size(self, stream=None) -> int:
+        return hc_size(self.handle, stream)
+
+    def load_factor(self, stream=None) -> float:
+        return hc_load_factor(self.handle, stream)
+
+    def dump_slots(self, stream=None):
+        out = torch.empty(self.capacity, dtype=torch.uint64, device=self.device)
+        hc_dump_slots(self.handle, out, stream)
+        return out

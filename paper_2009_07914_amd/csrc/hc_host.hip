@@ -1,0 +1,484 @@
+// C ABI of the cooperative-probing hash tables: handles, allocation, argument
+// checks, stream ordering, the prefix sum of the multi-value count pass and the
+// table fill kernel.  Kernels of the bulk operations live in hc_k_*.hip.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "hc.h"
+#include "hc_device.hpp"
+#include "hc_launch.hpp"
+
+struct hc_table_s {
+  int device;
+  uint32_t kind, scheme, window, group;
+  uint64_t P, C, seed;
+  uint64_t* slots;
+  unsigned long long* d_size;
+  uint64_t* d_tiles;      // prefix-sum workspace (tile sums)
+  uint64_t tiles_cap;     // entries allocated in d_tiles
+};
+
+namespace hc {
+
+static thread_local std::string g_last_error;
+
+hc_err fail(hc_err e, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return e;
+}
+
+static hc_err hip_fail(hipError_t e, const char* what) {
+  return fail(HC_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+hc_err check_launch(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, what);
+  return HC_OK;
+}
+
+int device_cu_count() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] == 0) {
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) cu = 256;
+    cached[dev] = cu;
+  }
+  return cached[dev];
+}
+
+// ---- table fill ----------------------------------------------------------------
+
+__global__ __launch_bounds__(BLOCK) void k_fill_empty(ulonglong2* __restrict__ slots, uint64_t pairs,
+                                                      unsigned long long* __restrict__ size) {
+  const uint64_t stride = (uint64_t)gridDim.x * BLOCK;
+  const ulonglong2 z = {0ull, 0ull};
+  for (uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; i < pairs; i += stride) slots[i] = z;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *size = 0ull;
+}
+
+// ---- exclusive prefix sum, in place, n counts -> n+1 offsets --------------------
+// Three launches: per-tile sums, one-block scan of the tile sums (also writing
+// offsets[n] = total), per-tile scan plus the tile's prefix.
+
+constexpr int SCAN_ITEMS = 8;
+constexpr uint64_t SCAN_TILE = (uint64_t)BLOCK * SCAN_ITEMS;
+
+// Block-wide exclusive scan of one value per thread; returns the prefix, *total the sum.
+__device__ uint64_t block_exclusive_scan(uint64_t x, uint64_t* total) {
+  __shared__ uint64_t wave_tot[BLOCK / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint64_t incl = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t lo = __shfl_up((uint32_t)incl, d, 64);
+    const uint32_t hi = __shfl_up((uint32_t)(incl >> 32), d, 64);
+    if (lane >= d) incl += (uint64_t)lo | ((uint64_t)hi << 32);
+  }
+  if (lane == 63) wave_tot[wave] = incl;
+  __syncthreads();
+  uint64_t before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < BLOCK / 64; ++w) {
+    if (w < wave) before += wave_tot[w];
+    all += wave_tot[w];
+  }
+  __syncthreads();
+  *total = all;
+  return before + incl - x;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_tile_sums(const uint64_t* __restrict__ a, uint64_t n,
+                                                          uint64_t* __restrict__ tiles) {
+  const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
+  uint64_t s = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; ++j)
+    if (base + j < n) s += a[base + j];
+  uint64_t total;
+  block_exclusive_scan(s, &total);
+  if (threadIdx.x == 0) tiles[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_tiles(uint64_t* __restrict__ tiles, uint64_t ntiles,
+                                                      uint64_t* __restrict__ offsets, uint64_t n) {
+  uint64_t carry = 0;
+  for (uint64_t c = 0; c < ntiles; c += SCAN_TILE) {
+    const uint64_t base = c + (uint64_t)threadIdx.x * SCAN_ITEMS;
+    uint64_t v[SCAN_ITEMS];
+    uint64_t s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+      v[j] = (base + j < ntiles) ? tiles[base + j] : 0;
+      s += v[j];
+    }
+    uint64_t total;
+    uint64_t p = carry + block_exclusive_scan(s, &total);
+#pragma unroll
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+      if (base + j < ntiles) tiles[base + j] = p;
+      p += v[j];
+    }
+    carry += total;
+  }
+  if (threadIdx.x == 0) offsets[n] = carry;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_apply(uint64_t* __restrict__ a, uint64_t n,
+                                                      const uint64_t* __restrict__ tiles) {
+  const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
+  uint64_t v[SCAN_ITEMS];
+  uint64_t s = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; ++j) {
+    v[j] = (base + j < n) ? a[base + j] : 0;
+    s += v[j];
+  }
+  uint64_t total;
+  uint64_t p = tiles[blockIdx.x] + block_exclusive_scan(s, &total);
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; ++j) {
+    if (base + j < n) a[base + j] = p;
+    p += v[j];
+  }
+}
+
+static TableView view_of(const hc_table_s* t) {
+  TableView v;
+  v.slots = t->slots;
+  v.size = t->d_size;
+  v.P = (uint32_t)t->P;
+  v.pow2 = (t->P & (t->P - 1)) == 0;
+  v.pmask = v.pow2 ? (uint32_t)(t->P - 1) : 0u;
+  v.scheme = t->scheme;
+  v.seed_lo = (uint32_t)t->seed;
+  v.seed_hi = (uint32_t)(t->seed >> 32);
+  return v;
+}
+
+static bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
+
+static bool is_prime(uint64_t x) {
+  if (x < 2) return false;
+  if (x % 2 == 0) return x == 2;
+  for (uint64_t d = 3; d * d <= x; d += 2)
+    if (x % d == 0) return false;
+  return true;
+}
+
+static hc_err check_table(hc_table t) {
+  if (t == nullptr) return fail(HC_E_ARG, "table handle is NULL");
+  return HC_OK;
+}
+
+static hc_err resolve_group(hc_table t, uint32_t group, uint32_t* out) {
+  const uint32_t g = group ? group : t->group;
+  if (!is_pow2(g) || g > 64) return fail(HC_E_ARG, "group size %u is not a power of two in [1, 64]", g);
+  *out = g;
+  return HC_OK;
+}
+
+static hc_err set_device(hc_table t) {
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(HC_E_DEVICE, "hipGetDevice failed");
+  if (cur != t->device) {
+    const hipError_t e = hipSetDevice(t->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  }
+  return HC_OK;
+}
+
+}  // namespace hc
+
+using namespace hc;
+
+extern "C" {
+
+void hc_default_params(hc_params* p) {
+  if (!p) return;
+  p->scheme = HC_DOUBLE;
+  p->window = 16;
+  p->group = 4;
+  p->reserved = 0;
+  p->seed = 0x5EED0F0C0A5CAD1Eull;
+}
+
+hc_err hc_create(hc_table* out, uint32_t kind, uint64_t capacity, const hc_params* params) {
+  if (out == nullptr) return fail(HC_E_ARG, "out is NULL");
+  *out = nullptr;
+  hc_params p;
+  hc_default_params(&p);
+  if (params) p = *params;
+  if (kind > 2) return fail(HC_E_ARG, "unknown table kind %u", kind);
+  if (p.scheme > 2) return fail(HC_E_ARG, "unknown probing scheme %u", p.scheme);
+  if (!(p.window == 8 || p.window == 16 || p.window == 32 || p.window == 64))
+    return fail(HC_E_ARG, "window %u is not one of 8, 16, 32, 64", p.window);
+  if (!is_pow2(p.group) || p.group > 64) return fail(HC_E_ARG, "group size %u is not a power of two in [1, 64]", p.group);
+  if (p.reserved != 0) return fail(HC_E_ARG, "params.reserved must be 0");
+  if (capacity == 0) return fail(HC_E_ARG, "capacity must be positive");
+  if (capacity > (1ull << 40)) return fail(HC_E_ARG, "capacity %llu too large", (unsigned long long)capacity);
+
+  uint64_t P = (capacity + p.window - 1) / p.window;
+  if (p.scheme == HC_QUADRATIC) {
+    uint64_t q = 1;
+    while (q < P) q <<= 1;
+    P = q;
+  } else if (p.scheme == HC_DOUBLE && !is_pow2(P)) {
+    while (!is_prime(P)) ++P;
+  }
+  if (P > (1ull << 31)) return fail(HC_E_ARG, "window count %llu exceeds 2^31", (unsigned long long)P);
+
+  hc_table_s* t = new (std::nothrow) hc_table_s();
+  if (!t) return fail(HC_E_NOMEM, "host allocation failed");
+  if (hipGetDevice(&t->device) != hipSuccess) {
+    delete t;
+    return fail(HC_E_DEVICE, "hipGetDevice failed");
+  }
+  t->kind = kind;
+  t->scheme = p.scheme;
+  t->window = p.window;
+  t->group = p.group;
+  t->P = P;
+  t->C = P * p.window;
+  t->seed = p.seed;
+  hipError_t e = hipMalloc((void**)&t->slots, t->C * sizeof(uint64_t));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    delete t;
+    return fail(HC_E_NOMEM, "hipMalloc of %llu slots failed: %s", (unsigned long long)P * p.window,
+                hipGetErrorString(e));
+  }
+  e = hipMalloc((void**)&t->d_size, 256);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(t->slots);
+    delete t;
+    return fail(HC_E_NOMEM, "hipMalloc of the size counter failed");
+  }
+  hc_err r = hc_clear(t, nullptr);
+  if (r == HC_OK) {
+    e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) r = hip_fail(e, "hc_create: synchronise");
+  }
+  if (r != HC_OK) {
+    (void)hipFree(t->slots);
+    (void)hipFree(t->d_size);
+    delete t;
+    return r;
+  }
+  *out = t;
+  return HC_OK;
+}
+
+hc_err hc_destroy(hc_table t) {
+  if (t == nullptr) return HC_OK;
+  hc_err r = set_device(t);
+  if (r != HC_OK) return r;
+  hipError_t e = hipDeviceSynchronize();
+  if (t->slots) (void)hipFree(t->slots);
+  if (t->d_size) (void)hipFree(t->d_size);
+  if (t->d_tiles) (void)hipFree(t->d_tiles);
+  delete t;
+  if (e != hipSuccess) return hip_fail(e, "hc_destroy: synchronise");
+  return HC_OK;
+}
+
+hc_err hc_clear(hc_table t, void* stream) {
+  hc_err r = check_table(t);
+  if (r != HC_OK) return r;
+  if ((r = set_device(t)) != HC_OK) return r;
+  const uint64_t pairs = t->C / 2;  // C = P * W with W >= 8: even
+  uint64_t blocks = (pairs + BLOCK - 1) / BLOCK;
+  const uint64_t cap = (uint64_t)device_cu_count() * 16;
+  if (blocks > cap) blocks = cap;
+  if (blocks == 0) blocks = 1;
+  hipLaunchKernelGGL(k_fill_empty, dim3((unsigned)blocks), dim3(BLOCK), 0, (hipStream_t)stream,
+                     reinterpret_cast<ulonglong2*>(t->slots), pairs, t->d_size);
+  return check_launch("clear");
+}
+
+hc_err hc_insert(hc_table t, const uint32_t* d_keys, const uint32_t* d_values, uint64_t n, uint8_t* d_status,
+                 uint32_t group, void* stream) {
+  hc_err r = check_table(t);
+  if (r != HC_OK) return r;
+  uint32_t g;
+  if ((r = resolve_group(t, group, &g)) != HC_OK) return r;
+  if (n == 0) return HC_OK;
+  if (d_keys == nullptr) return fail(HC_E_ARG, "keys is NULL");
+  if (t->kind == HC_COUNTING) {
+    if (d_values != nullptr) return fail(HC_E_ARG, "counting tables take no values");
+  } else if (d_values == nullptr) {
+    return fail(HC_E_ARG, "values is NULL");
+  }
+  if ((r = set_device(t)) != HC_OK) return r;
+  return launch_insert(view_of(t), (int)t->kind, g, t->window, d_keys, d_values, n, d_status, (hipStream_t)stream);
+}
+
+hc_err hc_retrieve(hc_table t, const uint32_t* d_keys, uint64_t n, uint32_t* d_values_out, uint8_t* d_found_out,
+                   uint32_t group, void* stream) {
+  hc_err r = check_table(t);
+  if (r != HC_OK) return r;
+  uint32_t g;
+  if ((r = resolve_group(t, group, &g)) != HC_OK) return r;
+  if (n == 0) return HC_OK;
+  if (d_keys == nullptr) return fail(HC_E_ARG, "keys is NULL");
+  if ((r = set_device(t)) != HC_OK) return r;
+  if (t->kind == HC_MULTI_VALUE)
+    return launch_count_multi(view_of(t), g, t->window, d_keys, n, d_values_out, nullptr, d_found_out,
+                              (hipStream_t)stream);
+  return launch_retrieve(view_of(t), g, t->window, d_keys, n, d_values_out, d_found_out, (hipStream_t)stream);
+}
+
+hc_err hc_erase(hc_table t, const uint32_t* d_keys, uint64_t n, uint8_t* d_status, uint32_t group, void* stream) {
+  hc_err r = check_table(t);
+  if (r != HC_OK) return r;
+  uint32_t g;
+  if ((r = resolve_group(t, group, &g)) != HC_OK) return r;
+  if (n == 0) return HC_OK;
+  if (d_keys == nullptr) return fail(HC_E_ARG, "keys is NULL");
+  if ((r = set_device(t)) != HC_OK) return r;
+  return launch_erase(view_of(t), (int)t->kind, g, t->window, d_keys, n, d_status, (hipStream_t)stream);
+}
+
+hc_err hc_count_values(hc_table t, const uint32_t* d_keys, uint64_t n, uint32_t* d_counts, uint64_t* d_offsets,
+                       uint64_t* h_total, uint32_t group, void* stream) {
+  hc_err r = check_table(t);
+  if (r != HC_OK) return r;
+  if (t->kind != HC_MULTI_VALUE) return fail(HC_E_KIND, "count_values needs a multi-value table");
+  uint32_t g;
+  if ((r = resolve_group(t, group, &g)) != HC_OK) return r;
+  if (d_offsets == nullptr) return fail(HC_E_ARG, "offsets is NULL");
+  if (n > 0 && d_keys == nullptr) return fail(HC_E_ARG, "keys is NULL");
+  if ((r = set_device(t)) != HC_OK) return r;
+  hipStream_t s = (hipStream_t)stream;
+  const uint64_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+  const uint64_t need = ntiles + 1;
+  if (t->tiles_cap < need) {
+    if (t->d_tiles) {
+      hipError_t e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return hip_fail(e, "count_values: synchronise");
+      (void)hipFree(t->d_tiles);
+      t->d_tiles = nullptr;
+      t->tiles_cap = 0;
+    }
+    hipError_t e = hipMalloc((void**)&t->d_tiles, need * sizeof(uint64_t));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(HC_E_NOMEM, "hipMalloc of %llu scan tiles failed", (unsigned long long)need);
+    }
+    t->tiles_cap = need;
+  }
+  if (n > 0) {
+    if ((r = launch_count_multi(view_of(t), g, t->window, d_keys, n, d_counts, d_offsets, nullptr, s)) != HC_OK)
+      return r;
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)ntiles), dim3(BLOCK), 0, s, d_offsets, n, t->d_tiles);
+    if ((r = check_launch("scan tile sums")) != HC_OK) return r;
+  }
+  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(BLOCK), 0, s, t->d_tiles, ntiles, d_offsets, n);
+  if ((r = check_launch("scan tiles")) != HC_OK) return r;
+  if (n > 0) {
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(BLOCK), 0, s, d_offsets, n, t->d_tiles);
+    if ((r = check_launch("scan apply")) != HC_OK) return r;
+  }
+  if (h_total) {
+    hipError_t e = hipMemcpyAsync(h_total, d_offsets + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "count_values: total");
+  }
+  return HC_OK;
+}
+
+hc_err hc_retrieve_all(hc_table t, const uint32_t* d_keys, uint64_t n, const uint64_t* d_offsets,
+                       uint32_t* d_values_out, uint32_t group, void* stream) {
+  hc_err r = check_table(t);
+  if (r != HC_OK) return r;
+  if (t->kind != HC_MULTI_VALUE) return fail(HC_E_KIND, "retrieve_all needs a multi-value table");
+  uint32_t g;
+  if ((r = resolve_group(t, group, &g)) != HC_OK) return r;
+  if (n == 0) return HC_OK;
+  if (d_keys == nullptr || d_offsets == nullptr) return fail(HC_E_ARG, "keys or offsets is NULL");
+  if ((r = set_device(t)) != HC_OK) return r;
+  return launch_write_multi(view_of(t), g, t->window, d_keys, n, d_offsets, d_values_out, (hipStream_t)stream);
+}
+
+hc_err hc_size(hc_table t, uint64_t* h_out, void* stream) {
+  hc_err r = check_table(t);
+  if (r != HC_OK) return r;
+  if (h_out == nullptr) return fail(HC_E_ARG, "out is NULL");
+  if ((r = set_device(t)) != HC_OK) return r;
+  unsigned long long v = 0;
+  hipError_t e = hipMemcpyAsync(&v, t->d_size, sizeof v, hipMemcpyDeviceToHost, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "hc_size");
+  *h_out = v;
+  return HC_OK;
+}
+
+hc_err hc_load_factor(hc_table t, double* h_out, void* stream) {
+  if (h_out == nullptr) return fail(HC_E_ARG, "out is NULL");
+  uint64_t s = 0;
+  hc_err r = hc_size(t, &s, stream);
+  if (r != HC_OK) return r;
+  *h_out = (double)s / (double)t->C;
+  return HC_OK;
+}
+
+hc_err hc_capacity(hc_table t, uint64_t* h_out) {
+  hc_err r = check_table(t);
+  if (r != HC_OK) return r;
+  if (h_out == nullptr) return fail(HC_E_ARG, "out is NULL");
+  *h_out = t->C;
+  return HC_OK;
+}
+
+hc_err hc_info(hc_table t, hc_table_info* h_out) {
+  hc_err r = check_table(t);
+  if (r != HC_OK) return r;
+  if (h_out == nullptr) return fail(HC_E_ARG, "out is NULL");
+  h_out->kind = t->kind;
+  h_out->scheme = t->scheme;
+  h_out->window = t->window;
+  h_out->group = t->group;
+  h_out->windows = t->P;
+  h_out->capacity = t->C;
+  h_out->seed = t->seed;
+  h_out->d_slots = t->slots;
+  return HC_OK;
+}
+
+hc_err hc_dump_slots(hc_table t, uint64_t* d_dst, void* stream) {
+  hc_err r = check_table(t);
+  if (r != HC_OK) return r;
+  if (d_dst == nullptr) return fail(HC_E_ARG, "destination is NULL");
+  if ((r = set_device(t)) != HC_OK) return r;
+  hipError_t e = hipMemcpyAsync(d_dst, t->slots, t->C * sizeof(uint64_t), hipMemcpyDeviceToDevice, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "hc_dump_slots");
+  return HC_OK;
+}
+
+const char* hc_error_string(hc_err err) {
+  switch (err) {
+    case HC_OK: return "ok";
+    case HC_E_ARG: return "invalid argument";
+    case HC_E_NOMEM: return "device allocation failed";
+    case HC_E_KIND: return "operation not defined for this table kind";
+    case HC_E_DEVICE: return "HIP runtime error";
+  }
+  return "unknown error";
+}
+
+const char* hc_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

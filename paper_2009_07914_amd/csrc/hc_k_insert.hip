@@ -1,0 +1,25 @@
+// Insert kernels (single-value, counting, multi-value) for every (G, W).
+#include "hc_kernels.hpp"
+#include "hc_launch.hpp"
+
+namespace hc {
+
+hc_err launch_insert(const TableView& t, int kind, uint32_t G, uint32_t W, const uint32_t* keys,
+                     const uint32_t* values, uint64_t n, uint8_t* status, hipStream_t stream) {
+  return dispatch_gw(G, W, [&](auto g, auto w) -> hc_err {
+    constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
+    if (kind == KIND_SINGLE) {
+      auto k = k_insert_unique<GG, WW, KIND_SINGLE>;
+      hipLaunchKernelGGL(k, dim3(grid_for(k, n, GG)), dim3(BLOCK), 0, stream, t, keys, values, n, status);
+    } else if (kind == KIND_COUNT) {
+      auto k = k_insert_unique<GG, WW, KIND_COUNT>;
+      hipLaunchKernelGGL(k, dim3(grid_for(k, n, GG)), dim3(BLOCK), 0, stream, t, keys, values, n, status);
+    } else {
+      auto k = k_insert_multi<GG, WW>;
+      hipLaunchKernelGGL(k, dim3(grid_for(k, n, GG)), dim3(BLOCK), 0, stream, t, keys, values, n, status);
+    }
+    return check_launch("insert");
+  });
+}
+
+}  // namespace hc

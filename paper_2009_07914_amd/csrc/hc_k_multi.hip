@@ -1,0 +1,27 @@
+// Multi-value count and write kernels for every (G, W).
+#include "hc_kernels.hpp"
+#include "hc_launch.hpp"
+
+namespace hc {
+
+hc_err launch_count_multi(const TableView& t, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n,
+                          uint32_t* counts, uint64_t* offsets, uint8_t* found_out, hipStream_t stream) {
+  return dispatch_gw(G, W, [&](auto g, auto w) -> hc_err {
+    constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
+    auto k = k_count_multi<GG, WW>;
+    hipLaunchKernelGGL(k, dim3(grid_for(k, n, GG)), dim3(BLOCK), 0, stream, t, keys, n, counts, offsets, found_out);
+    return check_launch("count_values");
+  });
+}
+
+hc_err launch_write_multi(const TableView& t, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n,
+                          const uint64_t* offsets, uint32_t* out, hipStream_t stream) {
+  return dispatch_gw(G, W, [&](auto g, auto w) -> hc_err {
+    constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
+    auto k = k_write_multi<GG, WW>;
+    hipLaunchKernelGGL(k, dim3(grid_for(k, n, GG)), dim3(BLOCK), 0, stream, t, keys, n, offsets, out);
+    return check_launch("retrieve_all");
+  });
+}
+
+}  // namespace hc

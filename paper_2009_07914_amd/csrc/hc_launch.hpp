@@ -1,0 +1,83 @@
+// Host-side launch helpers shared by the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "hc.h"
+#include "hc_device.hpp"
+
+namespace hc {
+
+// Record a message for hc_last_error() (thread-local) and return `e`.
+hc_err fail(hc_err e, const char* fmt, ...);
+
+// Number of compute units of the current device (cached per device).
+int device_cu_count();
+
+// Grid for a strided "one group per element" kernel: enough blocks to cover n
+// elements, capped at the resident capacity of the device for this kernel.
+template <typename Kernel>
+inline unsigned grid_for(Kernel kernel, uint64_t n, int G) {
+  static int blocks_per_cu = 0;  // one cache per kernel instance
+  if (blocks_per_cu == 0) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(kernel), BLOCK, 0) !=
+            hipSuccess ||
+        nb <= 0)
+      nb = 1;
+    blocks_per_cu = nb;
+  }
+  const uint64_t gpb = BLOCK / G;
+  const uint64_t need = (n + gpb - 1) / gpb;
+  const uint64_t cap = (uint64_t)device_cu_count() * (uint64_t)blocks_per_cu;
+  const uint64_t g = need < cap ? need : cap;
+  return (unsigned)(g == 0 ? 1 : g);
+}
+
+hc_err check_launch(const char* what);
+
+template <int V>
+using ic = std::integral_constant<int, V>;
+
+// Call f(ic<G>, ic<W>) for runtime G in {1..64} and W in {8,16,32,64}.
+template <int W, typename F>
+inline hc_err dispatch_g(uint32_t G, F&& f) {
+  switch (G) {
+    case 1: return f(ic<1>{}, ic<W>{});
+    case 2: return f(ic<2>{}, ic<W>{});
+    case 4: return f(ic<4>{}, ic<W>{});
+    case 8: return f(ic<8>{}, ic<W>{});
+    case 16: return f(ic<16>{}, ic<W>{});
+    case 32: return f(ic<32>{}, ic<W>{});
+    case 64: return f(ic<64>{}, ic<W>{});
+    default: return fail(HC_E_ARG, "group size %u is not a power of two in [1, 64]", G);
+  }
+}
+
+template <typename F>
+inline hc_err dispatch_gw(uint32_t G, uint32_t W, F&& f) {
+  switch (W) {
+    case 8: return dispatch_g<8>(G, f);
+    case 16: return dispatch_g<16>(G, f);
+    case 32: return dispatch_g<32>(G, f);
+    case 64: return dispatch_g<64>(G, f);
+    default: return fail(HC_E_ARG, "window %u is not one of 8, 16, 32, 64", W);
+  }
+}
+
+// Launchers, one translation unit each.
+hc_err launch_insert(const TableView& t, int kind, uint32_t G, uint32_t W, const uint32_t* keys,
+                     const uint32_t* values, uint64_t n, uint8_t* status, hipStream_t stream);
+hc_err launch_retrieve(const TableView& t, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n,
+                       uint32_t* values_out, uint8_t* found_out, hipStream_t stream);
+hc_err launch_erase(const TableView& t, int kind, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n,
+                    uint8_t* status, hipStream_t stream);
+hc_err launch_count_multi(const TableView& t, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n,
+                          uint32_t* counts, uint64_t* offsets, uint8_t* found_out, hipStream_t stream);
+hc_err launch_write_multi(const TableView& t, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n,
+                          const uint64_t* offsets, uint32_t* out, hipStream_t stream);
+
+}  // namespace hc

@@ -1,0 +1,66 @@
+"""The C ABI library loads on a CPU-only host and exports every symbol include/hc.h declares."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hc.h")
+LIB = os.path.join(ROOT, "paper_2009_07914_amd", "libhc.so")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hc_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_2009_07914_amd import build
+        build.build()
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ["hc_create", "hc_destroy", "hc_clear", "hc_insert", "hc_retrieve", "hc_erase",
+                 "hc_count_values", "hc_retrieve_all", "hc_size", "hc_load_factor", "hc_capacity"]:
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (hc_[a-z_]+)$", out, flags=re.M))
+    assert set(_declared()) <= exported
+
+
+def test_host_side_argument_errors_need_no_gpu(lib):
+    # argument validation happens before any device call
+    lib.hc_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p]
+    lib.hc_last_error.restype = ctypes.c_char_p
+    lib.hc_error_string.restype = ctypes.c_char_p
+    h = ctypes.c_void_p()
+    assert lib.hc_create(ctypes.byref(h), 7, 1024, None) == 1  # bad kind -> HC_E_ARG
+    assert b"kind" in lib.hc_last_error()
+    assert lib.hc_create(ctypes.byref(h), 0, 0, None) == 1     # capacity 0
+    assert lib.hc_create(None, 0, 1024, None) == 1
+    assert lib.hc_insert(None, None, None, 0, None, 0, None) == 1  # NULL handle
+    assert lib.hc_error_string(2) == b"device allocation failed"
+
+
+def test_no_oracle_in_product_path():
+    # the product package never imports or links the oracle
+    pkg = os.path.join(ROOT, "paper_2009_07914_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                src = open(os.path.join(dirpath, f), errors="replace").read()
+                assert "import oracle" not in src and "from oracle" not in src and "liboracle" not in src, f
+    deps = subprocess.run(["objdump", "-p", LIB], capture_output=True, text=True).stdout
+    assert "liboracle" not in deps

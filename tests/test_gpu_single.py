@@ -1,0 +1,177 @@
+"""GPU parity of the single-value table against the CPU oracle (bit-exact).
+
+Inputs are seeded synthetic keys (distinct, uniform over [1, 2^32-2]) and
+SplitMix64 values; queries mix present and absent keys 50/50.  Every output
+element, status and the size are compared with the oracle; the dumped slot
+array is checked against the layout invariants (a key sits before any empty
+position of its own window sequence, no key twice, exact encodings).
+"""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from tests.gpu_util import check_layout, d, h
+
+pytestmark = pytest.mark.gpu
+
+GROUPS = [1, 2, 4, 8, 16, 32, 64]
+WINDOWS = [8, 16, 32, 64]
+SCHEMES = ["linear", "quadratic", "double"]
+
+
+def _roundtrip(hc, cap, load, scheme, window, group, seed, group_query=None):
+    t = hc.Table("single", cap, scheme=scheme, window=window, group=group, seed=seed)
+    assert t.capacity == window * oracle.round_windows(cap, window, hc.SCHEMES[scheme])
+    w = gen.single_value_workload(t.capacity, load, seed)
+    orc = oracle.OracleTable(oracle.SINGLE, t.capacity)
+    st = t.insert(d(w["keys"]), d(w["values"]), status=True)
+    assert np.array_equal(h(st), orc.insert(w["keys"], w["values"]))
+    assert t.size() == orc.size()
+    gq = group_query or group
+    v, f = t.retrieve(d(w["queries"]), group=gq)
+    vo, fo = orc.retrieve(w["queries"])
+    assert np.array_equal(h(v), vo) and np.array_equal(h(f), fo)
+    check_layout(t, oracle.SINGLE)
+    st = t.erase(d(w["erase"]), status=True, group=gq)
+    assert np.array_equal(h(st), orc.erase(w["erase"]))
+    v, f = t.retrieve(d(w["queries"]), group=gq)
+    vo, fo = orc.retrieve(w["queries"])
+    assert np.array_equal(h(v), vo) and np.array_equal(h(f), fo)
+    assert t.size() == orc.size()
+    # re-insert the erased keys with new values: tombstones are reused (Sec. IV-B5)
+    nv = gen.values(seed + 1, w["erase"].size)
+    st = t.insert(d(w["erase"]), d(nv), status=True)
+    assert np.array_equal(h(st), orc.insert(w["erase"], nv))
+    v, f = t.retrieve(d(w["queries"]), group=gq)
+    vo, fo = orc.retrieve(w["queries"])
+    assert np.array_equal(h(v), vo) and np.array_equal(h(f), fo)
+    assert t.size() == orc.size()
+    check_layout(t, oracle.SINGLE)
+    t.close()
+
+
+def test_small_config_linear_g4(hc):
+    """2^20 slots, 0.8 load, linear probing, g=4: insert, query 50/50, erase 10%, re-query."""
+    cap = 1 << 20
+    t = hc.Table("single", cap, scheme="linear", window=16, group=4, seed=gen.SEED_BASE)
+    w = gen.single_value_workload(cap, 0.8, gen.SEED_BASE)
+    assert w["n"] == 838860 and w["queries"].size == 1677720 and w["erase"].size == 83886
+    orc = oracle.OracleTable(oracle.SINGLE, t.capacity)
+    st = t.insert(d(w["keys"]), d(w["values"]), status=True)
+    assert np.array_equal(h(st), orc.insert(w["keys"], w["values"]))
+    assert t.size() == w["n"]
+    v, f = t.retrieve(d(w["queries"]))
+    vo, fo = orc.retrieve(w["queries"])
+    assert np.array_equal(h(v), vo) and np.array_equal(h(f), fo)
+    assert int(h(f).sum()) == w["n"]
+    st = t.erase(d(w["erase"]), status=True)
+    assert np.array_equal(h(st), orc.erase(w["erase"]))
+    v, f = t.retrieve(d(w["queries"]))
+    vo, fo = orc.retrieve(w["queries"])
+    assert np.array_equal(h(v), vo) and np.array_equal(h(f), fo)
+    assert t.size() == orc.size() == w["n"] - w["erase"].size
+    assert abs(t.load_factor() - orc.size() / t.capacity) < 1e-12
+    stats = check_layout(t, oracle.SINGLE)
+    assert stats["tombstones"] == w["erase"].size and stats["live"] == orc.size()
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("window", WINDOWS)
+@pytest.mark.parametrize("group", GROUPS)
+def test_all_group_window_scheme(hc, scheme, window, group):
+    # 3000 windows-ish, ragged capacity (not a multiple of the window for linear), load 0.9
+    cap = 20011 if scheme == "linear" else 1 << 14
+    _roundtrip(hc, cap, 0.9, scheme, window, group, seed=1000 + group * 7 + window)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_high_load_and_prime_windows(hc, scheme):
+    cap = 3001 * 16 if scheme != "quadratic" else 1 << 15
+    _roundtrip(hc, cap, 0.99, scheme, 16, 4, seed=77)
+
+
+@pytest.mark.parametrize("ga,gb", [(1, 64), (4, 16), (64, 2), (8, 1)])
+def test_group_size_independence(hc, ga, gb):
+    """Build with g_a, query/erase with g_b: identical results (Sec. IV-B2)."""
+    _roundtrip(hc, 1 << 15, 0.95, "double", 16, ga, seed=5, group_query=gb)
+
+
+def test_in_batch_duplicates_and_upsert(hc):
+    """A repeated key: one OK, the rest DUPLICATE; the survivor is one of the batch's values."""
+    t = hc.Table("single", 1 << 12, scheme="double", window=16, group=4)
+    base = gen.keys(3, 1, 500)
+    reps = np.repeat(base, 8)
+    perm = gen.permutation(4, reps.size)
+    keys = reps[perm.astype(np.int64)]
+    vals = gen.values(5, keys.size)
+    st = h(t.insert(d(keys), d(vals), status=True))
+    for k in base[:50]:
+        s = st[keys == k]
+        assert (s == hc.S_OK).sum() == 1 and (s == hc.S_DUPLICATE).sum() == 7
+    assert t.size() == base.size
+    v, f = t.retrieve(d(base))
+    v, f = h(v), h(f)
+    assert f.all()
+    for i, k in enumerate(base):
+        assert v[i] in set(vals[keys == k].tolist())
+    # a later single-occurrence upsert is exact
+    nv = gen.values(6, base.size)
+    st = h(t.insert(d(base), d(nv), status=True))
+    assert (st == hc.S_DUPLICATE).all()
+    assert np.array_equal(h(t.retrieve(d(base))[0]), nv) and t.size() == base.size
+    check_layout(t, oracle.SINGLE)
+
+
+def test_reserved_keys_and_empty_batch(hc):
+    t = hc.Table("single", 1024, window=16)
+    keys = np.array([0, 5, 0xFFFFFFFF, 6], dtype=np.uint32)
+    st = h(t.insert(d(keys), d(np.array([1, 2, 3, 4], dtype=np.uint32)), status=True))
+    assert list(st) == [hc.S_INVALID_KEY, hc.S_OK, hc.S_INVALID_KEY, hc.S_OK]
+    v, f = t.retrieve(d(keys))
+    assert list(h(f)) == [0, 1, 0, 1] and list(h(v)) == [0, 2, 0, 4]
+    assert list(h(t.erase(d(keys), status=True))) == [hc.S_INVALID_KEY, hc.S_OK, hc.S_INVALID_KEY, hc.S_OK]
+    e = torch.empty(0, dtype=torch.uint32, device="cuda")
+    t.insert(e, e)
+    t.retrieve(e)
+    t.erase(e)
+    assert t.size() == 0
+
+
+@pytest.mark.parametrize("group", [1, 4, 64])
+def test_overfull_batch(hc, group):
+    """More distinct new keys than free slots: exactly C - size succeed, the rest report FULL."""
+    t = hc.Table("single", 256, scheme="double", window=16, group=group)
+    keys = gen.keys(8, 1, 400)
+    vals = gen.values(8, 400)
+    st = h(t.insert(d(keys), d(vals), status=True))
+    assert (st == hc.S_OK).sum() == t.capacity and (st == hc.S_FULL).sum() == 400 - t.capacity
+    assert t.size() == t.capacity
+    v, f = t.retrieve(d(keys))
+    v, f = h(v), h(f)
+    assert np.array_equal(f.astype(bool), st == hc.S_OK)
+    assert np.array_equal(v[st == hc.S_OK], vals[st == hc.S_OK])
+    # present keys still update in a full table; new ones still fail
+    st2 = h(t.insert(d(keys), d(vals), status=True))
+    assert np.array_equal(st2 == hc.S_DUPLICATE, st == hc.S_OK) and np.array_equal(st2 == hc.S_FULL, st == hc.S_FULL)
+    # erase one, then exactly one new key fits into the tombstone
+    ok_keys = keys[st == hc.S_OK]
+    assert list(h(t.erase(d(ok_keys[:1]), status=True))) == [hc.S_OK]
+    new = gen.keys(9, 1, 5)
+    st3 = h(t.insert(d(new), d(gen.values(9, 5)), status=True))
+    assert (st3 == hc.S_OK).sum() == 1 and (st3 == hc.S_FULL).sum() == 4
+    check_layout(t, oracle.SINGLE)
+
+
+def test_cas_contention_few_keys(hc):
+    """2^22 inserts of only 16 distinct keys from every CU: each key ends in exactly one slot."""
+    t = hc.Table("single", 1 << 16, scheme="double", window=16, group=4)
+    base = gen.keys(10, 1, 16)
+    keys = base[(gen.uniform(11, 0, 15, 1 << 22)).astype(np.int64)]
+    vals = gen.values(12, keys.size)
+    st = h(t.insert(d(keys), d(vals), status=True))
+    assert (st == hc.S_OK).sum() == 16 and (st == hc.S_DUPLICATE).sum() == keys.size - 16
+    assert t.size() == 16
+    st = check_layout(t, oracle.SINGLE)
+    assert st["live"] == 16
