@@ -2,11 +2,9 @@
 //
 // Launch shape: BLOCK threads per block, G lanes per operation (Sec. IV-B3: one
 // group per input element).  The grid is sized to the resident capacity of the
-// device and every group walks the batch with a stride, so a group that finishes
-// its element picks up the next one in the same loop iteration; the groups of a
-// wavefront therefore never wait for the slowest group of an earlier element.
-// Each loop iteration is one probing step of every live group: load the step's
-// window(s), vote (wavefront ballot), act.
+// device; see drive() for how elements reach groups.  Each loop iteration is one
+// probing step of every live group: load the step's window(s), vote (wavefront
+// ballot), act.
 //
 // Concurrency (Sec. IV-D): within one launch, slots only move from reusable
 // (empty or tombstone) to occupied, and an occupied slot keeps its key.  Plain
@@ -37,12 +35,13 @@ __device__ __forceinline__ int lowbit(uint64_t m) { return __ffsll((unsigned lon
 __device__ __forceinline__ uint32_t popcount(uint32_t m) { return (uint32_t)__popc(m); }
 __device__ __forceinline__ uint32_t popcount(uint64_t m) { return (uint32_t)__popcll((unsigned long long)m); }
 
-// Select word[j] for a runtime j without dynamic register indexing.
-template <int SPL>
-__device__ __forceinline__ uint64_t pick(const uint64_t (&w)[SPL], int j) {
-  uint64_t r = w[0];
+// The word of the lowest set bit of m (0 if none), selected by mask bits rather
+// than by an index, so the slots stay in registers.
+template <int SPL, typename M>
+__device__ __forceinline__ uint64_t pick_lowest(const uint64_t (&w)[SPL], M m) {
+  uint64_t r = 0;
 #pragma unroll
-  for (int q = 1; q < SPL; ++q) r = (j == q) ? w[q] : r;
+  for (int q = SPL - 1; q >= 0; --q) r = ((m >> q) & 1) ? w[q] : r;
   return r;
 }
 
@@ -92,188 +91,262 @@ __device__ __forceinline__ void classify(const uint64_t (&w)[SPL], uint32_t k, b
   if (!valid) m_match = m_empty = m_tomb = 0;
 }
 
+// One probing step of one lane: its slots of the step's window(s) and their classes.
+template <int SPL>
+struct Window {
+  uint64_t word[SPL];
+  MaskT<SPL> match, empty, tomb;
+  uint64_t first;  // slot index of word[0]
+};
+
+template <int G, int W>
+__device__ __forceinline__ void load_step(const TableView& t, const Lane<G, W>& ln, const Seq& s, uint32_t lbase,
+                                          uint32_t k, Window<Lane<G, W>::SPL>& win) {
+  constexpr int SPL = Lane<G, W>::SPL;
+  const bool lv = ln.valid(t, lbase);
+  win.first = (uint64_t)s.w * W + ln.jbase;
+  if (lv) {
+    load_slots<SPL>(t.slots, win.first, win.word);
+  } else {
+#pragma unroll
+    for (int j = 0; j < SPL; ++j) win.word[j] = WORD_EMPTY;
+  }
+  classify<SPL>(win.word, k, lv, win.match, win.empty, win.tomb);
+}
+
+// ------------------------------------------------------------------------------
+// Work distribution.  Block b owns the chunks q*gridDim + b (q = 0, 1, ...) of
+// CH consecutive elements; its groups take the block's elements strictly in
+// order from an LDS counter (one wavefront-aggregated LDS atomic per iteration).
+// The elements in flight in a block therefore stay within a window of about two
+// elements per group, so the 128-byte lines of every output array are completed
+// while they are still in the L2 cache, and the inputs are read as a stream.
+// Each group holds its current element and the reserved next one, whose inputs
+// are already being loaded (Op::load), so starting an element costs no round
+// trip.  Each loop iteration is one probing step of every group holding an
+// element; a group that completes one starts the next in the same iteration, so
+// groups never wait for each other.
+// ------------------------------------------------------------------------------
+template <int G, typename Op>
+__device__ __forceinline__ void drive(uint64_t n, Op& op) {
+  constexpr uint32_t CH = 16u * (uint32_t)(BLOCK / G);
+  __shared__ uint32_t s_next;
+  if (threadIdx.x == 0) s_next = 0;
+  __syncthreads();
+  const GroupCtx<G>& g = op.ln.g;
+  // The next element index of the block for every group with `want_group` set.
+  // Called by every lane of the wavefront.
+  auto reserve = [&](bool want_group) -> uint64_t {
+    const uint64_t want = __ballot(want_group && g.glane == 0);
+    if (want == 0) return ~0ull;
+    const int first = ffs64(want);
+    uint32_t base = 0;
+    if ((int)g.lane == first) base = atomicAdd(&s_next, (uint32_t)__popcll(want));
+    base = __shfl(base, first, 64);
+    const uint32_t rank = (uint32_t)__popcll(want & ((1ull << g.lane) - 1ull));
+    const uint32_t local = g.bcast(base + rank, 0);
+    return ((uint64_t)(local / CH) * gridDim.x + blockIdx.x) * CH + (local % CH);
+  };
+  uint64_t i_next = reserve(true);
+  bool has_next = i_next < n;
+  if (has_next) op.load(i_next);
+  bool active = false;
+  for (;;) {
+    const bool start = !active && has_next;
+    if (start) {
+      op.begin(i_next);
+      active = true;
+    }
+    const uint64_t r = reserve(start);
+    if (start) {
+      i_next = r;
+      has_next = r < n;
+      if (has_next) op.load(r);
+    }
+    if (__ballot(active) == 0) break;
+    if (active && op.step()) active = false;
+  }
+  op.end();
+}
+
 // ------------------------------------------------------------------------------
 // Single-value and counting insert (Sec. IV-B2 steps 1-7; Sec. IV-B3).
 // ------------------------------------------------------------------------------
 template <int G, int W, int KIND>
-__global__ __launch_bounds__(BLOCK) void k_insert_unique(TableView t, const uint32_t* __restrict__ keys,
-                                                         const uint32_t* __restrict__ values, uint64_t n,
-                                                         uint8_t* __restrict__ status) {
+struct InsertUnique {
   using L = Lane<G, W>;
-  constexpr int SPL = L::SPL;
-  const L ln;
-  const auto& g = ln.g;
-  const uint64_t gpb = BLOCK / G;
-  const uint64_t stride = (uint64_t)gridDim.x * gpb;
-  uint64_t i = (uint64_t)blockIdx.x * gpb + threadIdx.x / G;
-
-  bool active = i < n;
+  static constexpr int SPL = L::SPL;
+  L ln;
+  TableView t;
+  const uint32_t* __restrict__ keys;
+  const uint32_t* __restrict__ values;
+  uint8_t* __restrict__ status;
+  uint64_t i = 0, cand_idx = 0;
   uint32_t k = 0, v = 0, lbase = 0;
+  uint32_t k_nx = 0, v_nx = 0;
   Seq s{};
   bool cand = false;
-  uint64_t cand_idx = 0;
   long long added = 0;
 
-  auto begin = [&]() {
-    k = keys[i];
-    v = (KIND == KIND_COUNT) ? 1u : values[i];
+  __device__ __forceinline__ void load(uint64_t op) {
+    k_nx = keys[op];
+    v_nx = (KIND == KIND_COUNT) ? 1u : values[op];
+  }
+  __device__ __forceinline__ void begin(uint64_t op) {
+    i = op;
+    k = k_nx;
+    v = v_nx;
     ln.start(t, k, s, lbase);
     cand = false;
-  };
-  auto finish = [&](uint8_t st) {
-    if (status != nullptr && g.glane == 0) status[i] = st;
-    i += stride;
-    active = i < n;
-    if (active) begin();
-  };
-  auto update = [&](uint64_t idx) {  // key present at idx
+  }
+  __device__ __forceinline__ bool done(uint8_t st) {
+    if (status != nullptr && ln.g.glane == 0) status[i] = st;
+    return true;
+  }
+  __device__ __forceinline__ void update(uint64_t idx) {  // the key is present at idx
     if constexpr (KIND == KIND_COUNT) atomicAdd((unsigned long long*)&t.slots[idx], 1ull << 32);
     else atomicExch((unsigned long long*)&t.slots[idx], (unsigned long long)make_slot(k, v));
-  };
-  if (active) begin();
-
-  while (__ballot(active) != 0) {
-    if (!active) continue;
-    if (reserved_key(k)) { finish(ST_INVALID_KEY); continue; }
-
-    const bool lv = ln.valid(t, lbase);
-    const uint64_t first = (uint64_t)s.w * W + ln.jbase;
-    uint64_t word[SPL];
-    if (lv) load_slots<SPL>(t.slots, first, word);
-    else {
-#pragma unroll
-      for (int j = 0; j < SPL; ++j) word[j] = WORD_EMPTY;
-    }
-    MaskT<SPL> m_match, m_empty, m_tomb;
-    classify<SPL>(word, k, lv, m_match, m_empty, m_tomb);
-    const uint64_t b_match = g.bits(m_match != 0);
-
+  }
+  // CAS a reusable slot: 1 claimed, 2 found the key there (updated), 3 lost to another key.
+  __device__ __forceinline__ uint32_t claim(uint64_t idx, uint64_t expect) {
+    const uint64_t r = atomicCAS((unsigned long long*)&t.slots[idx], (unsigned long long)expect,
+                                 (unsigned long long)make_slot(k, v));
+    if (r == expect) { ++added; return 1; }
+    if (slot_key(r) == k) { update(idx); return 2; }
+    return 3;
+  }
+  __device__ __forceinline__ bool step() {
+    const auto& g = ln.g;
+    if (reserved_key(k)) return done(ST_INVALID_KEY);
+    Window<SPL> win;
+    load_step<G, W>(t, ln, s, lbase, k, win);
+    const uint64_t b_match = g.bits(win.match != 0);
     if (b_match) {  // key present: update in place (Sec. IV-B3 duplicate warning)
-      if (g.glane == (uint32_t)ffs64(b_match)) update(first + (lowbit(m_match)));
-      finish(ST_DUPLICATE);
-      continue;
+      if (g.glane == (uint32_t)ffs64(b_match)) update(win.first + lowbit(win.match));
+      return done(ST_DUPLICATE);
     }
-    const uint64_t b_empty = g.bits(m_empty != 0);
-    MaskT<SPL> m_reuse = m_empty | m_tomb;
-    uint64_t b_reuse = g.bits(m_reuse != 0);
+    const bool any_empty = g.bits(win.empty != 0) != 0;
+    MaskT<SPL> reuse = win.empty | win.tomb;
+    uint64_t b_reuse = g.bits(reuse != 0);
     const bool last = ln.exhausted(t, lbase);
-
-    if (b_empty || last) {  // the key is absent up to here: claim
-      if (cand) {           // a tombstone from an earlier window comes first
+    if (any_empty || last) {  // the key is absent up to here: claim
+      if (cand) {             // a tombstone from an earlier window comes first
         uint32_t outcome = 0;
-        if (g.glane == 0) {
-          const uint64_t r = atomicCAS((unsigned long long*)&t.slots[cand_idx], (unsigned long long)WORD_TOMB,
-                                       (unsigned long long)make_slot(k, v));
-          if (r == WORD_TOMB) { outcome = 1; ++added; }
-          else if (slot_key(r) == k) { update(cand_idx); outcome = 2; }
-          else outcome = 3;
-        }
+        if (g.glane == 0) outcome = claim(cand_idx, WORD_TOMB);
         outcome = g.bcast(outcome, 0);
-        if (outcome == 1) { finish(ST_OK); continue; }
-        if (outcome == 2) { finish(ST_DUPLICATE); continue; }
+        if (outcome == 1) return done(ST_OK);
+        if (outcome == 2) return done(ST_DUPLICATE);
         ln.start(t, k, s, lbase);  // lost it to another key: scan again
         cand = false;
-        continue;
+        return false;
       }
-      uint32_t outcome = 0;
-      while (b_reuse) {
+      while (b_reuse) {  // reusable slots of this step in position order
         const uint32_t r = (uint32_t)ffs64(b_reuse);
+        uint32_t outcome = 0;
         if (g.glane == r) {
-          const int j = lowbit(m_reuse);
-          const uint64_t obs = ((m_empty >> j) & 1) ? WORD_EMPTY : WORD_TOMB;
-          m_reuse &= m_reuse - 1;
-          const uint64_t idx = first + j;
-          const uint64_t res = atomicCAS((unsigned long long*)&t.slots[idx], (unsigned long long)obs,
-                                         (unsigned long long)make_slot(k, v));
-          if (res == obs) { outcome = 1; ++added; }
-          else if (slot_key(res) == k) { update(idx); outcome = 2; }
-          else outcome = 3;
+          const int j = lowbit(reuse);
+          const uint64_t expect = ((win.empty >> j) & 1) ? WORD_EMPTY : WORD_TOMB;
+          reuse &= reuse - 1;
+          outcome = claim(win.first + j, expect);
         }
         outcome = g.bcast(outcome, r);
-        if (outcome != 3) break;
-        outcome = 0;
-        b_reuse = g.bits(m_reuse != 0);
+        if (outcome == 1) return done(ST_OK);
+        if (outcome == 2) return done(ST_DUPLICATE);
+        b_reuse = g.bits(reuse != 0);
       }
-      if (outcome == 1) { finish(ST_OK); continue; }
-      if (outcome == 2) { finish(ST_DUPLICATE); continue; }
-      if (last) { finish(ST_FULL); continue; }
+      if (last) return done(ST_FULL);
     } else if (!cand && b_reuse) {  // first tombstone on the way: remember it
       const uint32_t r = (uint32_t)ffs64(b_reuse);
-      cand_idx = g.bcast64(first + (lowbit(m_reuse)), r);
+      cand_idx = g.bcast64(win.first + lowbit(reuse), r);
       cand = true;
     }
     ln.advance(t, s, lbase);
+    return false;
   }
-  wave_add_to(t.size, added);
+  __device__ __forceinline__ void end() { wave_add_to(t.size, added); }
+};
+
+template <int G, int W, int KIND>
+__global__ __launch_bounds__(BLOCK) void k_insert_unique(TableView t, const uint32_t* __restrict__ keys,
+                                                         const uint32_t* __restrict__ values, uint64_t n,
+                                                         uint8_t* __restrict__ status) {
+  InsertUnique<G, W, KIND> op;
+  op.t = t;
+  op.keys = keys;
+  op.values = values;
+  op.status = status;
+  drive<G>(n, op);
 }
 
 // ------------------------------------------------------------------------------
 // Multi-value insert: store one more pair at the first reusable position.
 // ------------------------------------------------------------------------------
 template <int G, int W>
-__global__ __launch_bounds__(BLOCK) void k_insert_multi(TableView t, const uint32_t* __restrict__ keys,
-                                                        const uint32_t* __restrict__ values, uint64_t n,
-                                                        uint8_t* __restrict__ status) {
+struct InsertMulti {
   using L = Lane<G, W>;
-  constexpr int SPL = L::SPL;
-  const L ln;
-  const auto& g = ln.g;
-  const uint64_t gpb = BLOCK / G;
-  const uint64_t stride = (uint64_t)gridDim.x * gpb;
-  uint64_t i = (uint64_t)blockIdx.x * gpb + threadIdx.x / G;
-
-  bool active = i < n;
-  uint32_t k = 0, v = 0, lbase = 0;
+  static constexpr int SPL = L::SPL;
+  L ln;
+  TableView t;
+  const uint32_t* __restrict__ keys;
+  const uint32_t* __restrict__ values;
+  uint8_t* __restrict__ status;
+  uint64_t i = 0;
+  uint32_t k = 0, v = 0, lbase = 0, k_nx = 0, v_nx = 0;
   Seq s{};
   long long added = 0;
-  auto begin = [&]() {
-    k = keys[i];
-    v = values[i];
-    ln.start(t, k, s, lbase);
-  };
-  auto finish = [&](uint8_t st) {
-    if (status != nullptr && g.glane == 0) status[i] = st;
-    i += stride;
-    active = i < n;
-    if (active) begin();
-  };
-  if (active) begin();
 
-  while (__ballot(active) != 0) {
-    if (!active) continue;
-    if (reserved_key(k)) { finish(ST_INVALID_KEY); continue; }
-    const bool lv = ln.valid(t, lbase);
-    const uint64_t first = (uint64_t)s.w * W + ln.jbase;
-    uint64_t word[SPL];
-    if (lv) load_slots<SPL>(t.slots, first, word);
-    else {
-#pragma unroll
-      for (int j = 0; j < SPL; ++j) word[j] = WORD_EMPTY;
-    }
-    MaskT<SPL> m_match, m_empty, m_tomb;
-    classify<SPL>(word, k, lv, m_match, m_empty, m_tomb);
-    MaskT<SPL> m_reuse = m_empty | m_tomb;
-    uint64_t b_reuse = g.bits(m_reuse != 0);
-    bool done = false;
+  __device__ __forceinline__ void load(uint64_t op) {
+    k_nx = keys[op];
+    v_nx = values[op];
+  }
+  __device__ __forceinline__ void begin(uint64_t op) {
+    i = op;
+    k = k_nx;
+    v = v_nx;
+    ln.start(t, k, s, lbase);
+  }
+  __device__ __forceinline__ bool done(uint8_t st) {
+    if (status != nullptr && ln.g.glane == 0) status[i] = st;
+    return true;
+  }
+  __device__ __forceinline__ bool step() {
+    const auto& g = ln.g;
+    if (reserved_key(k)) return done(ST_INVALID_KEY);
+    Window<SPL> win;
+    load_step<G, W>(t, ln, s, lbase, k, win);
+    MaskT<SPL> reuse = win.empty | win.tomb;
+    uint64_t b_reuse = g.bits(reuse != 0);
     while (b_reuse) {
       const uint32_t r = (uint32_t)ffs64(b_reuse);
       uint32_t ok = 0;
       if (g.glane == r) {
-        const int j = lowbit(m_reuse);
-        const uint64_t obs = ((m_empty >> j) & 1) ? WORD_EMPTY : WORD_TOMB;
-        m_reuse &= m_reuse - 1;
-        const uint64_t res = atomicCAS((unsigned long long*)&t.slots[first + j], (unsigned long long)obs,
+        const int j = lowbit(reuse);
+        const uint64_t expect = ((win.empty >> j) & 1) ? WORD_EMPTY : WORD_TOMB;
+        reuse &= reuse - 1;
+        const uint64_t res = atomicCAS((unsigned long long*)&t.slots[win.first + j], (unsigned long long)expect,
                                        (unsigned long long)make_slot(k, v));
-        if (res == obs) { ok = 1; ++added; }
+        if (res == expect) { ok = 1; ++added; }
       }
-      if (g.bcast(ok, r)) { done = true; break; }
-      b_reuse = g.bits(m_reuse != 0);
+      if (g.bcast(ok, r)) return done(ST_OK);
+      b_reuse = g.bits(reuse != 0);
     }
-    if (done) { finish(ST_OK); continue; }
-    if (ln.exhausted(t, lbase)) { finish(ST_FULL); continue; }
+    if (ln.exhausted(t, lbase)) return done(ST_FULL);
     ln.advance(t, s, lbase);
+    return false;
   }
-  wave_add_to(t.size, added);
+  __device__ __forceinline__ void end() { wave_add_to(t.size, added); }
+};
+
+template <int G, int W>
+__global__ __launch_bounds__(BLOCK) void k_insert_multi(TableView t, const uint32_t* __restrict__ keys,
+                                                        const uint32_t* __restrict__ values, uint64_t n,
+                                                        uint8_t* __restrict__ status) {
+  InsertMulti<G, W> op;
+  op.t = t;
+  op.keys = keys;
+  op.values = values;
+  op.status = status;
+  drive<G>(n, op);
 }
 
 // ------------------------------------------------------------------------------
@@ -281,64 +354,62 @@ __global__ __launch_bounds__(BLOCK) void k_insert_multi(TableView t, const uint3
 // window holding an empty slot.
 // ------------------------------------------------------------------------------
 template <int G, int W>
-__global__ __launch_bounds__(BLOCK) void k_retrieve(TableView t, const uint32_t* __restrict__ keys, uint64_t n,
-                                                    uint32_t* __restrict__ values_out,
-                                                    uint8_t* __restrict__ found_out) {
+struct Retrieve {
   using L = Lane<G, W>;
-  constexpr int SPL = L::SPL;
-  const L ln;
-  const auto& g = ln.g;
-  const uint64_t gpb = BLOCK / G;
-  const uint64_t stride = (uint64_t)gridDim.x * gpb;
-  uint64_t i = (uint64_t)blockIdx.x * gpb + threadIdx.x / G;
-
-  bool active = i < n;
-  uint32_t k = 0, lbase = 0;
+  static constexpr int SPL = L::SPL;
+  L ln;
+  TableView t;
+  const uint32_t* __restrict__ keys;
+  uint32_t* __restrict__ values_out;
+  uint8_t* __restrict__ found_out;
+  uint64_t i = 0;
+  uint32_t k = 0, lbase = 0, k_nx = 0;
   Seq s{};
-  auto begin = [&]() {
-    k = keys[i];
+
+  __device__ __forceinline__ void load(uint64_t op) { k_nx = keys[op]; }
+  __device__ __forceinline__ void begin(uint64_t op) {
+    i = op;
+    k = k_nx;
     ln.start(t, k, s, lbase);
-  };
-  auto next = [&]() {
-    i += stride;
-    active = i < n;
-    if (active) begin();
-  };
-  auto miss = [&]() {
-    if (g.glane == 0) {
+  }
+  __device__ __forceinline__ bool miss() {
+    if (ln.g.glane == 0) {
       if (values_out != nullptr) values_out[i] = 0u;
       if (found_out != nullptr) found_out[i] = 0;
     }
-    next();
-  };
-  if (active) begin();
-
-  while (__ballot(active) != 0) {
-    if (!active) continue;
-    if (reserved_key(k)) { miss(); continue; }
-    const bool lv = ln.valid(t, lbase);
-    const uint64_t first = (uint64_t)s.w * W + ln.jbase;
-    uint64_t word[SPL];
-    if (lv) load_slots<SPL>(t.slots, first, word);
-    else {
-#pragma unroll
-      for (int j = 0; j < SPL; ++j) word[j] = WORD_EMPTY;
-    }
-    MaskT<SPL> m_match, m_empty, m_tomb;
-    classify<SPL>(word, k, lv, m_match, m_empty, m_tomb);
-    const uint64_t b_match = g.bits(m_match != 0);
+    return true;
+  }
+  __device__ __forceinline__ bool step() {
+    const auto& g = ln.g;
+    if (reserved_key(k)) return miss();
+    Window<SPL> win;
+    load_step<G, W>(t, ln, s, lbase, k, win);
+    const uint64_t b_match = g.bits(win.match != 0);
     if (b_match) {
       if (g.glane == (uint32_t)ffs64(b_match)) {
-        const uint64_t w = pick<SPL>(word, lowbit(m_match));
+        const uint64_t w = pick_lowest<SPL>(win.word, win.match);
         if (values_out != nullptr) values_out[i] = slot_value(w);
         if (found_out != nullptr) found_out[i] = 1;
       }
-      next();
-      continue;
+      return true;
     }
-    if (g.bits(m_empty != 0) || ln.exhausted(t, lbase)) { miss(); continue; }
+    if (g.bits(win.empty != 0) || ln.exhausted(t, lbase)) return miss();
     ln.advance(t, s, lbase);
+    return false;
   }
+  __device__ __forceinline__ void end() {}
+};
+
+template <int G, int W>
+__global__ __launch_bounds__(BLOCK) void k_retrieve(TableView t, const uint32_t* __restrict__ keys, uint64_t n,
+                                                    uint32_t* __restrict__ values_out,
+                                                    uint8_t* __restrict__ found_out) {
+  Retrieve<G, W> op;
+  op.t = t;
+  op.keys = keys;
+  op.values_out = values_out;
+  op.found_out = found_out;
+  drive<G>(n, op);
 }
 
 // ------------------------------------------------------------------------------
@@ -346,85 +417,82 @@ __global__ __launch_bounds__(BLOCK) void k_retrieve(TableView t, const uint32_t*
 // the key.  Multi-value: every slot of the key up to the first empty window.
 // ------------------------------------------------------------------------------
 template <int G, int W, int KIND>
-__global__ __launch_bounds__(BLOCK) void k_erase(TableView t, const uint32_t* __restrict__ keys, uint64_t n,
-                                                 uint8_t* __restrict__ status) {
+struct Erase {
   using L = Lane<G, W>;
-  constexpr int SPL = L::SPL;
-  const L ln;
-  const auto& g = ln.g;
-  const uint64_t gpb = BLOCK / G;
-  const uint64_t stride = (uint64_t)gridDim.x * gpb;
-  uint64_t i = (uint64_t)blockIdx.x * gpb + threadIdx.x / G;
-
-  bool active = i < n;
-  uint32_t k = 0, lbase = 0, removed = 0;
+  static constexpr int SPL = L::SPL;
+  L ln;
+  TableView t;
+  const uint32_t* __restrict__ keys;
+  uint8_t* __restrict__ status;
+  uint64_t i = 0;
+  uint32_t k = 0, lbase = 0, removed = 0, k_nx = 0;
   Seq s{};
   long long added = 0;
-  auto begin = [&]() {
-    k = keys[i];
+
+  __device__ __forceinline__ void load(uint64_t op) { k_nx = keys[op]; }
+  __device__ __forceinline__ void begin(uint64_t op) {
+    i = op;
+    k = k_nx;
     ln.start(t, k, s, lbase);
     removed = 0;
-  };
-  auto finish = [&](uint8_t st) {
-    if (status != nullptr && g.glane == 0) status[i] = st;
-    i += stride;
-    active = i < n;
-    if (active) begin();
-  };
-  if (active) begin();
-
-  while (__ballot(active) != 0) {
-    if (!active) continue;
-    if (reserved_key(k)) { finish(ST_INVALID_KEY); continue; }
-    const bool lv = ln.valid(t, lbase);
-    const uint64_t first = (uint64_t)s.w * W + ln.jbase;
-    uint64_t word[SPL];
-    if (lv) load_slots<SPL>(t.slots, first, word);
-    else {
-#pragma unroll
-      for (int j = 0; j < SPL; ++j) word[j] = WORD_EMPTY;
-    }
-    MaskT<SPL> m_match, m_empty, m_tomb;
-    classify<SPL>(word, k, lv, m_match, m_empty, m_tomb);
-    const bool stop = g.bits(m_empty != 0) || ln.exhausted(t, lbase);
-
+  }
+  __device__ __forceinline__ bool done(uint8_t st) {
+    if (status != nullptr && ln.g.glane == 0) status[i] = st;
+    return true;
+  }
+  __device__ __forceinline__ bool step() {
+    const auto& g = ln.g;
+    if (reserved_key(k)) return done(ST_INVALID_KEY);
+    Window<SPL> win;
+    load_step<G, W>(t, ln, s, lbase, k, win);
+    const bool stop = g.bits(win.empty != 0) || ln.exhausted(t, lbase);
     if constexpr (KIND == KIND_MULTI) {
       uint32_t mine = 0;
 #pragma unroll
       for (int j = 0; j < SPL; ++j) {
-        if ((m_match >> j) & 1) {
-          const uint64_t res = atomicCAS((unsigned long long*)&t.slots[first + j], (unsigned long long)word[j],
-                                         (unsigned long long)WORD_TOMB);
-          mine += (res == word[j]);
+        if ((win.match >> j) & 1) {
+          const uint64_t res = atomicCAS((unsigned long long*)&t.slots[win.first + j],
+                                         (unsigned long long)win.word[j], (unsigned long long)WORD_TOMB);
+          mine += (res == win.word[j]);
         }
       }
       added -= mine;
       removed += g.sum(mine);
-      if (stop) { finish(removed ? ST_OK : ST_NOT_FOUND); continue; }
+      if (stop) return done(removed ? ST_OK : ST_NOT_FOUND);
     } else {
-      const uint64_t b_match = g.bits(m_match != 0);
+      const uint64_t b_match = g.bits(win.match != 0);
       if (b_match) {
         const uint32_t r = (uint32_t)ffs64(b_match);
         uint32_t ok = 0;
         if (g.glane == r) {
-          const uint64_t idx = first + (lowbit(m_match));
-          uint64_t obs = pick<SPL>(word, lowbit(m_match));
+          const uint64_t idx = win.first + lowbit(win.match);
+          uint64_t expect = pick_lowest<SPL>(win.word, win.match);
           for (;;) {  // the value half may change under a concurrent update; the key cannot
-            const uint64_t res = atomicCAS((unsigned long long*)&t.slots[idx], (unsigned long long)obs,
+            const uint64_t res = atomicCAS((unsigned long long*)&t.slots[idx], (unsigned long long)expect,
                                            (unsigned long long)WORD_TOMB);
-            if (res == obs) { ok = 1; --added; break; }
+            if (res == expect) { ok = 1; --added; break; }
             if (slot_key(res) != k) break;  // erased by another group meanwhile
-            obs = res;
+            expect = res;
           }
         }
-        finish(g.bcast(ok, r) ? ST_OK : ST_NOT_FOUND);
-        continue;
+        return done(g.bcast(ok, r) ? ST_OK : ST_NOT_FOUND);
       }
-      if (stop) { finish(ST_NOT_FOUND); continue; }
+      if (stop) return done(ST_NOT_FOUND);
     }
     ln.advance(t, s, lbase);
+    return false;
   }
-  wave_add_to(t.size, added);
+  __device__ __forceinline__ void end() { wave_add_to(t.size, added); }
+};
+
+template <int G, int W, int KIND>
+__global__ __launch_bounds__(BLOCK) void k_erase(TableView t, const uint32_t* __restrict__ keys, uint64_t n,
+                                                 uint8_t* __restrict__ status) {
+  Erase<G, W, KIND> op;
+  op.t = t;
+  op.keys = keys;
+  op.status = status;
+  drive<G>(n, op);
 }
 
 // ------------------------------------------------------------------------------
@@ -432,54 +500,58 @@ __global__ __launch_bounds__(BLOCK) void k_erase(TableView t, const uint32_t* __
 // into offsets[i] (to be scanned in place) and optionally into counts / found.
 // ------------------------------------------------------------------------------
 template <int G, int W>
-__global__ __launch_bounds__(BLOCK) void k_count_multi(TableView t, const uint32_t* __restrict__ keys, uint64_t n,
-                                                       uint32_t* __restrict__ counts, uint64_t* __restrict__ offsets,
-                                                       uint8_t* __restrict__ found_out) {
+struct CountMulti {
   using L = Lane<G, W>;
-  constexpr int SPL = L::SPL;
-  const L ln;
-  const auto& g = ln.g;
-  const uint64_t gpb = BLOCK / G;
-  const uint64_t stride = (uint64_t)gridDim.x * gpb;
-  uint64_t i = (uint64_t)blockIdx.x * gpb + threadIdx.x / G;
-
-  bool active = i < n;
-  uint32_t k = 0, lbase = 0, cnt = 0;
+  static constexpr int SPL = L::SPL;
+  L ln;
+  TableView t;
+  const uint32_t* __restrict__ keys;
+  uint32_t* __restrict__ counts;
+  uint64_t* __restrict__ offsets;
+  uint8_t* __restrict__ found_out;
+  uint64_t i = 0;
+  uint32_t k = 0, lbase = 0, cnt = 0, k_nx = 0;
   Seq s{};
-  auto begin = [&]() {
-    k = keys[i];
+
+  __device__ __forceinline__ void load(uint64_t op) { k_nx = keys[op]; }
+  __device__ __forceinline__ void begin(uint64_t op) {
+    i = op;
+    k = k_nx;
     ln.start(t, k, s, lbase);
     cnt = 0;
-  };
-  auto finish = [&]() {
-    if (g.glane == 0) {
+  }
+  __device__ __forceinline__ bool done() {
+    if (ln.g.glane == 0) {
       if (counts != nullptr) counts[i] = cnt;
       if (offsets != nullptr) offsets[i] = cnt;
       if (found_out != nullptr) found_out[i] = cnt != 0;
     }
-    i += stride;
-    active = i < n;
-    if (active) begin();
-  };
-  if (active) begin();
-
-  while (__ballot(active) != 0) {
-    if (!active) continue;
-    if (reserved_key(k)) { finish(); continue; }
-    const bool lv = ln.valid(t, lbase);
-    const uint64_t first = (uint64_t)s.w * W + ln.jbase;
-    uint64_t word[SPL];
-    if (lv) load_slots<SPL>(t.slots, first, word);
-    else {
-#pragma unroll
-      for (int j = 0; j < SPL; ++j) word[j] = WORD_EMPTY;
-    }
-    MaskT<SPL> m_match, m_empty, m_tomb;
-    classify<SPL>(word, k, lv, m_match, m_empty, m_tomb);
-    cnt += g.sum(popcount(m_match));
-    if (g.bits(m_empty != 0) || ln.exhausted(t, lbase)) { finish(); continue; }
-    ln.advance(t, s, lbase);
+    return true;
   }
+  __device__ __forceinline__ bool step() {
+    const auto& g = ln.g;
+    if (reserved_key(k)) return done();
+    Window<SPL> win;
+    load_step<G, W>(t, ln, s, lbase, k, win);
+    cnt += g.sum(popcount(win.match));
+    if (g.bits(win.empty != 0) || ln.exhausted(t, lbase)) return done();
+    ln.advance(t, s, lbase);
+    return false;
+  }
+  __device__ __forceinline__ void end() {}
+};
+
+template <int G, int W>
+__global__ __launch_bounds__(BLOCK) void k_count_multi(TableView t, const uint32_t* __restrict__ keys, uint64_t n,
+                                                       uint32_t* __restrict__ counts, uint64_t* __restrict__ offsets,
+                                                       uint8_t* __restrict__ found_out) {
+  CountMulti<G, W> op;
+  op.t = t;
+  op.keys = keys;
+  op.counts = counts;
+  op.offsets = offsets;
+  op.found_out = found_out;
+  drive<G>(n, op);
 }
 
 // ------------------------------------------------------------------------------
@@ -487,63 +559,65 @@ __global__ __launch_bounds__(BLOCK) void k_count_multi(TableView t, const uint32
 // its segment [offsets[i], offsets[i+1]).
 // ------------------------------------------------------------------------------
 template <int G, int W>
-__global__ __launch_bounds__(BLOCK) void k_write_multi(TableView t, const uint32_t* __restrict__ keys, uint64_t n,
-                                                       const uint64_t* __restrict__ offsets,
-                                                       uint32_t* __restrict__ out) {
+struct WriteMulti {
   using L = Lane<G, W>;
-  constexpr int SPL = L::SPL;
-  const L ln;
-  const auto& g = ln.g;
-  const uint64_t gpb = BLOCK / G;
-  const uint64_t stride = (uint64_t)gridDim.x * gpb;
-  uint64_t i = (uint64_t)blockIdx.x * gpb + threadIdx.x / G;
-
-  bool active = i < n;
-  uint32_t k = 0, lbase = 0;
-  uint64_t base = 0, limit = 0, written = 0;
+  static constexpr int SPL = L::SPL;
+  L ln;
+  TableView t;
+  const uint32_t* __restrict__ keys;
+  const uint64_t* __restrict__ offsets;
+  uint32_t* __restrict__ out;
+  uint64_t i = 0, base = 0, limit = 0, written = 0, base_nx = 0, end_nx = 0;
+  uint32_t k = 0, lbase = 0, k_nx = 0;
   Seq s{};
-  auto begin = [&]() {
-    k = keys[i];
-    ln.start(t, k, s, lbase);
-    base = offsets[i];
-    limit = offsets[i + 1] - base;
-    written = 0;
-  };
-  auto next = [&]() {
-    i += stride;
-    active = i < n;
-    if (active) begin();
-  };
-  if (active) begin();
 
-  while (__ballot(active) != 0) {
-    if (!active) continue;
-    if (reserved_key(k) || limit == 0) { next(); continue; }
-    const bool lv = ln.valid(t, lbase);
-    const uint64_t first = (uint64_t)s.w * W + ln.jbase;
-    uint64_t word[SPL];
-    if (lv) load_slots<SPL>(t.slots, first, word);
-    else {
-#pragma unroll
-      for (int j = 0; j < SPL; ++j) word[j] = WORD_EMPTY;
-    }
-    MaskT<SPL> m_match, m_empty, m_tomb;
-    classify<SPL>(word, k, lv, m_match, m_empty, m_tomb);
-    const uint32_t c = popcount(m_match);
+  __device__ __forceinline__ void load(uint64_t op) {
+    k_nx = keys[op];
+    base_nx = offsets[op];
+    end_nx = offsets[op + 1];
+  }
+  __device__ __forceinline__ void begin(uint64_t op) {
+    i = op;
+    k = k_nx;
+    ln.start(t, k, s, lbase);
+    base = base_nx;
+    limit = end_nx - base_nx;
+    written = 0;
+  }
+  __device__ __forceinline__ bool step() {
+    const auto& g = ln.g;
+    if (reserved_key(k) || limit == 0) return true;
+    Window<SPL> win;
+    load_step<G, W>(t, ln, s, lbase, k, win);
+    const uint32_t c = popcount(win.match);
     const uint32_t before = g.exclusive_scan(c);
     const uint32_t total = g.sum(c);
     uint64_t rank = written + before;
 #pragma unroll
     for (int j = 0; j < SPL; ++j) {
-      if ((m_match >> j) & 1) {
-        if (rank < limit) out[base + rank] = slot_value(word[j]);
+      if ((win.match >> j) & 1) {
+        if (rank < limit) out[base + rank] = slot_value(win.word[j]);
         ++rank;
       }
     }
     written += total;
-    if (written >= limit || g.bits(m_empty != 0) || ln.exhausted(t, lbase)) { next(); continue; }
+    if (written >= limit || g.bits(win.empty != 0) || ln.exhausted(t, lbase)) return true;
     ln.advance(t, s, lbase);
+    return false;
   }
+  __device__ __forceinline__ void end() {}
+};
+
+template <int G, int W>
+__global__ __launch_bounds__(BLOCK) void k_write_multi(TableView t, const uint32_t* __restrict__ keys, uint64_t n,
+                                                       const uint64_t* __restrict__ offsets,
+                                                       uint32_t* __restrict__ out) {
+  WriteMulti<G, W> op;
+  op.t = t;
+  op.keys = keys;
+  op.offsets = offsets;
+  op.out = out;
+  drive<G>(n, op);
 }
 
 }  // namespace hc
