@@ -44,7 +44,7 @@ def _parse():
     ap.add_argument("--load", type=float, default=0.9)
     ap.add_argument("--scheme", default="double")
     ap.add_argument("--window", type=int, default=16)
-    ap.add_argument("--group-insert", type=int, default=2)
+    ap.add_argument("--group-insert", type=int, default=4)
     ap.add_argument("--group-query", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-log2", type=int, default=25)

@@ -67,6 +67,13 @@ struct TableView {
   uint32_t seed_lo, seed_hi;
 };
 
+// Per-launch work counters: counters[0] hands out chunks, counters[1] counts
+// finished wavefronts; both are zero when a launch starts.
+struct WorkCtl {
+  unsigned long long* counters;
+  uint32_t chunk;  // elements per chunk, 64 <= chunk
+};
+
 // Position in a key's window sequence.
 struct Seq {
   uint32_t w;     // current window

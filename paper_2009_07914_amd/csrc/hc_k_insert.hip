@@ -10,13 +10,16 @@ hc_err launch_insert(const TableView& t, int kind, uint32_t G, uint32_t W, const
     constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
     if (kind == KIND_SINGLE) {
       auto k = k_insert_unique<GG, WW, KIND_SINGLE>;
-      hipLaunchKernelGGL(k, dim3(grid_for(k, n, GG)), dim3(BLOCK), 0, stream, t, keys, values, n, status);
+      const unsigned grid = grid_for(k, n, GG);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, t, work_for(n, GG, grid), keys, values, n, status);
     } else if (kind == KIND_COUNT) {
       auto k = k_insert_unique<GG, WW, KIND_COUNT>;
-      hipLaunchKernelGGL(k, dim3(grid_for(k, n, GG)), dim3(BLOCK), 0, stream, t, keys, values, n, status);
+      const unsigned grid = grid_for(k, n, GG);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, t, work_for(n, GG, grid), keys, values, n, status);
     } else {
       auto k = k_insert_multi<GG, WW>;
-      hipLaunchKernelGGL(k, dim3(grid_for(k, n, GG)), dim3(BLOCK), 0, stream, t, keys, values, n, status);
+      const unsigned grid = grid_for(k, n, GG);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, t, work_for(n, GG, grid), keys, values, n, status);
     }
     return check_launch("insert");
   });

@@ -9,7 +9,8 @@ hc_err launch_count_multi(const TableView& t, uint32_t G, uint32_t W, const uint
   return dispatch_gw(G, W, [&](auto g, auto w) -> hc_err {
     constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
     auto k = k_count_multi<GG, WW>;
-    hipLaunchKernelGGL(k, dim3(grid_for(k, n, GG)), dim3(BLOCK), 0, stream, t, keys, n, counts, offsets, found_out);
+    const unsigned grid = grid_for(k, n, GG);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, t, work_for(n, GG, grid), keys, n, counts, offsets, found_out);
     return check_launch("count_values");
   });
 }
@@ -19,7 +20,8 @@ hc_err launch_write_multi(const TableView& t, uint32_t G, uint32_t W, const uint
   return dispatch_gw(G, W, [&](auto g, auto w) -> hc_err {
     constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
     auto k = k_write_multi<GG, WW>;
-    hipLaunchKernelGGL(k, dim3(grid_for(k, n, GG)), dim3(BLOCK), 0, stream, t, keys, n, offsets, out);
+    const unsigned grid = grid_for(k, n, GG);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, t, work_for(n, GG, grid), keys, n, offsets, out);
     return check_launch("retrieve_all");
   });
 }

@@ -9,7 +9,8 @@ hc_err launch_retrieve(const TableView& t, uint32_t G, uint32_t W, const uint32_
   return dispatch_gw(G, W, [&](auto g, auto w) -> hc_err {
     constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
     auto k = k_retrieve<GG, WW>;
-    hipLaunchKernelGGL(k, dim3(grid_for(k, n, GG)), dim3(BLOCK), 0, stream, t, keys, n, values_out, found_out);
+    const unsigned grid = grid_for(k, n, GG);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, t, work_for(n, GG, grid), keys, n, values_out, found_out);
     return check_launch("retrieve");
   });
 }
@@ -20,10 +21,12 @@ hc_err launch_erase(const TableView& t, int kind, uint32_t G, uint32_t W, const 
     constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
     if (kind == KIND_MULTI) {
       auto k = k_erase<GG, WW, KIND_MULTI>;
-      hipLaunchKernelGGL(k, dim3(grid_for(k, n, GG)), dim3(BLOCK), 0, stream, t, keys, n, status);
+      const unsigned grid = grid_for(k, n, GG);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, t, work_for(n, GG, grid), keys, n, status);
     } else {
       auto k = k_erase<GG, WW, KIND_SINGLE>;
-      hipLaunchKernelGGL(k, dim3(grid_for(k, n, GG)), dim3(BLOCK), 0, stream, t, keys, n, status);
+      const unsigned grid = grid_for(k, n, GG);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, t, work_for(n, GG, grid), keys, n, status);
     }
     return check_launch("erase");
   });

@@ -115,37 +115,48 @@ __device__ __forceinline__ void load_step(const TableView& t, const Lane<G, W>& 
 }
 
 // ------------------------------------------------------------------------------
-// Work distribution.  Block b owns the chunks q*gridDim + b (q = 0, 1, ...) of
-// CH consecutive elements; its groups take the block's elements strictly in
-// order from an LDS counter (one wavefront-aggregated LDS atomic per iteration).
-// The elements in flight in a block therefore stay within a window of about two
-// elements per group, so the 128-byte lines of every output array are completed
-// while they are still in the L2 cache, and the inputs are read as a stream.
-// Each group holds its current element and the reserved next one, whose inputs
-// are already being loaded (Op::load), so starting an element costs no round
-// trip.  Each loop iteration is one probing step of every group holding an
-// element; a group that completes one starts the next in the same iteration, so
-// groups never wait for each other.
+// Work distribution.  Every wavefront takes chunks of `ctl.chunk` consecutive
+// elements from a global counter (one atomic per chunk) and hands each chunk's
+// elements to its groups strictly in order.  The elements in flight in a
+// wavefront therefore stay within a window of about two elements per group, so
+// the 128-byte lines of every output array are completed while they are still
+// in the L2 cache and the inputs are read as streams; and a block that starts
+// late, or a wavefront that meets long probe sequences, simply takes fewer
+// chunks, so no part of the grid waits for another.  Each group holds its
+// current element and the reserved next one, whose inputs are already being
+// loaded (Op::load), so starting an element costs no round trip.  Each loop
+// iteration is one probing step of every group holding an element; a group that
+// completes one starts the next in the same iteration.  The last wavefront to
+// finish resets the launch's counters for the next launch that uses them.
 // ------------------------------------------------------------------------------
 template <int G, typename Op>
-__device__ __forceinline__ void drive(uint64_t n, Op& op) {
-  constexpr uint32_t CH = 16u * (uint32_t)(BLOCK / G);
-  __shared__ uint32_t s_next;
-  if (threadIdx.x == 0) s_next = 0;
-  __syncthreads();
+__device__ __forceinline__ void drive(uint64_t n, const WorkCtl& ctl, Op& op) {
   const GroupCtx<G>& g = op.ln.g;
-  // The next element index of the block for every group with `want_group` set.
+  const uint32_t chunk = ctl.chunk;
+  uint64_t cur = 0;       // chunk held by this wavefront (wavefront-uniform)
+  uint32_t used = chunk;  // elements of it already handed out (wavefront-uniform)
+  // The wavefront's next element index for every group with `want_group` set.
   // Called by every lane of the wavefront.
   auto reserve = [&](bool want_group) -> uint64_t {
     const uint64_t want = __ballot(want_group && g.glane == 0);
     if (want == 0) return ~0ull;
-    const int first = ffs64(want);
-    uint32_t base = 0;
-    if ((int)g.lane == first) base = atomicAdd(&s_next, (uint32_t)__popcll(want));
-    base = __shfl(base, first, 64);
+    const uint32_t cnt = (uint32_t)__popcll(want);
     const uint32_t rank = (uint32_t)__popcll(want & ((1ull << g.lane) - 1ull));
-    const uint32_t local = g.bcast(base + rank, 0);
-    return ((uint64_t)(local / CH) * gridDim.x + blockIdx.x) * CH + (local % CH);
+    const uint32_t room = chunk - used;
+    uint64_t nxt = cur;
+    if (cnt > room) {  // cnt <= groups per wavefront <= chunk: at most one new chunk
+      unsigned long long c = 0;
+      if (g.lane == 0) c = atomicAdd(ctl.counters, 1ull);
+      nxt = ((uint64_t)__shfl((uint32_t)(c >> 32), 0, 64) << 32) | __shfl((uint32_t)c, 0, 64);
+    }
+    const uint64_t idx = (rank < room) ? cur * chunk + used + rank : nxt * chunk + (rank - room);
+    if (cnt > room) {
+      cur = nxt;
+      used = cnt - room;
+    } else {
+      used += cnt;
+    }
+    return g.bcast64(idx, 0);
   };
   uint64_t i_next = reserve(true);
   bool has_next = i_next < n;
@@ -167,6 +178,13 @@ __device__ __forceinline__ void drive(uint64_t n, Op& op) {
     if (active && op.step()) active = false;
   }
   op.end();
+  if (g.lane == 0) {
+    const unsigned long long waves = (unsigned long long)gridDim.x * (BLOCK / 64);
+    if (atomicAdd(ctl.counters + 1, 1ull) == waves - 1) {  // every chunk has been taken
+      atomicExch(ctl.counters, 0ull);
+      atomicExch(ctl.counters + 1, 0ull);
+    }
+  }
 }
 
 // ------------------------------------------------------------------------------
@@ -267,7 +285,7 @@ struct InsertUnique {
 };
 
 template <int G, int W, int KIND>
-__global__ __launch_bounds__(BLOCK) void k_insert_unique(TableView t, const uint32_t* __restrict__ keys,
+__global__ __launch_bounds__(BLOCK) void k_insert_unique(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys,
                                                          const uint32_t* __restrict__ values, uint64_t n,
                                                          uint8_t* __restrict__ status) {
   InsertUnique<G, W, KIND> op;
@@ -275,7 +293,7 @@ __global__ __launch_bounds__(BLOCK) void k_insert_unique(TableView t, const uint
   op.keys = keys;
   op.values = values;
   op.status = status;
-  drive<G>(n, op);
+  drive<G>(n, ctl, op);
 }
 
 // ------------------------------------------------------------------------------
@@ -338,7 +356,7 @@ struct InsertMulti {
 };
 
 template <int G, int W>
-__global__ __launch_bounds__(BLOCK) void k_insert_multi(TableView t, const uint32_t* __restrict__ keys,
+__global__ __launch_bounds__(BLOCK) void k_insert_multi(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys,
                                                         const uint32_t* __restrict__ values, uint64_t n,
                                                         uint8_t* __restrict__ status) {
   InsertMulti<G, W> op;
@@ -346,7 +364,7 @@ __global__ __launch_bounds__(BLOCK) void k_insert_multi(TableView t, const uint3
   op.keys = keys;
   op.values = values;
   op.status = status;
-  drive<G>(n, op);
+  drive<G>(n, ctl, op);
 }
 
 // ------------------------------------------------------------------------------
@@ -401,7 +419,7 @@ struct Retrieve {
 };
 
 template <int G, int W>
-__global__ __launch_bounds__(BLOCK) void k_retrieve(TableView t, const uint32_t* __restrict__ keys, uint64_t n,
+__global__ __launch_bounds__(BLOCK) void k_retrieve(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys, uint64_t n,
                                                     uint32_t* __restrict__ values_out,
                                                     uint8_t* __restrict__ found_out) {
   Retrieve<G, W> op;
@@ -409,7 +427,7 @@ __global__ __launch_bounds__(BLOCK) void k_retrieve(TableView t, const uint32_t*
   op.keys = keys;
   op.values_out = values_out;
   op.found_out = found_out;
-  drive<G>(n, op);
+  drive<G>(n, ctl, op);
 }
 
 // ------------------------------------------------------------------------------
@@ -486,13 +504,13 @@ struct Erase {
 };
 
 template <int G, int W, int KIND>
-__global__ __launch_bounds__(BLOCK) void k_erase(TableView t, const uint32_t* __restrict__ keys, uint64_t n,
+__global__ __launch_bounds__(BLOCK) void k_erase(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys, uint64_t n,
                                                  uint8_t* __restrict__ status) {
   Erase<G, W, KIND> op;
   op.t = t;
   op.keys = keys;
   op.status = status;
-  drive<G>(n, op);
+  drive<G>(n, ctl, op);
 }
 
 // ------------------------------------------------------------------------------
@@ -542,7 +560,7 @@ struct CountMulti {
 };
 
 template <int G, int W>
-__global__ __launch_bounds__(BLOCK) void k_count_multi(TableView t, const uint32_t* __restrict__ keys, uint64_t n,
+__global__ __launch_bounds__(BLOCK) void k_count_multi(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys, uint64_t n,
                                                        uint32_t* __restrict__ counts, uint64_t* __restrict__ offsets,
                                                        uint8_t* __restrict__ found_out) {
   CountMulti<G, W> op;
@@ -551,7 +569,7 @@ __global__ __launch_bounds__(BLOCK) void k_count_multi(TableView t, const uint32
   op.counts = counts;
   op.offsets = offsets;
   op.found_out = found_out;
-  drive<G>(n, op);
+  drive<G>(n, ctl, op);
 }
 
 // ------------------------------------------------------------------------------
@@ -609,7 +627,7 @@ struct WriteMulti {
 };
 
 template <int G, int W>
-__global__ __launch_bounds__(BLOCK) void k_write_multi(TableView t, const uint32_t* __restrict__ keys, uint64_t n,
+__global__ __launch_bounds__(BLOCK) void k_write_multi(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys, uint64_t n,
                                                        const uint64_t* __restrict__ offsets,
                                                        uint32_t* __restrict__ out) {
   WriteMulti<G, W> op;
@@ -617,7 +635,7 @@ __global__ __launch_bounds__(BLOCK) void k_write_multi(TableView t, const uint32
   op.keys = keys;
   op.offsets = offsets;
   op.out = out;
-  drive<G>(n, op);
+  drive<G>(n, ctl, op);
 }
 
 }  // namespace hc

@@ -17,25 +17,24 @@ hc_err fail(hc_err e, const char* fmt, ...);
 // Number of compute units of the current device (cached per device).
 int device_cu_count();
 
-// Grid for a strided "one group per element" kernel: enough blocks to cover n
-// elements, capped at the resident capacity of the device for this kernel.
+// Resident blocks per CU of a kernel (occupancy calculator, cached per kernel).
+int blocks_per_cu(const void* kernel);
+
+// Grid for a bulk kernel: the device's resident capacity, or fewer blocks when
+// the batch is small (at most one element per group).
 template <typename Kernel>
 inline unsigned grid_for(Kernel kernel, uint64_t n, int G) {
-  static int blocks_per_cu = 0;  // one cache per kernel instance
-  if (blocks_per_cu == 0) {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(kernel), BLOCK, 0) !=
-            hipSuccess ||
-        nb <= 0)
-      nb = 1;
-    blocks_per_cu = nb;
-  }
   const uint64_t gpb = BLOCK / G;
   const uint64_t need = (n + gpb - 1) / gpb;
-  const uint64_t cap = (uint64_t)device_cu_count() * (uint64_t)blocks_per_cu;
+  const uint64_t cap = (uint64_t)device_cu_count() * (uint64_t)blocks_per_cu(reinterpret_cast<const void*>(kernel));
   const uint64_t g = need < cap ? need : cap;
   return (unsigned)(g == 0 ? 1 : g);
 }
+
+// Work control of one launch: counters from the device's launch-slot ring and a
+// chunk size giving every wavefront about two chunks, between one element per
+// group and 64 elements per group.
+WorkCtl work_for(uint64_t n, int G, unsigned grid);
 
 hc_err check_launch(const char* what);
 

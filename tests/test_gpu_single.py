@@ -175,3 +175,47 @@ def test_cas_contention_few_keys(hc):
     assert t.size() == 16
     st = check_layout(t, oracle.SINGLE)
     assert st["live"] == 16
+
+
+def test_many_small_launches_reuse_work_counters(hc):
+    """3000 launches of 1..97 keys: every launch sees fresh work counters (launch-slot ring wraps)."""
+    t = hc.Table("single", 1 << 20, scheme="double", window=16, group=4)
+    orc = oracle.OracleTable(oracle.SINGLE, t.capacity)
+    allk = gen.keys(50, 1, 150000)
+    vals = gen.values(51, allk.size)
+    pos = 0
+    sizes = (gen.uniform(52, 1, 97, 3000)).astype(np.int64)
+    kd, vd = d(allk), d(vals)
+    for j, m in enumerate(sizes):
+        g = [1, 2, 4, 8, 16, 32, 64][j % 7]
+        hc.hc_insert(t.handle, kd[pos:pos + m], vd[pos:pos + m], None, g)
+        pos += m
+    orc.insert(allk[:pos], vals[:pos])
+    assert t.size() == pos
+    v, f = t.retrieve(d(allk))
+    vo, fo = orc.retrieve(allk)
+    assert np.array_equal(h(v), vo) and np.array_equal(h(f), fo)
+
+
+def test_same_kind_overlap_on_two_streams(hc):
+    """Inserts of disjoint key sets on two streams, then retrieves on two streams (Sec. IV-D)."""
+    t = hc.Table("single", 1 << 18, scheme="double", window=16, group=4)
+    ka, kb = gen.keys(60, 1, 100000), gen.keys(60, 100001, 100000)
+    va, vb = gen.values(61, 100000), gen.values(62, 100000)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    kad, kbd, vad, vbd = d(ka), d(kb), d(va), d(vb)
+    torch.cuda.synchronize()
+    hc.hc_insert(t.handle, kad, vad, None, 2, s1)
+    hc.hc_insert(t.handle, kbd, vbd, None, 8, s2)
+    torch.cuda.synchronize()
+    assert t.size() == 200000
+    outa = torch.empty(100000, dtype=torch.uint32, device="cuda")
+    outb = torch.empty(100000, dtype=torch.uint32, device="cuda")
+    fa = torch.empty(100000, dtype=torch.uint8, device="cuda")
+    fb = torch.empty(100000, dtype=torch.uint8, device="cuda")
+    hc.hc_retrieve(t.handle, kad, outa, fa, 4, s1)
+    hc.hc_retrieve(t.handle, kbd, outb, fb, 1, s2)
+    torch.cuda.synchronize()
+    assert np.array_equal(h(outa), va) and np.array_equal(h(outb), vb)
+    assert h(fa).all() and h(fb).all()
+    check_layout(t, oracle.SINGLE)
