@@ -163,6 +163,63 @@ hc_err hc_info(hc_table table, hc_table_info* h_out);
 /* Copy the C slot words into caller memory d_dst (C uint64, device), on the stream. */
 hc_err hc_dump_slots(hc_table table, uint64_t* d_dst, void* stream);
 
+/* ---- batched launches over many tables ------------------------------------------
+ * Not in the paper (its bulk calls take one table each, Sec. IV-B3); built from the
+ * same per-element operations and the concurrency rules of Sec. IV-D.
+ *
+ * A batch is an ordered list of operations on single-value or counting tables.
+ * Operations on one table run in list order, except that consecutive operations of
+ * the same kind on a table run concurrently (Sec. IV-D: same-kind overlap is valid);
+ * operations on different tables are independent.  The list is split into phases
+ * (a table's next phase starts where its operation kind changes); each phase is one
+ * persistent kernel per distinct (kind, group size, window) in it, on one stream,
+ * in which wavefronts take chunks of any table's elements from a shared counter.
+ * Results are exactly those of the same calls made one by one in list order, except
+ * where concurrent same-kind writes of one phase touch the same key (then, as for one
+ * call with a repeated key, which write wins is unspecified). */
+
+enum { HC_OP_INSERT = 0, HC_OP_RETRIEVE = 1, HC_OP_ERASE = 2 };
+
+typedef struct {
+  hc_table table;            /* single-value or counting table (HC_E_KIND otherwise) */
+  uint32_t op;               /* HC_OP_* */
+  uint32_t group;            /* group size g; 0 = the table's default */
+  const uint32_t* d_keys;    /* n keys */
+  const uint32_t* d_values;  /* insert into a single-value table: n values; NULL otherwise */
+  uint32_t* d_values_out;    /* retrieve: n values (or counts); optional */
+  uint8_t* d_flags;          /* optional: n status codes (insert, erase) or found flags (retrieve) */
+  uint64_t n;
+} hc_batch_op;
+
+typedef struct hc_batch_s* hc_batch;
+
+/* Build a launch plan for `count` operations: validates them (HC_E_ARG / HC_E_KIND,
+ * nothing allocated on error), assigns phases and uploads the device descriptors
+ * (allocates device memory; synchronous).  The plan keeps the pointers it was given:
+ * the caller keeps those buffers alive and unchanged in size while it is launched.
+ * All tables must live on the current device. */
+hc_err hc_batch_create(hc_batch* out, const hc_batch_op* ops, uint32_t count);
+
+/* Enqueue every phase of the plan on `stream` (asynchronous; no allocation and no
+ * memset, so it may be captured into a graph).  Two launches of one plan must not
+ * run concurrently. */
+hc_err hc_batch_launch(hc_batch batch, void* stream);
+
+/* Number of phases and of kernel launches per hc_batch_launch. */
+hc_err hc_batch_info(hc_batch batch, uint32_t* h_phases, uint32_t* h_launches);
+
+/* Release the plan's device memory (synchronises the device). */
+hc_err hc_batch_destroy(hc_batch batch);
+
+/* create + launch + synchronise the stream + destroy. */
+hc_err hc_batch_run(const hc_batch_op* ops, uint32_t count, void* stream);
+
+/* Capture hc_batch_launch(batch) into an instantiated hipGraphExec (returned as
+ * void*); replay it with hc_graph_launch.  Replays must not overlap each other. */
+hc_err hc_batch_capture(hc_batch batch, void** h_graph_exec);
+hc_err hc_graph_launch(void* graph_exec, void* stream);
+hc_err hc_graph_destroy(void* graph_exec);
+
 /* Static text for an error code, and the calling thread's last error message. */
 const char* hc_error_string(hc_err err);
 const char* hc_last_error(void);

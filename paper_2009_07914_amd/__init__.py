@@ -26,6 +26,8 @@ LINEAR, QUADRATIC, DOUBLE = 0, 1, 2
 S_OK, S_DUPLICATE, S_FULL, S_INVALID_KEY, S_NOT_FOUND = 0, 1, 2, 3, 4
 E_OK, E_ARG, E_NOMEM, E_KIND, E_DEVICE = 0, 1, 2, 3, 4
 
+OP_INSERT, OP_RETRIEVE, OP_ERASE = 0, 1, 2
+
 SCHEMES = {"linear": LINEAR, "quadratic": QUADRATIC, "double": DOUBLE}
 KINDS = {"single": SINGLE_VALUE, "multi": MULTI_VALUE, "counting": COUNTING}
 
@@ -39,6 +41,12 @@ class HcTableInfo(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_uint32), ("scheme", ctypes.c_uint32), ("window", ctypes.c_uint32),
                 ("group", ctypes.c_uint32), ("windows", ctypes.c_uint64), ("capacity", ctypes.c_uint64),
                 ("seed", ctypes.c_uint64), ("d_slots", ctypes.c_void_p)]
+
+
+class HcBatchOp(ctypes.Structure):
+    _fields_ = [("table", ctypes.c_void_p), ("op", ctypes.c_uint32), ("group", ctypes.c_uint32),
+                ("d_keys", ctypes.c_void_p), ("d_values", ctypes.c_void_p), ("d_values_out", ctypes.c_void_p),
+                ("d_flags", ctypes.c_void_p), ("n", ctypes.c_uint64)]
 
 
 _p, _u32, _u64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
@@ -57,6 +65,14 @@ _SIGS = {
     "hc_capacity": ([_p, ctypes.POINTER(_u64)], ctypes.c_int),
     "hc_info": ([_p, ctypes.POINTER(HcTableInfo)], ctypes.c_int),
     "hc_dump_slots": ([_p, _p, _p], ctypes.c_int),
+    "hc_batch_create": ([ctypes.POINTER(_p), ctypes.POINTER(HcBatchOp), _u32], ctypes.c_int),
+    "hc_batch_launch": ([_p, _p], ctypes.c_int),
+    "hc_batch_info": ([_p, ctypes.POINTER(_u32), ctypes.POINTER(_u32)], ctypes.c_int),
+    "hc_batch_destroy": ([_p], ctypes.c_int),
+    "hc_batch_run": ([ctypes.POINTER(HcBatchOp), _u32, _p], ctypes.c_int),
+    "hc_batch_capture": ([_p, ctypes.POINTER(_p)], ctypes.c_int),
+    "hc_graph_launch": ([_p, _p], ctypes.c_int),
+    "hc_graph_destroy": ([_p], ctypes.c_int),
     "hc_error_string": ([ctypes.c_int], ctypes.c_char_p),
     "hc_last_error": ([], ctypes.c_char_p),
 }
@@ -192,6 +208,95 @@ def hc_info(h: int) -> HcTableInfo:
 def hc_dump_slots(h: int, dst, stream=None):
     _check(_lib.hc_dump_slots(h, _dptr(dst, torch.uint64, "dst", hc_capacity(h)), _stream(stream)),
            "hc_dump_slots")
+
+
+def _ops_array(ops):
+    arr = (HcBatchOp * max(1, len(ops)))()
+    for j, o in enumerate(ops):
+        arr[j] = o
+    return arr
+
+
+def hc_batch_op(table, op: int, keys, values=None, values_out=None, flags=None, group: int = 0) -> HcBatchOp:
+    """One batched operation; ``table`` is a handle or a ``Table``.  Tensors must outlive the plan."""
+    h = table.handle if isinstance(table, Table) else table
+    n = keys.numel()
+    return HcBatchOp(h, op, group, _u32t(keys, "keys"), _u32t(values, "values", n),
+                     _u32t(values_out, "values_out", n), _dptr(flags, torch.uint8, "flags", n), n)
+
+
+def hc_batch_create(ops) -> int:
+    h = ctypes.c_void_p()
+    _check(_lib.hc_batch_create(ctypes.byref(h), _ops_array(ops), len(ops)), "hc_batch_create")
+    return h.value
+
+
+def hc_batch_launch(batch: int, stream=None):
+    _check(_lib.hc_batch_launch(batch, _stream(stream)), "hc_batch_launch")
+
+
+def hc_batch_info(batch: int):
+    ph, la = ctypes.c_uint32(0), ctypes.c_uint32(0)
+    _check(_lib.hc_batch_info(batch, ctypes.byref(ph), ctypes.byref(la)), "hc_batch_info")
+    return int(ph.value), int(la.value)
+
+
+def hc_batch_destroy(batch: int):
+    _check(_lib.hc_batch_destroy(batch), "hc_batch_destroy")
+
+
+def hc_batch_run(ops, stream=None):
+    _check(_lib.hc_batch_run(_ops_array(ops), len(ops), _stream(stream)), "hc_batch_run")
+
+
+def hc_batch_capture(batch: int) -> int:
+    g = ctypes.c_void_p()
+    _check(_lib.hc_batch_capture(batch, ctypes.byref(g)), "hc_batch_capture")
+    return g.value
+
+
+def hc_graph_launch(graph: int, stream=None):
+    _check(_lib.hc_graph_launch(graph, _stream(stream)), "hc_graph_launch")
+
+
+def hc_graph_destroy(graph: int):
+    _check(_lib.hc_graph_destroy(graph), "hc_graph_destroy")
+
+
+class Batch:
+    """A launch plan over many tables; keeps the tensors of its operations alive."""
+
+    def __init__(self, ops_with_tensors):
+        # ops_with_tensors: list of (HcBatchOp, [tensors...])
+        self._keep = [t for _, ts in ops_with_tensors for t in ts]
+        self.handle = hc_batch_create([o for o, _ in ops_with_tensors])
+        self.phases, self.launches = hc_batch_info(self.handle)
+        self.graph = None
+
+    def launch(self, stream=None):
+        hc_batch_launch(self.handle, stream)
+
+    def capture(self):
+        if self.graph is None:
+            self.graph = hc_batch_capture(self.handle)
+        return self.graph
+
+    def replay(self, stream=None):
+        hc_graph_launch(self.capture(), stream)
+
+    def close(self):
+        if getattr(self, "graph", None):
+            hc_graph_destroy(self.graph)
+            self.graph = None
+        if getattr(self, "handle", None):
+            hc_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---- convenience wrapper ---------------------------------------------------------------

@@ -8,13 +8,30 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <algorithm>
 #include <new>
 #include <string>
 #include <unordered_map>
+#include <vector>
 
 #include "hc.h"
+#include "hc_batch.hpp"
 #include "hc_device.hpp"
 #include "hc_launch.hpp"
+
+struct hc_batch_s {
+  struct Launch {
+    uint32_t op, G, W;
+    uint32_t first_desc, ndesc;  // descriptors [first_desc, first_desc + ndesc)
+    uint64_t cs_offset;          // this launch's chunk starts in d_chunk_start
+    uint64_t total_chunks;
+  };
+  int device = 0;
+  uint32_t phases = 0;
+  std::vector<Launch> launches;  // in phase order
+  hc::BatchDesc* d_descs = nullptr;
+  uint64_t* d_chunk_start = nullptr;
+};
 
 struct hc_table_s {
   int device;
@@ -534,6 +551,200 @@ hc_err hc_dump_slots(hc_table t, uint64_t* d_dst, void* stream) {
   if ((r = set_device(t)) != HC_OK) return r;
   hipError_t e = hipMemcpyAsync(d_dst, t->slots, t->C * sizeof(uint64_t), hipMemcpyDeviceToDevice, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "hc_dump_slots");
+  return HC_OK;
+}
+
+hc_err hc_batch_create(hc_batch* out, const hc_batch_op* ops, uint32_t count) {
+  if (out == nullptr) return fail(HC_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (count > 0 && ops == nullptr) return fail(HC_E_ARG, "ops is NULL");
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(HC_E_DEVICE, "hipGetDevice failed");
+  // validate; phase per operation: a table's phase advances where its operation kind changes
+  struct Item {
+    uint32_t phase, op, G, W;
+    uint32_t index;
+  };
+  std::vector<Item> items;
+  std::unordered_map<const hc_table_s*, std::pair<uint32_t, uint32_t>> last;  // table -> (phase, op)
+  uint32_t phases = 0;
+  for (uint32_t j = 0; j < count; ++j) {
+    const hc_batch_op& o = ops[j];
+    if (o.table == nullptr) return fail(HC_E_ARG, "op %u: table is NULL", j);
+    const hc_table_s* t = o.table;
+    if (t->kind == HC_MULTI_VALUE) return fail(HC_E_KIND, "op %u: batched operations take single-value or counting tables", j);
+    if (t->device != dev) return fail(HC_E_ARG, "op %u: table lives on device %d, current device is %d", j, t->device, dev);
+    if (o.op > HC_OP_ERASE) return fail(HC_E_ARG, "op %u: unknown operation %u", j, o.op);
+    uint32_t g;
+    if (hc_err r = resolve_group(o.table, o.group, &g); r != HC_OK) return r;
+    if (o.n > 0 && o.d_keys == nullptr) return fail(HC_E_ARG, "op %u: keys is NULL", j);
+    uint32_t bop = o.op == HC_OP_RETRIEVE ? BATCH_RETRIEVE : o.op == HC_OP_ERASE ? BATCH_ERASE : BATCH_INSERT;
+    if (o.op == HC_OP_INSERT) {
+      if (t->kind == HC_COUNTING) {
+        if (o.d_values != nullptr) return fail(HC_E_ARG, "op %u: counting tables take no values", j);
+        bop = BATCH_COUNT;
+      } else if (o.n > 0 && o.d_values == nullptr) {
+        return fail(HC_E_ARG, "op %u: values is NULL", j);
+      }
+    }
+    uint32_t phase = 0;
+    auto it = last.find(t);
+    if (it != last.end()) phase = it->second.first + (it->second.second == o.op ? 0u : 1u);
+    last[t] = {phase, o.op};
+    if (phase + 1 > phases) phases = phase + 1;
+    if (o.n > 0) items.push_back({phase, bop, g, t->window, j});
+  }
+  // launches: (phase, kind, G, W) groups, list order kept inside each group
+  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
+    if (a.phase != b.phase) return a.phase < b.phase;
+    if (a.op != b.op) return a.op < b.op;
+    if (a.G != b.G) return a.G < b.G;
+    return a.W < b.W;
+  });
+  hc_batch_s* b = new (std::nothrow) hc_batch_s();
+  if (!b) return fail(HC_E_NOMEM, "host allocation failed");
+  b->device = dev;
+  b->phases = phases;
+  std::vector<BatchDesc> descs;
+  std::vector<uint64_t> cs;
+  for (size_t a = 0; a < items.size();) {
+    size_t e = a;
+    while (e < items.size() && items[e].phase == items[a].phase && items[e].op == items[a].op &&
+           items[e].G == items[a].G && items[e].W == items[a].W)
+      ++e;
+    hc_batch_s::Launch L;
+    L.op = items[a].op;
+    L.G = items[a].G;
+    L.W = items[a].W;
+    L.first_desc = (uint32_t)descs.size();
+    L.ndesc = (uint32_t)(e - a);
+    L.cs_offset = cs.size();
+    uint64_t chunks = 0;
+    for (size_t q = a; q < e; ++q) {
+      const hc_batch_op& o = ops[items[q].index];
+      BatchDesc d;
+      d.t = view_of(o.table);
+      d.keys = o.d_keys;
+      d.values = o.d_values;
+      d.values_out = o.d_values_out;
+      d.flags = o.d_flags;
+      d.n = o.n;
+      const uint64_t gpw = 64 / L.G;
+      d.chunk = (uint32_t)(o.n < 64 * gpw ? o.n : 64 * gpw);
+      d.op = L.op;
+      descs.push_back(d);
+      cs.push_back(chunks);
+      chunks += (o.n + d.chunk - 1) / d.chunk;
+    }
+    cs.push_back(chunks);
+    L.total_chunks = chunks;
+    b->launches.push_back(L);
+    a = e;
+  }
+  if (!descs.empty()) {
+    hipError_t e1 = hipMalloc((void**)&b->d_descs, descs.size() * sizeof(BatchDesc));
+    hipError_t e2 = e1 == hipSuccess ? hipMalloc((void**)&b->d_chunk_start, cs.size() * sizeof(uint64_t)) : e1;
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+      (void)hipGetLastError();
+      if (b->d_descs) (void)hipFree(b->d_descs);
+      delete b;
+      return fail(HC_E_NOMEM, "hipMalloc of batch descriptors failed");
+    }
+    hipError_t e = hipMemcpy(b->d_descs, descs.data(), descs.size() * sizeof(BatchDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->d_chunk_start, cs.data(), cs.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(b->d_descs);
+      (void)hipFree(b->d_chunk_start);
+      delete b;
+      return hip_fail(e, "batch descriptor upload");
+    }
+  }
+  *out = b;
+  return HC_OK;
+}
+
+hc_err hc_batch_launch(hc_batch b, void* stream) {
+  if (b == nullptr) return fail(HC_E_ARG, "batch is NULL");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(HC_E_DEVICE, "hipGetDevice failed");
+  if (cur != b->device) {
+    const hipError_t e = hipSetDevice(b->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  }
+  for (const auto& L : b->launches) {
+    hc_err r = launch_batch(L.op, L.G, L.W, b->d_descs + L.first_desc, b->d_chunk_start + L.cs_offset, L.ndesc,
+                            L.total_chunks, (hipStream_t)stream);
+    if (r != HC_OK) return r;
+  }
+  return HC_OK;
+}
+
+hc_err hc_batch_info(hc_batch b, uint32_t* h_phases, uint32_t* h_launches) {
+  if (b == nullptr) return fail(HC_E_ARG, "batch is NULL");
+  if (h_phases) *h_phases = b->phases;
+  if (h_launches) *h_launches = (uint32_t)b->launches.size();
+  return HC_OK;
+}
+
+hc_err hc_batch_destroy(hc_batch b) {
+  if (b == nullptr) return HC_OK;
+  if (b->d_descs) (void)hipFree(b->d_descs);
+  if (b->d_chunk_start) (void)hipFree(b->d_chunk_start);
+  delete b;
+  return HC_OK;
+}
+
+hc_err hc_batch_run(const hc_batch_op* ops, uint32_t count, void* stream) {
+  hc_batch b = nullptr;
+  hc_err r = hc_batch_create(&b, ops, count);
+  if (r != HC_OK) return r;
+  r = hc_batch_launch(b, stream);
+  if (r == HC_OK) {
+    const hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) r = hip_fail(e, "hc_batch_run: synchronise");
+  }
+  hc_batch_destroy(b);
+  return r;
+}
+
+hc_err hc_batch_capture(hc_batch b, void** h_graph_exec) {
+  if (b == nullptr || h_graph_exec == nullptr) return fail(HC_E_ARG, "batch or out is NULL");
+  *h_graph_exec = nullptr;
+  hipStream_t s = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "capture stream");
+  hipGraph_t graph = nullptr;
+  e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  hc_err r = HC_OK;
+  if (e == hipSuccess) {
+    r = hc_batch_launch(b, s);
+    const hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (r == HC_OK && e2 != hipSuccess) r = hip_fail(e2, "end capture");
+  } else {
+    r = hip_fail(e, "begin capture");
+  }
+  hipGraphExec_t exec = nullptr;
+  if (r == HC_OK) {
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) r = hip_fail(e, "graph instantiate");
+  }
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(s);
+  if (r == HC_OK) *h_graph_exec = (void*)exec;
+  return r;
+}
+
+hc_err hc_graph_launch(void* graph_exec, void* stream) {
+  if (graph_exec == nullptr) return fail(HC_E_ARG, "graph is NULL");
+  const hipError_t e = hipGraphLaunch((hipGraphExec_t)graph_exec, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+  return HC_OK;
+}
+
+hc_err hc_graph_destroy(void* graph_exec) {
+  if (graph_exec == nullptr) return HC_OK;
+  const hipError_t e = hipGraphExecDestroy((hipGraphExec_t)graph_exec);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphExecDestroy");
   return HC_OK;
 }
 

@@ -187,6 +187,43 @@ __device__ __forceinline__ void drive(uint64_t n, const WorkCtl& ctl, Op& op) {
   }
 }
 
+// The same loop over the elements [begin, end) of one chunk that this wavefront
+// already holds (batched launches): elements are handed to the groups in order,
+// and the call returns when every element of the chunk is done.
+template <int G, typename Op>
+__device__ __forceinline__ void drive_range(uint64_t begin, uint64_t end, Op& op) {
+  const GroupCtx<G>& g = op.ln.g;
+  uint64_t pos = begin;  // wavefront-uniform
+  auto reserve = [&](bool want_group) -> uint64_t {
+    const uint64_t want = __ballot(want_group && g.glane == 0);
+    if (want == 0) return ~0ull;
+    const uint32_t rank = (uint32_t)__popcll(want & ((1ull << g.lane) - 1ull));
+    const uint64_t idx = pos + rank;
+    pos += (uint32_t)__popcll(want);
+    return g.bcast64(idx, 0);
+  };
+  uint64_t i_next = reserve(true);
+  bool has_next = i_next < end;
+  if (has_next) op.load(i_next);
+  bool active = false;
+  for (;;) {
+    const bool start = !active && has_next;
+    if (start) {
+      op.begin(i_next);
+      active = true;
+    }
+    const uint64_t r = reserve(start);
+    if (start) {
+      i_next = r;
+      has_next = r < end;
+      if (has_next) op.load(r);
+    }
+    if (__ballot(active) == 0) break;
+    if (active && op.step()) active = false;
+  }
+  op.end();
+}
+
 // ------------------------------------------------------------------------------
 // Single-value and counting insert (Sec. IV-B2 steps 1-7; Sec. IV-B3).
 // ------------------------------------------------------------------------------

@@ -1,0 +1,166 @@
+"""GPU parity of batched launches over many tables against the CPU oracle.
+
+Every table's results are compared element by element with an oracle table that
+replays the same operations one by one in list order.
+"""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from tests.gpu_util import check_layout, d, h
+
+pytestmark = pytest.mark.gpu
+
+
+def _tables(hc, n_tables, log2_lo, log2_hi, seed, kind="single"):
+    spec = gen.batched_tables_spec(n_tables, log2_lo, log2_hi, 0.6, 0.95, 16, seed)
+    out = []
+    for j, sp in enumerate(spec):
+        scheme = ["linear", "double", "quadratic"][j % 3]
+        window = [8, 16, 32][(j // 3) % 3]
+        group = [1, 2, 4, 8, 16][j % 5]
+        t = hc.Table(kind, sp["capacity"], scheme=scheme, window=window, group=group, seed=sp["seed"])
+        w = gen.single_value_workload(t.capacity, sp["load"], sp["seed"])
+        out.append((t, w))
+    return out
+
+
+def test_many_tables_build_then_query(hc):
+    tabs = _tables(hc, 40, 10, 16, 123)
+    ins, ret, keep = [], [], []
+    outs = []
+    for j, (t, w) in enumerate(tabs):
+        k, v, q = d(w["keys"]), d(w["values"]), d(w["queries"])
+        st = torch.empty(k.numel(), dtype=torch.uint8, device="cuda")
+        vo = torch.empty(q.numel(), dtype=torch.uint32, device="cuda")
+        fo = torch.empty(q.numel(), dtype=torch.uint8, device="cuda")
+        ins.append((hc.hc_batch_op(t, hc.OP_INSERT, k, v, flags=st, group=[1, 2, 4, 8, 16][(j + 1) % 5]), [k, v, st]))
+        ret.append((hc.hc_batch_op(t, hc.OP_RETRIEVE, q, values_out=vo, flags=fo), [q, vo, fo]))
+        outs.append((st, vo, fo))
+    b = hc.Batch(ins + ret)
+    assert b.phases == 2
+    b.launch()
+    torch.cuda.synchronize()
+    for (t, w), (st, vo, fo) in zip(tabs, outs):
+        orc = oracle.OracleTable(oracle.SINGLE, t.capacity)
+        assert np.array_equal(h(st), orc.insert(w["keys"], w["values"]))
+        vv, ff = orc.retrieve(w["queries"])
+        assert np.array_equal(h(vo), vv) and np.array_equal(h(fo), ff)
+        assert t.size() == orc.size()
+    for t, _ in tabs[:6]:
+        check_layout(t, oracle.SINGLE)
+    b.close()
+
+
+def test_mixed_phases_follow_list_order(hc):
+    t1 = hc.Table("single", 1 << 14, scheme="double", window=16, group=4)
+    t2 = hc.Table("single", 1 << 13, scheme="linear", window=8, group=2)
+    o1, o2 = oracle.OracleTable(oracle.SINGLE, t1.capacity), oracle.OracleTable(oracle.SINGLE, t2.capacity)
+    k1, v1 = gen.keys(70, 1, 9000), gen.values(71, 9000)
+    k2, v2 = gen.keys(72, 1, 5000), gen.values(73, 5000)
+    er = k1[:3000]
+    k2b, v2b = gen.keys(72, 5001, 1000), gen.values(74, 1000)
+    q1 = np.concatenate([k1, gen.keys(70, 9001, 2000)])
+    q2 = np.concatenate([k2, k2b, gen.keys(72, 7000, 500)])
+    T = {}
+    def buf(name, a):
+        T[name] = d(a)
+        return T[name]
+    def out(name, n, dt):
+        T[name] = torch.zeros(n, dtype=dt, device="cuda")
+        return T[name]
+    ops = [
+        (hc.hc_batch_op(t1, hc.OP_INSERT, buf("k1", k1), buf("v1", v1), flags=out("s1", k1.size, torch.uint8)), []),
+        (hc.hc_batch_op(t2, hc.OP_INSERT, buf("k2", k2), buf("v2", v2)), []),
+        (hc.hc_batch_op(t2, hc.OP_RETRIEVE, buf("q2a", q2), values_out=out("r2a", q2.size, torch.uint32),
+                        flags=out("f2a", q2.size, torch.uint8)), []),
+        (hc.hc_batch_op(t1, hc.OP_ERASE, buf("e1", er), flags=out("se", er.size, torch.uint8), group=16), []),
+        (hc.hc_batch_op(t1, hc.OP_RETRIEVE, buf("q1", q1), values_out=out("r1", q1.size, torch.uint32),
+                        flags=out("f1", q1.size, torch.uint8), group=1), []),
+        (hc.hc_batch_op(t2, hc.OP_INSERT, buf("k2b", k2b), buf("v2b", v2b)), []),
+        (hc.hc_batch_op(t2, hc.OP_RETRIEVE, buf("q2b", q2), values_out=out("r2b", q2.size, torch.uint32),
+                        flags=out("f2b", q2.size, torch.uint8), group=8), []),
+    ]
+    b = hc.Batch([(o, list(T.values())) for o, _ in ops])
+    assert b.phases == 4
+    b.launch()
+    torch.cuda.synchronize()
+    # oracle replay in list order
+    assert np.array_equal(h(T["s1"]), o1.insert(k1, v1))
+    o2.insert(k2, v2)
+    vv, ff = o2.retrieve(q2)
+    assert np.array_equal(h(T["r2a"]), vv) and np.array_equal(h(T["f2a"]), ff)
+    assert np.array_equal(h(T["se"]), o1.erase(er))
+    vv, ff = o1.retrieve(q1)
+    assert np.array_equal(h(T["r1"]), vv) and np.array_equal(h(T["f1"]), ff)
+    o2.insert(k2b, v2b)
+    vv, ff = o2.retrieve(q2)
+    assert np.array_equal(h(T["r2b"]), vv) and np.array_equal(h(T["f2b"]), ff)
+    assert t1.size() == o1.size() and t2.size() == o2.size()
+    b.close()
+
+
+def test_graph_replays_match_eager(hc):
+    tabs = _tables(hc, 12, 10, 15, 7)
+    ops, outs = [], []
+    for t, w in tabs:
+        t.insert(d(w["keys"]), d(w["values"]))
+        q = d(w["queries"])
+        vo = torch.empty(q.numel(), dtype=torch.uint32, device="cuda")
+        fo = torch.empty(q.numel(), dtype=torch.uint8, device="cuda")
+        ops.append((hc.hc_batch_op(t, hc.OP_RETRIEVE, q, values_out=vo, flags=fo), [q, vo, fo]))
+        outs.append((vo, fo))
+    b = hc.Batch(ops)
+    b.launch()
+    torch.cuda.synchronize()
+    eager = [(h(vo).copy(), h(fo).copy()) for vo, fo in outs]
+    for rep in range(3):
+        for vo, fo in outs:  # scribble over the outputs between replays
+            vo.view(torch.int32).fill_(0xABCD)
+            fo.fill_(7)
+        torch.cuda.synchronize()
+        b.replay()
+        torch.cuda.synchronize()
+        for (vo, fo), (ve, fe) in zip(outs, eager):
+            assert np.array_equal(h(vo), ve) and np.array_equal(h(fo), fe), rep
+    b.close()
+
+
+def test_counting_tables_in_a_batch(hc):
+    tabs = []
+    ops = []
+    for j in range(6):
+        t = hc.Table("counting", 1 << (11 + j), scheme="double", window=16, group=[2, 4, 8][j % 3])
+        w = gen.multi_value_zipf_workload(3 << (10 + j), 1 << (9 + j), 1.1, 200 + j)
+        k = d(w["keys"])
+        ops.append((hc.hc_batch_op(t, hc.OP_INSERT, k), [k]))
+        tabs.append((t, w))
+    hc.Batch(ops).launch()
+    torch.cuda.synchronize()
+    for t, w in tabs:
+        o = oracle.OracleTable(oracle.COUNT, t.capacity)
+        o.insert(w["keys"])
+        v, f = t.retrieve(d(w["queries"]))
+        vv, ff = o.retrieve(w["queries"])
+        assert np.array_equal(h(v), vv) and np.array_equal(h(f), ff)
+        assert t.size() == o.size()
+
+
+def test_batch_argument_errors(hc):
+    mv = hc.Table("multi", 1024)
+    sv = hc.Table("single", 1024)
+    k = torch.zeros(4, dtype=torch.uint32, device="cuda")
+    with pytest.raises(hc.HcError) as e:
+        hc.hc_batch_create([hc.hc_batch_op(mv, hc.OP_RETRIEVE, k)])
+    assert e.value.code == hc.E_KIND
+    with pytest.raises(hc.HcError) as e:
+        hc.hc_batch_create([hc.HcBatchOp(sv.handle, hc.OP_INSERT, 0, None, None, None, None, 4)])
+    assert e.value.code == hc.E_ARG
+    with pytest.raises(hc.HcError) as e:
+        hc.hc_batch_create([hc.hc_batch_op(sv, 9, k)])
+    assert e.value.code == hc.E_ARG
+    b = hc.hc_batch_create([])  # an empty plan launches nothing
+    hc.hc_batch_launch(b)
+    hc.hc_batch_destroy(b)
