@@ -38,6 +38,13 @@ KERNEL_NAMES = {"insert": "k_insert_unique", "retrieve": "k_retrieve"}
 def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="single", choices=["single", "batched", "serving", "multi"],
+                    help="single: the 2^28-slot table (default); batched: 256 tables in one launch; "
+                         "serving: Poisson request stream on 16 resident tables")
+    ap.add_argument("--requests", type=int, default=1500)
+    ap.add_argument("--max-log2-request", type=int, default=24)
+    ap.add_argument("--zipf", action="store_true", help="serving: Zipf(1.1) keys instead of uniform")
+    ap.add_argument("--tables", type=int, default=256)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--log2-capacity", type=int, default=28)
@@ -100,6 +107,12 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (no sharding); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "serving":
+        return bench_serving(args)
+    if args.workload == "multi":
+        return bench_multi(args)
     import numpy as np
     import torch
 
@@ -211,6 +224,366 @@ def main():
     table.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(w, args.cpu_sample_log2)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(args):
+    """Many independent single-value tables (capacities log-uniform in [2^10, 2^24], loads uniform in
+    [0.6, 0.95]): build all, then query all 50/50, as (a) one launch per table and operation, with the
+    default layout and with the autotuned one, (b) one batched plan, and (c) the plan replayed as a graph."""
+    import numpy as np
+    import torch
+
+    lib = os.path.join(ROOT, "paper_2009_07914_amd", "libhc.so")
+    if not os.path.exists(lib):
+        import __graft_entry__
+        __graft_entry__.build()
+    import gen
+    import paper_2009_07914_amd as hc
+    from paper_2009_07914_amd import autotune
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    s = torch.cuda.current_stream()
+    spec = gen.batched_tables_spec(args.tables, 10, 24, 0.6, 0.95, 16, gen.SEED_BASE + 3)
+    sets = {}
+    for label in ("default", "tuned"):
+        tabs = []
+        for sp in spec:
+            cfg = dict(autotune.DEFAULT) if label == "default" else autotune.choose(sp["capacity"], sp["load"])
+            t = hc.Table("single", sp["capacity"], scheme=cfg["scheme"], window=cfg["window"],
+                         group=cfg["group_insert"], seed=sp["seed"], device=dev)
+            tabs.append((t, cfg))
+        sets[label] = tabs
+    data = []
+    for sp, (t, _) in zip(spec, sets["default"]):
+        w = gen.single_value_workload(sp["capacity"], sp["load"], sp["seed"])
+        k, v, q = (torch.from_numpy(w[x]).to(dev) for x in ("keys", "values", "queries"))
+        vo = torch.empty(q.numel(), dtype=torch.uint32, device=dev)
+        fo = torch.empty(q.numel(), dtype=torch.uint8, device=dev)
+        data.append({"n": w["n"], "k": k, "v": v, "q": q, "vo": vo, "fo": fo, "src": w["query_src"],
+                     "values": w["values"]})
+    n_ins = sum(x["n"] for x in data)
+    n_ret = sum(x["q"].numel() for x in data)
+    ops_total = n_ins + n_ret
+
+    def clear(tabs):
+        for t, _ in tabs:
+            hc.hc_clear(t.handle, s)
+
+    def per_table(tabs):
+        for (t, cfg), x in zip(tabs, data):
+            hc.hc_insert(t.handle, x["k"], x["v"], None, cfg["group_insert"], s)
+        for (t, cfg), x in zip(tabs, data):
+            hc.hc_retrieve(t.handle, x["q"], x["vo"], x["fo"], cfg["group_query"], s)
+
+    def plan(tabs):
+        ops = [(hc.hc_batch_op(t, hc.OP_INSERT, x["k"], x["v"], group=cfg["group_insert"]), [x["k"], x["v"]])
+               for (t, cfg), x in zip(tabs, data)]
+        ops += [(hc.hc_batch_op(t, hc.OP_RETRIEVE, x["q"], values_out=x["vo"], flags=x["fo"],
+                                group=cfg["group_query"]), [x["q"], x["vo"], x["fo"]])
+                for (t, cfg), x in zip(tabs, data)]
+        return hc.Batch(ops)
+
+    def timed(tabs, fn):
+        ms = []
+        for rep in range(args.warmup + args.steps):
+            clear(tabs)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            fn()
+            b.record(s)
+            torch.cuda.synchronize()
+            if rep >= args.warmup:
+                ms.append(a.elapsed_time(b))
+        return ms
+
+    def check(tabs):
+        for (t, _), x in zip(tabs, data):
+            f = x["fo"].cpu().numpy()
+            v = x["vo"].cpu().numpy()
+            present = x["src"] < x["n"]
+            assert np.array_equal(f.astype(bool), present), "found flags disagree"
+            assert np.array_equal(v[present], x["values"][x["src"][present].astype(np.int64)]), "values disagree"
+            assert t.size() == x["n"], "size disagrees"
+
+    res = {}
+    res["per_table_default"] = timed(sets["default"], lambda: per_table(sets["default"]))
+    check(sets["default"])
+    res["per_table_tuned"] = timed(sets["tuned"], lambda: per_table(sets["tuned"]))
+    check(sets["tuned"])
+    b_def = plan(sets["default"])
+    res["batched_default"] = timed(sets["default"], lambda: b_def.launch(s))
+    check(sets["default"])
+    b_tun = plan(sets["tuned"])
+    res["batched_tuned"] = timed(sets["tuned"], lambda: b_tun.launch(s))
+    check(sets["tuned"])
+    b_tun.capture()
+    res["graph_tuned"] = timed(sets["tuned"], lambda: b_tun.replay(s))
+    check(sets["tuned"])
+
+    def pct(xs, p):
+        xs = sorted(xs)
+        return xs[min(len(xs) - 1, int(round(p / 100 * (len(xs) - 1))))]
+
+    summary = {k: {"ms_mean": round(statistics.mean(v), 4), "ms_p50": round(pct(v, 50), 4),
+                   "ms_p99": round(pct(v, 99), 4), "gops": round(ops_total / (statistics.mean(v) * 1e-3) / 1e9, 4)}
+               for k, v in res.items()}
+    best = summary["graph_tuned"]
+    layouts = {}
+    for _, cfg in sets["tuned"]:
+        key = f"{cfg['scheme']}/W{cfg['window']}/g{cfg['group_insert']},{cfg['group_query']}"
+        layouts[key] = layouts.get(key, 0) + 1
+    out = {
+        "metric": "G ops/s, build then 50/50 query of many tables: batched graph launch vs one launch per table",
+        "value": best["gops"], "unit": "G ops/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": best["ms_mean"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"{args.tables} single-value tables, capacity log-uniform in [2^10, 2^24], "
+                               f"load uniform in [0.6, 0.95], uint32 keys; build all then query present+absent",
+                   "tables": args.tables, "slots": sum(t.capacity for t, _ in sets["tuned"]),
+                   "n_insert": n_ins, "n_retrieve": n_ret, "tuned_layouts": layouts,
+                   "plan_phases": b_tun.phases, "plan_launches": b_tun.launches},
+        "modes": summary,
+        "speedup_graph_vs_per_table_default": round(summary["per_table_default"]["ms_mean"] / best["ms_mean"], 3),
+    }
+    b_def.close()
+    b_tun.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_multi(args):
+    """Counting table: 2^26 keys drawn from Zipf(1.1) over 2^22 distinct k-mer-like keys into 2^27 slots,
+    then the count of every one of the 2^22 keys.  Multi-value table: 2^26 pairs with keys uniform on
+    1..2^26/r into 2^27 slots, then count / prefix sum / retrieve-all for the queries 1..2^26 (the
+    paper's multiplicity workload), r in {1, 4, 16, 64}."""
+    import numpy as np
+    import torch
+
+    lib = os.path.join(ROOT, "paper_2009_07914_amd", "libhc.so")
+    if not os.path.exists(lib):
+        import __graft_entry__
+        __graft_entry__.build()
+    import gen
+    import paper_2009_07914_amd as hc
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    s = torch.cuda.current_stream()
+    cap, n = 1 << 27, 1 << 26
+
+    def ev_time(fn, reps):
+        ms = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            pre = fn[0]
+            if pre:
+                pre()
+            a.record(s)
+            fn[1]()
+            b.record(s)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        return ms
+
+    reps = args.warmup + args.steps
+    res = {}
+    # ---- counting, Zipf(1.1)
+    w = gen.multi_value_zipf_workload(n, 1 << 22, 1.1, gen.SEED_BASE + 2)
+    keys = torch.from_numpy(w["keys"]).to(dev)
+    q = torch.from_numpy(w["queries"]).to(dev)
+    ct = hc.Table("counting", cap, scheme="double", window=16, group=4, device=dev)
+    cnt = torch.empty(q.numel(), dtype=torch.uint32, device=dev)
+    fnd = torch.empty(q.numel(), dtype=torch.uint8, device=dev)
+    ins = ev_time((ct.clear, lambda: hc.hc_insert(ct.handle, keys, None, None, args.group_insert, s)), reps)[args.warmup:]
+    ret = ev_time((None, lambda: hc.hc_retrieve(ct.handle, q, cnt, fnd, args.group_query, s)), reps)[args.warmup:]
+    u, c = np.unique(w["keys"], return_counts=True)
+    expect = np.zeros(q.numel(), dtype=np.uint32)
+    pos = np.searchsorted(u, w["queries"])
+    hit = (pos < u.size) & (u[np.minimum(pos, u.size - 1)] == w["queries"])
+    expect[hit] = c[pos[hit]]
+    assert np.array_equal(cnt.cpu().numpy(), expect), "counts disagree with numpy.unique"
+    assert ct.size() == u.size
+    res["counting_zipf"] = {"insert_ms": round(statistics.mean(ins), 4), "retrieve_ms": round(statistics.mean(ret), 4),
+                            "insert_gops": round(n / statistics.mean(ins) / 1e6, 4),
+                            "retrieve_gops": round(q.numel() / statistics.mean(ret) / 1e6, 4),
+                            "distinct_keys": int(u.size), "top_key_count": int(c.max())}
+    del keys, q, cnt, fnd, ct, w
+    # ---- multi-value, uniform multiplicity r
+    mv = hc.Table("multi", cap, scheme="double", window=16, group=4, device=dev)
+    for r in (1, 4, 16, 64):
+        w = gen.multi_value_uniform_r_workload(n, r, gen.SEED_BASE + 20 + r)
+        keys = torch.from_numpy(w["keys"]).to(dev)
+        vals = torch.from_numpy(w["values"]).to(dev)
+        q = torch.from_numpy(w["queries"]).to(dev)
+        offs = torch.empty(n + 1, dtype=torch.uint64, device=dev)
+        out = torch.empty(n, dtype=torch.uint32, device=dev)
+        ins = ev_time((mv.clear, lambda: hc.hc_insert(mv.handle, keys, vals, None, 8, s)), reps)[args.warmup:]
+        cnt_ms = ev_time((None, lambda: hc.hc_count_values(mv.handle, q, offs, None, False, 4, s)), reps)[args.warmup:]
+        wr_ms = ev_time((None, lambda: hc.hc_retrieve_all(mv.handle, q, offs, out, 4, s)), reps)[args.warmup:]
+        off = offs.cpu().numpy()
+        assert int(off[-1]) == n, "sum of counts must equal the number of stored pairs"
+        # sampled segments against lexsort grouping of the inputs
+        order = np.lexsort((w["values"], w["keys"]))
+        sk, sv = w["keys"][order], w["values"][order]
+        o = out.cpu().numpy()
+        for qi in np.linspace(0, n - 1, 2000).astype(np.int64):
+            key = w["queries"][qi]
+            lo, hi = np.searchsorted(sk, key, "left"), np.searchsorted(sk, key, "right")
+            seg = np.sort(o[off[qi]:off[qi + 1]])
+            assert np.array_equal(seg, sv[lo:hi]), "segment disagrees"
+        t_all = statistics.mean(cnt_ms) + statistics.mean(wr_ms)
+        res[f"multi_uniform_r{r}"] = {"insert_ms": round(statistics.mean(ins), 4),
+                                      "count_scan_ms": round(statistics.mean(cnt_ms), 4),
+                                      "write_ms": round(statistics.mean(wr_ms), 4),
+                                      "insert_gops": round(n / statistics.mean(ins) / 1e6, 4),
+                                      "retrieve_all_gops": round(n / t_all / 1e6, 4)}
+        del keys, vals, q, offs, out, w
+    out = {
+        "metric": "G ops/s of counting and multi-value tables (insert; count / prefix sum / retrieve-all)",
+        "value": res["multi_uniform_r16"]["retrieve_all_gops"], "unit": "G ops/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "2^27-slot tables, 2^26 uint32 pairs; counting: Zipf(1.1) over 2^22 keys; "
+                               "multi-value: keys uniform on 1..2^26/r, queries 1..2^26",
+                   "capacity": cap, "pairs": n},
+        "modes": res,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serving(args):
+    """16 resident single-value tables (2^20..2^28 slots) prefilled to half of a 0.9-load key universe;
+    requests of log-uniform size in [1, 2^max] (30% insert of fresh keys, 60% retrieve with 10% absent
+    keys, 10% erase of prefilled keys) arrive as a Poisson process.  The serial per-request path is
+    measured first; the server then takes the same stream at 50%, 80% and 95% of that path's rate."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    lib = os.path.join(ROOT, "paper_2009_07914_amd", "libhc.so")
+    if not os.path.exists(lib):
+        import __graft_entry__
+        __graft_entry__.build()
+    import gen
+    import paper_2009_07914_amd as hc
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    caps = [1 << 20, 1 << 20, 1 << 21, 1 << 21, 1 << 22, 1 << 22, 1 << 23, 1 << 23,
+            1 << 24, 1 << 24, 1 << 25, 1 << 25, 1 << 26, 1 << 26, 1 << 27, 1 << 28]
+    seed = gen.SEED_BASE + 4
+    uni = [gen.keys(gen.derive_seed(seed, 10 + j), 1, int(0.9 * c)) for j, c in enumerate(caps)]
+    pre = [u.size // 2 for u in uni]
+    rng = np.random.default_rng(seed & 0xFFFFFFFF)
+    zipf_pmf = None
+    reqs = []
+    nxt_ins, nxt_er = list(pre), [0] * len(caps)
+    for r in range(args.requests):
+        t = int(rng.integers(len(caps)))
+        n = max(1, int(2.0 ** (args.max_log2_request * rng.random())))
+        kind = rng.choice(3, p=[0.3, 0.6, 0.1])
+        if kind == 0 and uni[t].size - nxt_ins[t] >= n:
+            keys = uni[t][nxt_ins[t]:nxt_ins[t] + n]
+            nxt_ins[t] += n
+            reqs.append((t, hc.OP_INSERT, keys, gen.values(gen.derive_seed(seed, 100000 + r), n)))
+            continue
+        if kind == 2 and pre[t] - nxt_er[t] >= n:
+            keys = uni[t][nxt_er[t]:nxt_er[t] + n]
+            nxt_er[t] += n
+            reqs.append((t, hc.OP_ERASE, keys, None))
+            continue
+        if args.zipf:
+            ranks = gen.zipf_ranks(gen.derive_seed(seed, 200000 + r), uni[t].size, 1.1, n)
+            keys = uni[t][ranks.astype(np.int64) - 1]
+        else:
+            keys = uni[t][rng.integers(0, uni[t].size, n)]
+        m = n // 10
+        if m:
+            keys[:m] = gen.keys(gen.derive_seed(seed, 300000 + r), 1, m)  # absent keys (another key family)
+        reqs.append((t, hc.OP_RETRIEVE, keys, None))
+    total_ops = sum(k.size for _, _, k, _ in reqs)
+
+    def pinned(a):
+        x = torch.empty(a.size, dtype=torch.uint32, pin_memory=True)
+        x.numpy()[:] = a
+        return x
+
+    host = []
+    for t, op, keys, vals in reqs:
+        k = pinned(keys)
+        v = pinned(vals) if vals is not None else None
+        vo = torch.empty(keys.size, dtype=torch.uint32, pin_memory=True) if op == hc.OP_RETRIEVE else None
+        fl = torch.empty(keys.size, dtype=torch.uint8, pin_memory=True)
+        host.append((t, op, k, v, vo, fl))
+
+    tables = [hc.Table("single", c, scheme="double", window=16, group=4, seed=gen.derive_seed(seed, 50 + j), device=dev)
+              for j, c in enumerate(caps)]
+    pre_d = [(torch.from_numpy(u[:p]).to(dev), torch.from_numpy(gen.values(gen.derive_seed(seed, 60 + j), p)).to(dev))
+             for j, (u, p) in enumerate(zip(uni, pre))]
+
+    def reset():
+        for t, (k, v) in zip(tables, pre_d):
+            t.clear()
+            t.insert(k, v)
+        torch.cuda.synchronize()
+
+    def run(serial, rate):
+        """Submit the stream at Poisson times of `rate` requests/s (0: all at once)."""
+        reset()
+        srv = hc.Server(staging_bytes=4 << 30, serial=serial)
+        gaps = rng.exponential(1.0 / rate, len(host)) if rate > 0 else np.zeros(len(host))
+        arrivals = np.cumsum(gaps)
+        tickets = []
+        t0 = time.perf_counter()
+        for (t, op, k, v, vo, fl), at in zip(host, arrivals):
+            while time.perf_counter() - t0 < at:
+                pass
+            tickets.append(srv.submit(tables[t], op, k, v, vo, fl))
+        srv.drain()
+        wall = time.perf_counter() - t0
+        lat = np.array([srv.query(tk)[1] for tk in tickets]) / 1000.0
+        st = srv.stats()
+        srv.close()
+        outs = [(None if vo is None else vo.numpy().copy(), fl.numpy().copy()) for _, _, _, _, vo, fl in host]
+        return {"ops_per_s": total_ops / wall, "wall_s": wall, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+                "launch_groups": st["launch_groups"], "offered_rate": rate}, outs
+
+    for _ in range(max(0, args.warmup)):
+        run(False, 0)
+    base, base_out = run(True, 0)  # serial path, saturated: its sustainable request rate
+    base_rate = len(host) / base["wall_s"]
+    res = {"serial_saturated": base}
+    for frac in (0.5, 0.8, 0.95):
+        r_serial, _ = run(True, frac * base_rate)
+        r_server, out = run(False, frac * base_rate)
+        res[f"serial_at_{frac}"] = r_serial
+        res[f"server_at_{frac}"] = r_server
+        for (vm, fm), (vb, fb) in zip(out, base_out):  # same results alone and in the mix
+            assert np.array_equal(fm, fb), "flags differ between the serial path and the server"
+            if vm is not None:
+                assert np.array_equal(vm, vb), "values differ between the serial path and the server"
+    sat, _ = run(False, 0)
+    res["server_saturated"] = sat
+
+    def fmt(d):
+        return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+
+    out = {
+        "metric": "sustained G ops/s and p50/p99 request latency of the serving loop vs the per-request path",
+        "value": round(sat["ops_per_s"] / 1e9, 4), "unit": "G ops/s", "n_gpus": 1, "steps": 1,
+        "warmup": args.warmup, "ms_per_step": round(sat["wall_s"] * 1000, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "16 resident single-value tables (2^20..2^28 slots), prefilled to 45% of capacity; "
+                               f"{len(host)} requests of log-uniform size in [1, 2^{args.max_log2_request}], "
+                               "30% insert / 60% retrieve (10% absent keys) / 10% erase, "
+                               + ("Zipf(1.1)" if args.zipf else "uniform") + " retrieve keys; Poisson arrivals",
+                   "requests": len(host), "ops": total_ops, "host_buffers": "pinned"},
+        "modes": {k: fmt(v) for k, v in res.items()},
+        "serial_rate_req_per_s": round(base_rate, 2),
+    }
     print(json.dumps(out), flush=True)
 
 

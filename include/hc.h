@@ -220,6 +220,69 @@ hc_err hc_batch_capture(hc_batch batch, void** h_graph_exec);
 hc_err hc_graph_launch(void* graph_exec, void* stream);
 hc_err hc_graph_destroy(void* graph_exec);
 
+/* ---- serving loop -----------------------------------------------------------------
+ * Not in the paper.  A server owns a worker thread that admits requests (host-side
+ * key/value buffers on resident single-value or counting tables) in arrival order
+ * while its device staging ring has room, coalesces everything admitted at once into
+ * one batched launch group (whose phases keep every table's operations in arrival
+ * order), overlaps the input/output copies of a group with the kernels of its
+ * neighbours on rotating streams, and orders the kernels of consecutive groups, so
+ * every request's results equal those of running the requests one by one in
+ * arrival order -- except where requests admitted together write the same key of one
+ * table with the same kind of operation (then which write wins is unspecified).
+ * Host buffers should be pinned (hipHostMalloc) for asynchronous copies; they must
+ * stay valid until the request completes. */
+
+typedef struct hc_server_s* hc_server;
+
+typedef struct {
+  uint64_t staging_bytes;       /* device staging ring = admission budget (>= 1 MiB) */
+  uint64_t max_group_ops;       /* most elements coalesced into one launch group; 0 = no limit */
+  uint32_t max_group_requests;  /* most requests per launch group; 0 = 1024 */
+  uint32_t streams;             /* streams rotated over launch groups; 0 = 3 */
+  uint32_t serial;              /* 1: one request at a time, each waiting for the previous one */
+  uint32_t reserved;
+} hc_server_params;
+
+typedef struct {
+  hc_table table;
+  uint32_t op;                  /* HC_OP_* */
+  uint32_t group;               /* group size; 0 = the table's default */
+  const uint32_t* h_keys;       /* n keys */
+  const uint32_t* h_values;     /* insert into a single-value table: n values; NULL otherwise */
+  uint32_t* h_values_out;       /* retrieve: n values (counts); optional */
+  uint8_t* h_flags;             /* optional: status (insert, erase) or found (retrieve) */
+  uint64_t n;
+} hc_request;
+
+typedef struct {
+  uint64_t submitted, completed, launch_groups, ops_completed, staging_in_use;
+} hc_server_counts;
+
+/* Defaults: 1 GiB staging, no element limit, 1024 requests per group, 3 streams. */
+void hc_default_server_params(hc_server_params* params);
+
+/* Create a server on the current device (allocates its staging ring, streams and a
+ * worker thread).  params may be NULL. */
+hc_err hc_server_create(hc_server* out, const hc_server_params* params);
+
+/* Queue a request; returns at once with a ticket.  HC_E_ARG / HC_E_KIND for invalid
+ * requests, HC_E_ARG if the request can never fit the staging ring. */
+hc_err hc_server_submit(hc_server server, const hc_request* req, uint64_t* h_ticket);
+
+/* Non-blocking status of a ticket; latency = completion - submission (microseconds),
+ * -1 while pending. */
+hc_err hc_server_query(hc_server server, uint64_t ticket, int* h_done, double* h_latency_us);
+
+/* Block until the ticket completes / until every submitted request completes. */
+hc_err hc_server_wait(hc_server server, uint64_t ticket);
+hc_err hc_server_drain(hc_server server);
+
+hc_err hc_server_stats(hc_server server, hc_server_counts* h_out);
+
+/* Finish the queued work, stop the worker and release everything. */
+hc_err hc_server_destroy(hc_server server);
+
 /* Static text for an error code, and the calling thread's last error message. */
 const char* hc_error_string(hc_err err);
 const char* hc_last_error(void);

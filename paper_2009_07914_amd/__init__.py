@@ -49,6 +49,23 @@ class HcBatchOp(ctypes.Structure):
                 ("d_flags", ctypes.c_void_p), ("n", ctypes.c_uint64)]
 
 
+class HcServerParams(ctypes.Structure):
+    _fields_ = [("staging_bytes", ctypes.c_uint64), ("max_group_ops", ctypes.c_uint64),
+                ("max_group_requests", ctypes.c_uint32), ("streams", ctypes.c_uint32),
+                ("serial", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class HcRequest(ctypes.Structure):
+    _fields_ = [("table", ctypes.c_void_p), ("op", ctypes.c_uint32), ("group", ctypes.c_uint32),
+                ("h_keys", ctypes.c_void_p), ("h_values", ctypes.c_void_p), ("h_values_out", ctypes.c_void_p),
+                ("h_flags", ctypes.c_void_p), ("n", ctypes.c_uint64)]
+
+
+class HcServerCounts(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("launch_groups", ctypes.c_uint64),
+                ("ops_completed", ctypes.c_uint64), ("staging_in_use", ctypes.c_uint64)]
+
+
 _p, _u32, _u64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
 _SIGS = {
     "hc_default_params": ([ctypes.POINTER(HcParams)], None),
@@ -73,6 +90,14 @@ _SIGS = {
     "hc_batch_capture": ([_p, ctypes.POINTER(_p)], ctypes.c_int),
     "hc_graph_launch": ([_p, _p], ctypes.c_int),
     "hc_graph_destroy": ([_p], ctypes.c_int),
+    "hc_default_server_params": ([ctypes.POINTER(HcServerParams)], None),
+    "hc_server_create": ([ctypes.POINTER(_p), ctypes.POINTER(HcServerParams)], ctypes.c_int),
+    "hc_server_submit": ([_p, ctypes.POINTER(HcRequest), ctypes.POINTER(_u64)], ctypes.c_int),
+    "hc_server_query": ([_p, _u64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "hc_server_wait": ([_p, _u64], ctypes.c_int),
+    "hc_server_drain": ([_p], ctypes.c_int),
+    "hc_server_stats": ([_p, ctypes.POINTER(HcServerCounts)], ctypes.c_int),
+    "hc_server_destroy": ([_p], ctypes.c_int),
     "hc_error_string": ([ctypes.c_int], ctypes.c_char_p),
     "hc_last_error": ([], ctypes.c_char_p),
 }
@@ -291,6 +316,111 @@ class Batch:
         if getattr(self, "handle", None):
             hc_batch_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _hptr(t, dtype, what, n=None):
+    """Host pointer of a contiguous CPU tensor (pinned for asynchronous copies) or None."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.is_cuda:
+        raise TypeError(f"{what} must be a CPU tensor")
+    if t.dtype == torch.int32 and dtype == torch.uint32:
+        t = t.view(torch.uint32)
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{what} must be a contiguous {dtype} tensor")
+    if n is not None and t.numel() < n:
+        raise ValueError(f"{what} has {t.numel()} elements, needs {n}")
+    return t.data_ptr()
+
+
+def hc_default_server_params() -> HcServerParams:
+    p = HcServerParams()
+    _lib.hc_default_server_params(ctypes.byref(p))
+    return p
+
+
+def hc_server_create(params: HcServerParams | None = None) -> int:
+    h = ctypes.c_void_p()
+    _check(_lib.hc_server_create(ctypes.byref(h), ctypes.byref(params) if params else None), "hc_server_create")
+    return h.value
+
+
+def hc_request(table, op: int, keys, values=None, values_out=None, flags=None, group: int = 0) -> HcRequest:
+    h = table.handle if isinstance(table, Table) else table
+    n = keys.numel()
+    return HcRequest(h, op, group, _hptr(keys, torch.uint32, "keys"), _hptr(values, torch.uint32, "values", n),
+                     _hptr(values_out, torch.uint32, "values_out", n), _hptr(flags, torch.uint8, "flags", n), n)
+
+
+def hc_server_submit(server: int, req: HcRequest) -> int:
+    t = ctypes.c_uint64(0)
+    _check(_lib.hc_server_submit(server, ctypes.byref(req), ctypes.byref(t)), "hc_server_submit")
+    return int(t.value)
+
+
+def hc_server_query(server: int, ticket: int):
+    done, lat = ctypes.c_int(0), ctypes.c_double(0)
+    _check(_lib.hc_server_query(server, ticket, ctypes.byref(done), ctypes.byref(lat)), "hc_server_query")
+    return bool(done.value), float(lat.value)
+
+
+def hc_server_wait(server: int, ticket: int):
+    _check(_lib.hc_server_wait(server, ticket), "hc_server_wait")
+
+
+def hc_server_drain(server: int):
+    _check(_lib.hc_server_drain(server), "hc_server_drain")
+
+
+def hc_server_stats(server: int) -> dict:
+    c = HcServerCounts()
+    _check(_lib.hc_server_stats(server, ctypes.byref(c)), "hc_server_stats")
+    return {k: int(getattr(c, k)) for k, _ in HcServerCounts._fields_}
+
+
+def hc_server_destroy(server: int):
+    _check(_lib.hc_server_destroy(server), "hc_server_destroy")
+
+
+class Server:
+    """Continuous-batching server; keeps each request's host tensors alive until it completes."""
+
+    def __init__(self, staging_bytes=1 << 30, max_group_ops=0, max_group_requests=1024, streams=3, serial=False):
+        p = hc_default_server_params()
+        p.staging_bytes, p.max_group_ops = staging_bytes, max_group_ops
+        p.max_group_requests, p.streams, p.serial = max_group_requests, streams, int(serial)
+        self.handle = hc_server_create(p)
+        self._keep = {}
+
+    def submit(self, table, op, keys, values=None, values_out=None, flags=None, group=0) -> int:
+        t = hc_server_submit(self.handle, hc_request(table, op, keys, values, values_out, flags, group))
+        self._keep[t] = (keys, values, values_out, flags)
+        return t
+
+    def query(self, ticket):
+        return hc_server_query(self.handle, ticket)
+
+    def wait(self, ticket):
+        hc_server_wait(self.handle, ticket)
+
+    def drain(self):
+        hc_server_drain(self.handle)
+        self._keep.clear()
+
+    def stats(self):
+        return hc_server_stats(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            hc_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
 
     def __del__(self):
         try:

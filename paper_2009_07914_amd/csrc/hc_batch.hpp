@@ -1,6 +1,8 @@
 // Device descriptor of one operation of a batched launch.
 #pragma once
 
+#include <vector>
+
 #include "hc.h"
 #include "hc_device.hpp"
 
@@ -24,5 +26,27 @@ struct BatchDesc {
 // kind `op`, group size G and window W) on `stream`.
 hc_err launch_batch(uint32_t op, uint32_t G, uint32_t W, const BatchDesc* d_descs, const uint64_t* d_chunk_start,
                     uint32_t ndesc, uint64_t total_chunks, hipStream_t stream);
+
+struct PlanLaunch {
+  uint32_t op, G, W;
+  uint32_t first_desc, ndesc;  // descriptors [first_desc, first_desc + ndesc)
+  uint64_t cs_offset;          // this launch's chunk starts
+  uint64_t total_chunks;
+};
+
+// Host side of a plan: descriptors, per-launch chunk starts, launches in phase order.
+struct PlanHost {
+  std::vector<BatchDesc> descs;
+  std::vector<uint64_t> cs;
+  std::vector<PlanLaunch> launches;
+  uint32_t phases = 0;
+};
+
+// Validate and lay out `ops` (tables on device `dev`); no device work.
+hc_err build_plan(const hc_batch_op* ops, uint32_t count, int dev, PlanHost* out);
+
+// Enqueue a plan whose descriptors and chunk starts are in device memory.
+hc_err launch_plan(const std::vector<PlanLaunch>& launches, const BatchDesc* d_descs, const uint64_t* d_cs,
+                   hipStream_t stream);
 
 }  // namespace hc

@@ -20,15 +20,9 @@
 #include "hc_launch.hpp"
 
 struct hc_batch_s {
-  struct Launch {
-    uint32_t op, G, W;
-    uint32_t first_desc, ndesc;  // descriptors [first_desc, first_desc + ndesc)
-    uint64_t cs_offset;          // this launch's chunk starts in d_chunk_start
-    uint64_t total_chunks;
-  };
   int device = 0;
   uint32_t phases = 0;
-  std::vector<Launch> launches;  // in phase order
+  std::vector<hc::PlanLaunch> launches;  // in phase order
   hc::BatchDesc* d_descs = nullptr;
   uint64_t* d_chunk_start = nullptr;
 };
@@ -278,6 +272,116 @@ static hc_err set_device(hc_table t) {
   if (cur != t->device) {
     const hipError_t e = hipSetDevice(t->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  }
+  return HC_OK;
+}
+
+}  // namespace hc
+
+namespace hc {
+
+// Validate `ops`, assign phases (a table's phase advances where its operation kind
+// changes) and lay out the per-launch descriptor groups on the host.
+hc_err build_plan(const hc_batch_op* ops, uint32_t count, int dev, PlanHost* out) {
+  out->descs.clear();
+  out->cs.clear();
+  out->launches.clear();
+  out->phases = 0;
+  if (count > 0 && ops == nullptr) return fail(HC_E_ARG, "ops is NULL");
+  struct Item {
+    uint32_t phase, op, G, W;
+    uint32_t index;
+  };
+  std::vector<Item> items;
+  items.reserve(count);
+  std::unordered_map<const hc_table_s*, std::pair<uint32_t, uint32_t>> last;  // table -> (phase, op)
+  uint32_t phases = 0;
+  for (uint32_t j = 0; j < count; ++j) {
+    const hc_batch_op& o = ops[j];
+    if (o.table == nullptr) return fail(HC_E_ARG, "op %u: table is NULL", j);
+    const hc_table_s* t = o.table;
+    if (t->kind == HC_MULTI_VALUE)
+      return fail(HC_E_KIND, "op %u: batched operations take single-value or counting tables", j);
+    if (t->device != dev) return fail(HC_E_ARG, "op %u: table lives on device %d, current device is %d", j, t->device, dev);
+    if (o.op > HC_OP_ERASE) return fail(HC_E_ARG, "op %u: unknown operation %u", j, o.op);
+    uint32_t g;
+    if (hc_err r = resolve_group(o.table, o.group, &g); r != HC_OK) return r;
+    if (o.n > 0 && o.d_keys == nullptr) return fail(HC_E_ARG, "op %u: keys is NULL", j);
+    uint32_t bop = o.op == HC_OP_RETRIEVE ? BATCH_RETRIEVE : o.op == HC_OP_ERASE ? BATCH_ERASE : BATCH_INSERT;
+    if (o.op == HC_OP_INSERT) {
+      if (t->kind == HC_COUNTING) {
+        if (o.d_values != nullptr) return fail(HC_E_ARG, "op %u: counting tables take no values", j);
+        bop = BATCH_COUNT;
+      } else if (o.n > 0 && o.d_values == nullptr) {
+        return fail(HC_E_ARG, "op %u: values is NULL", j);
+      }
+    }
+    uint32_t phase = 0;
+    auto it = last.find(t);
+    if (it != last.end()) phase = it->second.first + (it->second.second == o.op ? 0u : 1u);
+    last[t] = {phase, o.op};
+    if (phase + 1 > phases) phases = phase + 1;
+    if (o.n > 0) items.push_back({phase, bop, g, t->window, j});
+  }
+  // launches: (phase, kind, G, W) groups, list order kept inside each group
+  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
+    if (a.phase != b.phase) return a.phase < b.phase;
+    if (a.op != b.op) return a.op < b.op;
+    if (a.G != b.G) return a.G < b.G;
+    return a.W < b.W;
+  });
+  out->phases = phases;
+  for (size_t a = 0; a < items.size();) {
+    size_t e = a;
+    while (e < items.size() && items[e].phase == items[a].phase && items[e].op == items[a].op &&
+           items[e].G == items[a].G && items[e].W == items[a].W)
+      ++e;
+    PlanLaunch L;
+    L.op = items[a].op;
+    L.G = items[a].G;
+    L.W = items[a].W;
+    L.first_desc = (uint32_t)out->descs.size();
+    L.ndesc = (uint32_t)(e - a);
+    L.cs_offset = out->cs.size();
+    // chunk size: about two chunks per resident wavefront over the whole launch, between
+    // one element per group and 64 elements per group of a wavefront
+    uint64_t total = 0;
+    for (size_t q = a; q < e; ++q) total += ops[items[q].index].n;
+    const uint64_t gpw = 64 / L.G;
+    const uint64_t waves = (uint64_t)device_cu_count() * 32;
+    uint64_t ch = (total + 2 * waves - 1) / (2 * waves);
+    if (ch < gpw) ch = gpw;
+    if (ch > 64 * gpw) ch = 64 * gpw;
+    uint64_t chunks = 0;
+    for (size_t q = a; q < e; ++q) {
+      const hc_batch_op& o = ops[items[q].index];
+      BatchDesc d;
+      d.t = view_of(o.table);
+      d.keys = o.d_keys;
+      d.values = o.d_values;
+      d.values_out = o.d_values_out;
+      d.flags = o.d_flags;
+      d.n = o.n;
+      d.chunk = (uint32_t)(o.n < ch ? o.n : ch);
+      d.op = L.op;
+      out->descs.push_back(d);
+      out->cs.push_back(chunks);
+      chunks += (o.n + d.chunk - 1) / d.chunk;
+    }
+    out->cs.push_back(chunks);
+    L.total_chunks = chunks;
+    out->launches.push_back(L);
+    a = e;
+  }
+  return HC_OK;
+}
+
+hc_err launch_plan(const std::vector<PlanLaunch>& launches, const BatchDesc* d_descs, const uint64_t* d_cs,
+                   hipStream_t stream) {
+  for (const auto& L : launches) {
+    hc_err r = launch_batch(L.op, L.G, L.W, d_descs + L.first_desc, d_cs + L.cs_offset, L.ndesc, L.total_chunks,
+                            stream);
+    if (r != HC_OK) return r;
   }
   return HC_OK;
 }
@@ -554,104 +658,31 @@ hc_err hc_dump_slots(hc_table t, uint64_t* d_dst, void* stream) {
   return HC_OK;
 }
 
+
 hc_err hc_batch_create(hc_batch* out, const hc_batch_op* ops, uint32_t count) {
   if (out == nullptr) return fail(HC_E_ARG, "out is NULL");
   *out = nullptr;
-  if (count > 0 && ops == nullptr) return fail(HC_E_ARG, "ops is NULL");
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(HC_E_DEVICE, "hipGetDevice failed");
-  // validate; phase per operation: a table's phase advances where its operation kind changes
-  struct Item {
-    uint32_t phase, op, G, W;
-    uint32_t index;
-  };
-  std::vector<Item> items;
-  std::unordered_map<const hc_table_s*, std::pair<uint32_t, uint32_t>> last;  // table -> (phase, op)
-  uint32_t phases = 0;
-  for (uint32_t j = 0; j < count; ++j) {
-    const hc_batch_op& o = ops[j];
-    if (o.table == nullptr) return fail(HC_E_ARG, "op %u: table is NULL", j);
-    const hc_table_s* t = o.table;
-    if (t->kind == HC_MULTI_VALUE) return fail(HC_E_KIND, "op %u: batched operations take single-value or counting tables", j);
-    if (t->device != dev) return fail(HC_E_ARG, "op %u: table lives on device %d, current device is %d", j, t->device, dev);
-    if (o.op > HC_OP_ERASE) return fail(HC_E_ARG, "op %u: unknown operation %u", j, o.op);
-    uint32_t g;
-    if (hc_err r = resolve_group(o.table, o.group, &g); r != HC_OK) return r;
-    if (o.n > 0 && o.d_keys == nullptr) return fail(HC_E_ARG, "op %u: keys is NULL", j);
-    uint32_t bop = o.op == HC_OP_RETRIEVE ? BATCH_RETRIEVE : o.op == HC_OP_ERASE ? BATCH_ERASE : BATCH_INSERT;
-    if (o.op == HC_OP_INSERT) {
-      if (t->kind == HC_COUNTING) {
-        if (o.d_values != nullptr) return fail(HC_E_ARG, "op %u: counting tables take no values", j);
-        bop = BATCH_COUNT;
-      } else if (o.n > 0 && o.d_values == nullptr) {
-        return fail(HC_E_ARG, "op %u: values is NULL", j);
-      }
-    }
-    uint32_t phase = 0;
-    auto it = last.find(t);
-    if (it != last.end()) phase = it->second.first + (it->second.second == o.op ? 0u : 1u);
-    last[t] = {phase, o.op};
-    if (phase + 1 > phases) phases = phase + 1;
-    if (o.n > 0) items.push_back({phase, bop, g, t->window, j});
-  }
-  // launches: (phase, kind, G, W) groups, list order kept inside each group
-  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
-    if (a.phase != b.phase) return a.phase < b.phase;
-    if (a.op != b.op) return a.op < b.op;
-    if (a.G != b.G) return a.G < b.G;
-    return a.W < b.W;
-  });
+  PlanHost plan;
+  if (hc_err r = build_plan(ops, count, dev, &plan); r != HC_OK) return r;
   hc_batch_s* b = new (std::nothrow) hc_batch_s();
   if (!b) return fail(HC_E_NOMEM, "host allocation failed");
   b->device = dev;
-  b->phases = phases;
-  std::vector<BatchDesc> descs;
-  std::vector<uint64_t> cs;
-  for (size_t a = 0; a < items.size();) {
-    size_t e = a;
-    while (e < items.size() && items[e].phase == items[a].phase && items[e].op == items[a].op &&
-           items[e].G == items[a].G && items[e].W == items[a].W)
-      ++e;
-    hc_batch_s::Launch L;
-    L.op = items[a].op;
-    L.G = items[a].G;
-    L.W = items[a].W;
-    L.first_desc = (uint32_t)descs.size();
-    L.ndesc = (uint32_t)(e - a);
-    L.cs_offset = cs.size();
-    uint64_t chunks = 0;
-    for (size_t q = a; q < e; ++q) {
-      const hc_batch_op& o = ops[items[q].index];
-      BatchDesc d;
-      d.t = view_of(o.table);
-      d.keys = o.d_keys;
-      d.values = o.d_values;
-      d.values_out = o.d_values_out;
-      d.flags = o.d_flags;
-      d.n = o.n;
-      const uint64_t gpw = 64 / L.G;
-      d.chunk = (uint32_t)(o.n < 64 * gpw ? o.n : 64 * gpw);
-      d.op = L.op;
-      descs.push_back(d);
-      cs.push_back(chunks);
-      chunks += (o.n + d.chunk - 1) / d.chunk;
-    }
-    cs.push_back(chunks);
-    L.total_chunks = chunks;
-    b->launches.push_back(L);
-    a = e;
-  }
-  if (!descs.empty()) {
-    hipError_t e1 = hipMalloc((void**)&b->d_descs, descs.size() * sizeof(BatchDesc));
-    hipError_t e2 = e1 == hipSuccess ? hipMalloc((void**)&b->d_chunk_start, cs.size() * sizeof(uint64_t)) : e1;
+  b->phases = plan.phases;
+  b->launches = plan.launches;
+  if (!plan.descs.empty()) {
+    hipError_t e1 = hipMalloc((void**)&b->d_descs, plan.descs.size() * sizeof(BatchDesc));
+    hipError_t e2 = e1 == hipSuccess ? hipMalloc((void**)&b->d_chunk_start, plan.cs.size() * sizeof(uint64_t)) : e1;
     if (e1 != hipSuccess || e2 != hipSuccess) {
       (void)hipGetLastError();
       if (b->d_descs) (void)hipFree(b->d_descs);
       delete b;
       return fail(HC_E_NOMEM, "hipMalloc of batch descriptors failed");
     }
-    hipError_t e = hipMemcpy(b->d_descs, descs.data(), descs.size() * sizeof(BatchDesc), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(b->d_chunk_start, cs.data(), cs.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
+    hipError_t e = hipMemcpy(b->d_descs, plan.descs.data(), plan.descs.size() * sizeof(BatchDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(b->d_chunk_start, plan.cs.data(), plan.cs.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
       (void)hipFree(b->d_descs);
       (void)hipFree(b->d_chunk_start);
@@ -671,12 +702,7 @@ hc_err hc_batch_launch(hc_batch b, void* stream) {
     const hipError_t e = hipSetDevice(b->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   }
-  for (const auto& L : b->launches) {
-    hc_err r = launch_batch(L.op, L.G, L.W, b->d_descs + L.first_desc, b->d_chunk_start + L.cs_offset, L.ndesc,
-                            L.total_chunks, (hipStream_t)stream);
-    if (r != HC_OK) return r;
-  }
-  return HC_OK;
+  return launch_plan(b->launches, b->d_descs, b->d_chunk_start, (hipStream_t)stream);
 }
 
 hc_err hc_batch_info(hc_batch b, uint32_t* h_phases, uint32_t* h_launches) {
