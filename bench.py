@@ -439,13 +439,44 @@ def bench_multi(args):
                                       "insert_gops": round(n / statistics.mean(ins) / 1e6, 4),
                                       "retrieve_all_gops": round(n / t_all / 1e6, 4)}
         del keys, vals, q, offs, out, w
+    # ---- multi-value, Zipf(1.1) keys: grouped insert, then every distinct key's values (long queries)
+    w = gen.multi_value_zipf_workload(n, 1 << 22, 1.1, gen.SEED_BASE + 3)
+    keys = torch.from_numpy(w["keys"]).to(dev)
+    vals = torch.from_numpy(w["values"]).to(dev)
+    q = torch.from_numpy(w["queries"]).to(dev)
+    nq = q.numel()
+    offs = torch.empty(nq + 1, dtype=torch.uint64, device=dev)
+    out = torch.empty(n, dtype=torch.uint32, device=dev)
+    ins = ev_time((mv.clear, lambda: hc.hc_insert_grouped(mv.handle, keys, vals, s)), reps)[args.warmup:]
+    cnt_ms = ev_time((None, lambda: hc.hc_count_values(mv.handle, q, offs, None, False, 4, s)), reps)[args.warmup:]
+    wr_ms = ev_time((None, lambda: hc.hc_retrieve_all(mv.handle, q, offs, out, 4, s)), reps)[args.warmup:]
+    off = offs.cpu().numpy()
+    assert int(off[-1]) == n, "sum of counts must equal the number of stored pairs"
+    order = np.lexsort((w["values"], w["keys"]))
+    sk, sv = w["keys"][order], w["values"][order]
+    o = out.cpu().numpy()
+    heavy = np.argsort(np.diff(off.astype(np.int64)))[-8:]  # the eight longest segments, plus a spread
+    for qi in np.concatenate([heavy, np.linspace(0, nq - 1, 2000).astype(np.int64)]):
+        key = w["queries"][qi]
+        lo, hi = np.searchsorted(sk, key, "left"), np.searchsorted(sk, key, "right")
+        seg = np.sort(o[off[qi]:off[qi + 1]])
+        assert np.array_equal(seg, sv[lo:hi]), "segment disagrees"
+    t_all = statistics.mean(cnt_ms) + statistics.mean(wr_ms)
+    res["multi_zipf_grouped"] = {"insert_ms": round(statistics.mean(ins), 4),
+                                 "count_scan_ms": round(statistics.mean(cnt_ms), 4),
+                                 "write_ms": round(statistics.mean(wr_ms), 4),
+                                 "insert_gops": round(n / statistics.mean(ins) / 1e6, 4),
+                                 "retrieve_all_gops": round(n / t_all / 1e6, 4),
+                                 "top_key_count": int(np.diff(off.astype(np.int64)).max())}
+    del keys, vals, q, offs, out, w
     out = {
         "metric": "G ops/s of counting and multi-value tables (insert; count / prefix sum / retrieve-all)",
         "value": res["multi_uniform_r16"]["retrieve_all_gops"], "unit": "G ops/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
         "config": {"workload": "2^27-slot tables, 2^26 uint32 pairs; counting: Zipf(1.1) over 2^22 keys; "
-                               "multi-value: keys uniform on 1..2^26/r, queries 1..2^26",
+                               "multi-value: keys uniform on 1..2^26/r, queries 1..2^26; "
+                               "skewed multi-value: Zipf(1.1) over 2^22 keys, grouped insert",
                    "capacity": cap, "pairs": n},
         "modes": res,
     }

@@ -137,6 +137,8 @@ hc_err hc_erase(hc_table table, const uint32_t* d_keys, uint64_t n, uint8_t* d_s
 /* Multi-value pass 1 (Sec. IV-B4): d_offsets (n+1 uint64) receives the exclusive prefix sum
  * of the per-query value counts, d_offsets[n] = total; d_counts (optional, n uint32) the
  * counts themselves; *h_total (optional) the total, which synchronises the stream.
+ * A query still open after 64 windows is finished by a block of 1024 threads (keys with
+ * very many values).  Uses the table's workspace (8 bytes per query).
  * Multi-value tables only (HC_E_KIND otherwise). */
 hc_err hc_count_values(hc_table table, const uint32_t* d_keys, uint64_t n, uint32_t* d_counts,
                        uint64_t* d_offsets, uint64_t* h_total, uint32_t group, void* stream);
@@ -147,6 +149,16 @@ hc_err hc_count_values(hc_table table, const uint32_t* d_keys, uint64_t n, uint3
  * writes never leave a segment.  Multi-value tables only. */
 hc_err hc_retrieve_all(hc_table table, const uint32_t* d_keys, uint64_t n, const uint64_t* d_offsets,
                        uint32_t* d_values_out, uint32_t group, void* stream);
+
+/* Multi-value insert of n pairs grouped by key (not in the paper: the paper's per-pair insert,
+ * hc_insert, makes the i-th copy of a key scan past the i-1 earlier ones, so a key with m copies
+ * costs about m^2/(2W) window visits, Sec. V-B).  The pairs are sorted by key in a workspace and each
+ * key's run claims its slots in one pass along its window sequence (runs of 2048 or more pairs by a
+ * block of 1024 threads); the stored multiset, the layout invariant and every later result equal
+ * those of hc_insert.  Pairs with reserved keys are skipped; pairs that find no reusable slot are
+ * dropped (hc_size tells how many were stored).  Needs a workspace of about 48 bytes per pair
+ * (allocated by the table; growing it synchronises the device).  Multi-value tables only. */
+hc_err hc_insert_grouped(hc_table table, const uint32_t* d_keys, const uint32_t* d_values, uint64_t n, void* stream);
 
 /* Live entries (single-value / counting: keys; multi-value: pairs).  Synchronises the stream. */
 hc_err hc_size(hc_table table, uint64_t* h_out, void* stream);

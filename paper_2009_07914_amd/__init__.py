@@ -77,6 +77,7 @@ _SIGS = {
     "hc_erase": ([_p, _p, _u64, _p, _u32, _p], ctypes.c_int),
     "hc_count_values": ([_p, _p, _u64, _p, _p, ctypes.POINTER(_u64), _u32, _p], ctypes.c_int),
     "hc_retrieve_all": ([_p, _p, _u64, _p, _p, _u32, _p], ctypes.c_int),
+    "hc_insert_grouped": ([_p, _p, _p, _u64, _p], ctypes.c_int),
     "hc_size": ([_p, ctypes.POINTER(_u64), _p], ctypes.c_int),
     "hc_load_factor": ([_p, ctypes.POINTER(ctypes.c_double), _p], ctypes.c_int),
     "hc_capacity": ([_p, ctypes.POINTER(_u64)], ctypes.c_int),
@@ -204,6 +205,12 @@ def hc_retrieve_all(h: int, keys, offsets, values_out, group: int = 0, stream=No
     off = offsets.view(torch.uint64) if offsets.dtype == torch.int64 else offsets
     _check(_lib.hc_retrieve_all(h, _u32t(keys, "keys"), n, _dptr(off, torch.uint64, "offsets", n + 1),
                                 _u32t(values_out, "values_out"), group, _stream(stream)), "hc_retrieve_all")
+
+
+def hc_insert_grouped(h: int, keys, values, stream=None):
+    n = keys.numel()
+    _check(_lib.hc_insert_grouped(h, _u32t(keys, "keys"), _u32t(values, "values", n), n, _stream(stream)),
+           "hc_insert_grouped")
 
 
 def hc_size(h: int, stream=None) -> int:

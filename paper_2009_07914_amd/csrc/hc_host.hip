@@ -17,7 +17,9 @@
 #include "hc.h"
 #include "hc_batch.hpp"
 #include "hc_device.hpp"
+#include "hc_group.hpp"
 #include "hc_launch.hpp"
+#include "hc_sort.hpp"
 
 struct hc_batch_s {
   int device = 0;
@@ -35,6 +37,8 @@ struct hc_table_s {
   unsigned long long* d_size;
   uint64_t* d_tiles;      // prefix-sum workspace (tile sums)
   uint64_t tiles_cap;     // entries allocated in d_tiles
+  void* d_ws;             // workspace of the multi-value passes (long-query lists, grouped insert)
+  uint64_t ws_bytes;
 };
 
 namespace hc {
@@ -73,17 +77,19 @@ int device_cu_count() {
   return cached[dev];
 }
 
-int blocks_per_cu(const void* kernel) {
+int blocks_per_cu_threads(const void* kernel, int threads) {
   static std::mutex mu;
   static std::unordered_map<const void*, int> cache;
   std::lock_guard<std::mutex> lock(mu);
   auto it = cache.find(kernel);
   if (it != cache.end()) return it->second;
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, BLOCK, 0) != hipSuccess || nb <= 0) nb = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess || nb <= 0) nb = 1;
   cache.emplace(kernel, nb);
   return nb;
 }
+
+int blocks_per_cu(const void* kernel) { return blocks_per_cu_threads(kernel, BLOCK); }
 
 // Launch-slot ring: per device, LAUNCH_SLOTS pairs of work counters, one pair per
 // launch in round-robin order.  A launch's last wavefront resets its pair, so a
@@ -229,6 +235,43 @@ __global__ __launch_bounds__(BLOCK) void k_scan_apply(uint64_t* __restrict__ a, 
     if (base + j < n) a[base + j] = p;
     p += v[j];
   }
+}
+
+uint64_t scan_tiles_needed(uint64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE + 1; }
+
+hc_err exclusive_scan_inplace(uint64_t* a, uint64_t n, uint64_t* tiles, hipStream_t s) {
+  const uint64_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+  if (n > 0) {
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)ntiles), dim3(BLOCK), 0, s, a, n, tiles);
+    if (hc_err r = check_launch("scan tile sums"); r != HC_OK) return r;
+  }
+  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(BLOCK), 0, s, tiles, ntiles, a, n);
+  if (hc_err r = check_launch("scan tiles"); r != HC_OK) return r;
+  if (n > 0) {
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(BLOCK), 0, s, a, n, tiles);
+    if (hc_err r = check_launch("scan apply"); r != HC_OK) return r;
+  }
+  return HC_OK;
+}
+
+// Grow the table's workspace to at least `bytes` (synchronises the device when it grows).
+static hc_err ensure_ws(hc_table_s* t, uint64_t bytes) {
+  if (t->ws_bytes >= bytes) return HC_OK;
+  if (t->d_ws) {
+    const hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return fail(HC_E_DEVICE, "workspace: synchronise: %s", hipGetErrorString(e));
+    (void)hipFree(t->d_ws);
+    t->d_ws = nullptr;
+    t->ws_bytes = 0;
+  }
+  const hipError_t e = hipMalloc(&t->d_ws, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    t->d_ws = nullptr;
+    return fail(HC_E_NOMEM, "hipMalloc of %llu workspace bytes failed", (unsigned long long)bytes);
+  }
+  t->ws_bytes = bytes;
+  return HC_OK;
 }
 
 static TableView view_of(const hc_table_s* t) {
@@ -480,6 +523,7 @@ hc_err hc_destroy(hc_table t) {
   if (t->slots) (void)hipFree(t->slots);
   if (t->d_size) (void)hipFree(t->d_size);
   if (t->d_tiles) (void)hipFree(t->d_tiles);
+  if (t->d_ws) (void)hipFree(t->d_ws);
   delete t;
   if (e != hipSuccess) return hip_fail(e, "hc_destroy: synchronise");
   return HC_OK;
@@ -526,8 +570,8 @@ hc_err hc_retrieve(hc_table t, const uint32_t* d_keys, uint64_t n, uint32_t* d_v
   if (d_keys == nullptr) return fail(HC_E_ARG, "keys is NULL");
   if ((r = set_device(t)) != HC_OK) return r;
   if (t->kind == HC_MULTI_VALUE)
-    return launch_count_multi(view_of(t), g, t->window, d_keys, n, d_values_out, nullptr, d_found_out,
-                              (hipStream_t)stream);
+    return launch_count_multi(view_of(t), g, t->window, d_keys, n, d_values_out, nullptr, d_found_out, 0xFFFFFFFFu,
+                              nullptr, nullptr, (hipStream_t)stream);
   return launch_retrieve(view_of(t), g, t->window, d_keys, n, d_values_out, d_found_out, (hipStream_t)stream);
 }
 
@@ -571,17 +615,19 @@ hc_err hc_count_values(hc_table t, const uint32_t* d_keys, uint64_t n, uint32_t*
     t->tiles_cap = need;
   }
   if (n > 0) {
-    if ((r = launch_count_multi(view_of(t), g, t->window, d_keys, n, d_counts, d_offsets, nullptr, s)) != HC_OK)
+    // queries still open after LONG_BUDGET windows are finished by the block-wide kernel
+    if ((r = ensure_ws(t, 256 + 8 * n)) != HC_OK) return r;
+    unsigned long long* nlong = (unsigned long long*)t->d_ws;
+    uint64_t* list = (uint64_t*)((char*)t->d_ws + 256);
+    if ((r = launch_zero_u64(nlong, 1, s)) != HC_OK) return r;
+    if ((r = launch_count_multi(view_of(t), g, t->window, d_keys, n, d_counts, d_offsets, nullptr, LONG_BUDGET, list,
+                                nlong, s)) != HC_OK)
       return r;
-    hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)ntiles), dim3(BLOCK), 0, s, d_offsets, n, t->d_tiles);
-    if ((r = check_launch("scan tile sums")) != HC_OK) return r;
+    if ((r = launch_long_count(view_of(t), t->window, d_keys, list, nlong, n, LONG_BUDGET, d_offsets, d_counts, s)) !=
+        HC_OK)
+      return r;
   }
-  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(BLOCK), 0, s, t->d_tiles, ntiles, d_offsets, n);
-  if ((r = check_launch("scan tiles")) != HC_OK) return r;
-  if (n > 0) {
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)ntiles), dim3(BLOCK), 0, s, d_offsets, n, t->d_tiles);
-    if ((r = check_launch("scan apply")) != HC_OK) return r;
-  }
+  if ((r = exclusive_scan_inplace(d_offsets, n, t->d_tiles, s)) != HC_OK) return r;
   if (h_total) {
     hipError_t e = hipMemcpyAsync(h_total, d_offsets + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -600,7 +646,27 @@ hc_err hc_retrieve_all(hc_table t, const uint32_t* d_keys, uint64_t n, const uin
   if (n == 0) return HC_OK;
   if (d_keys == nullptr || d_offsets == nullptr) return fail(HC_E_ARG, "keys or offsets is NULL");
   if ((r = set_device(t)) != HC_OK) return r;
-  return launch_write_multi(view_of(t), g, t->window, d_keys, n, d_offsets, d_values_out, (hipStream_t)stream);
+  hipStream_t s = (hipStream_t)stream;
+  if ((r = ensure_ws(t, 256 + 16 * n)) != HC_OK) return r;
+  unsigned long long* nlong = (unsigned long long*)t->d_ws;
+  uint64_t* list = (uint64_t*)((char*)t->d_ws + 256);
+  if ((r = launch_zero_u64(nlong, 1, s)) != HC_OK) return r;
+  if ((r = launch_write_multi(view_of(t), g, t->window, d_keys, n, d_offsets, d_values_out, LONG_BUDGET, list, nlong,
+                              s)) != HC_OK)
+    return r;
+  return launch_long_write(view_of(t), t->window, d_keys, list, nlong, n, LONG_BUDGET, d_offsets, d_values_out, s);
+}
+
+hc_err hc_insert_grouped(hc_table t, const uint32_t* d_keys, const uint32_t* d_values, uint64_t n, void* stream) {
+  hc_err r = check_table(t);
+  if (r != HC_OK) return r;
+  if (t->kind != HC_MULTI_VALUE) return fail(HC_E_KIND, "grouped insert needs a multi-value table");
+  if (n == 0) return HC_OK;
+  if (d_keys == nullptr || d_values == nullptr) return fail(HC_E_ARG, "keys or values is NULL");
+  if (n > 0xFFFFFFFFull) return fail(HC_E_ARG, "grouped insert takes at most 2^32-1 pairs");
+  if ((r = set_device(t)) != HC_OK) return r;
+  if ((r = ensure_ws(t, grouped_workspace_bytes(n))) != HC_OK) return r;
+  return launch_grouped_insert(view_of(t), t->window, d_keys, d_values, n, t->d_ws, (hipStream_t)stream);
 }
 
 hc_err hc_size(hc_table t, uint64_t* h_out, void* stream) {

@@ -564,6 +564,9 @@ struct CountMulti {
   uint32_t* __restrict__ counts;
   uint64_t* __restrict__ offsets;
   uint8_t* __restrict__ found_out;
+  uint32_t budget = 0xFFFFFFFFu;              // windows before handing the query over
+  uint64_t* __restrict__ long_list = nullptr;  // handed-over queries
+  unsigned long long* long_n = nullptr;
   uint64_t i = 0;
   uint32_t k = 0, lbase = 0, cnt = 0, k_nx = 0;
   Seq s{};
@@ -590,6 +593,13 @@ struct CountMulti {
     load_step<G, W>(t, ln, s, lbase, k, win);
     cnt += g.sum(popcount(win.match));
     if (g.bits(win.empty != 0) || ln.exhausted(t, lbase)) return done();
+    if (lbase + L::WPS >= budget) {  // long: continued by the block-wide kernel from window `budget`
+      if (g.glane == 0) {
+        long_list[atomicAdd(long_n, 1ull)] = i;
+        offsets[i] = cnt;
+      }
+      return true;
+    }
     ln.advance(t, s, lbase);
     return false;
   }
@@ -599,13 +609,17 @@ struct CountMulti {
 template <int G, int W>
 __global__ __launch_bounds__(BLOCK) void k_count_multi(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys, uint64_t n,
                                                        uint32_t* __restrict__ counts, uint64_t* __restrict__ offsets,
-                                                       uint8_t* __restrict__ found_out) {
+                                                       uint8_t* __restrict__ found_out, uint32_t budget,
+                                                       uint64_t* __restrict__ long_list, unsigned long long* long_n) {
   CountMulti<G, W> op;
   op.t = t;
   op.keys = keys;
   op.counts = counts;
   op.offsets = offsets;
   op.found_out = found_out;
+  op.budget = budget;
+  op.long_list = long_list;
+  op.long_n = long_n;
   drive<G>(n, ctl, op);
 }
 
@@ -622,6 +636,9 @@ struct WriteMulti {
   const uint32_t* __restrict__ keys;
   const uint64_t* __restrict__ offsets;
   uint32_t* __restrict__ out;
+  uint32_t budget = 0xFFFFFFFFu;
+  uint64_t* __restrict__ long_list = nullptr;  // (query, values written) pairs
+  unsigned long long* long_n = nullptr;
   uint64_t i = 0, base = 0, limit = 0, written = 0, base_nx = 0, end_nx = 0;
   uint32_t k = 0, lbase = 0, k_nx = 0;
   Seq s{};
@@ -657,6 +674,14 @@ struct WriteMulti {
     }
     written += total;
     if (written >= limit || g.bits(win.empty != 0) || ln.exhausted(t, lbase)) return true;
+    if (lbase + L::WPS >= budget) {
+      if (g.glane == 0) {
+        const unsigned long long j = atomicAdd(long_n, 1ull);
+        long_list[2 * j] = i;
+        long_list[2 * j + 1] = written;
+      }
+      return true;
+    }
     ln.advance(t, s, lbase);
     return false;
   }
@@ -666,12 +691,16 @@ struct WriteMulti {
 template <int G, int W>
 __global__ __launch_bounds__(BLOCK) void k_write_multi(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys, uint64_t n,
                                                        const uint64_t* __restrict__ offsets,
-                                                       uint32_t* __restrict__ out) {
+                                                       uint32_t* __restrict__ out, uint32_t budget,
+                                                       uint64_t* __restrict__ long_list, unsigned long long* long_n) {
   WriteMulti<G, W> op;
   op.t = t;
   op.keys = keys;
   op.offsets = offsets;
   op.out = out;
+  op.budget = budget;
+  op.long_list = long_list;
+  op.long_n = long_n;
   drive<G>(n, ctl, op);
 }
 

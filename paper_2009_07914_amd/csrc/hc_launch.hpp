@@ -19,6 +19,7 @@ int device_cu_count();
 
 // Resident blocks per CU of a kernel (occupancy calculator, cached per kernel).
 int blocks_per_cu(const void* kernel);
+int blocks_per_cu_threads(const void* kernel, int threads);
 
 // Grid for a bulk kernel: the device's resident capacity, or fewer blocks when
 // the batch is small (at most one element per group).
@@ -74,9 +75,13 @@ hc_err launch_retrieve(const TableView& t, uint32_t G, uint32_t W, const uint32_
                        uint32_t* values_out, uint8_t* found_out, hipStream_t stream);
 hc_err launch_erase(const TableView& t, int kind, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n,
                     uint8_t* status, hipStream_t stream);
+// budget: windows a group scans before handing the query to the long-query kernel
+// (appending it to long_list); 0xFFFFFFFF: never.
 hc_err launch_count_multi(const TableView& t, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n,
-                          uint32_t* counts, uint64_t* offsets, uint8_t* found_out, hipStream_t stream);
+                          uint32_t* counts, uint64_t* offsets, uint8_t* found_out, uint32_t budget,
+                          uint64_t* long_list, unsigned long long* long_n, hipStream_t stream);
 hc_err launch_write_multi(const TableView& t, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n,
-                          const uint64_t* offsets, uint32_t* out, hipStream_t stream);
+                          const uint64_t* offsets, uint32_t* out, uint32_t budget, uint64_t* long_list,
+                          unsigned long long* long_n, hipStream_t stream);
 
 }  // namespace hc

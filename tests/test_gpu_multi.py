@@ -110,3 +110,70 @@ def test_multivalue_full_and_reserved(hc):
     # empty query batch still yields offsets[0] = 0
     _, off, tot = t.count_values(torch.empty(0, dtype=torch.uint32, device="cuda"))
     assert tot == 0 and int(h(off)[0]) == 0
+
+
+# ---- grouped insert and long queries (keys with thousands of values) -------------------
+
+@pytest.mark.parametrize("scheme", ["linear", "quadratic", "double"])
+@pytest.mark.parametrize("window", [8, 16, 32, 64])
+def test_grouped_insert_zipf_matches_oracle(hc, scheme, window):
+    """Zipf(1.1) over 2^10 keys, 2^18 pairs: the top keys have tens of thousands of copies, so runs are
+    claimed by whole blocks and count / retrieve-all hand them to the long-query kernels."""
+    w = gen.multi_value_zipf_workload(1 << 18, 1 << 10, 1.1, 51 + window)
+    t = hc.Table("multi", 1 << 19, scheme=scheme, window=window, group=4)
+    hc.hc_insert_grouped(t.handle, d(w["keys"]), d(w["values"]))
+    orc = oracle.OracleTable(oracle.MULTI, t.capacity)
+    orc.insert(w["keys"], w["values"])
+    assert t.size() == orc.size() == w["keys"].size
+    _mv_parity(t, orc, w["queries"], 4)
+    _mv_parity(t, orc, w["queries"], 64)
+    check_layout(t, oracle.MULTI)
+
+
+def test_grouped_then_per_pair_then_erase(hc):
+    w = gen.multi_value_zipf_workload(1 << 17, 1 << 9, 1.1, 77)
+    t = hc.Table("multi", 1 << 18, scheme="double", window=16, group=8)
+    orc = oracle.OracleTable(oracle.MULTI, t.capacity)
+    half = w["keys"].size // 2
+    hc.hc_insert_grouped(t.handle, d(w["keys"][:half]), d(w["values"][:half]))
+    orc.insert(w["keys"][:half], w["values"][:half])
+    t.insert(d(w["keys"][half:]), d(w["values"][half:]))
+    orc.insert(w["keys"][half:], w["values"][half:])
+    _mv_parity(t, orc, w["queries"], 4)
+    er = w["queries"][:40]  # includes heavy keys
+    assert np.array_equal(h(t.erase(d(er), status=True)), orc.erase(er))
+    hc.hc_insert_grouped(t.handle, d(w["keys"][:5000]), d(w["values"][:5000]))  # reuses tombstones
+    orc.insert(w["keys"][:5000], w["values"][:5000])
+    assert t.size() == orc.size()
+    _mv_parity(t, orc, w["queries"], 16)
+    check_layout(t, oracle.MULTI)
+
+
+def test_grouped_insert_reserved_and_overfull(hc):
+    keys = np.concatenate([np.full(3000, 5, np.uint32), np.arange(1, 2000, dtype=np.uint32),
+                           np.array([0, 0xFFFFFFFF, 0], np.uint32)])
+    vals = gen.values(9, keys.size)
+    t = hc.Table("multi", 1 << 13, scheme="double", window=16)
+    hc.hc_insert_grouped(t.handle, d(keys), d(vals))
+    orc = oracle.OracleTable(oracle.MULTI, t.capacity)
+    orc.insert(keys, vals)
+    assert t.size() == orc.size() == keys.size - 3
+    _mv_parity(t, orc, np.arange(0, 2001, dtype=np.uint32), 4)
+    # over-full: 600 pairs into 512 slots -> exactly 512 stored, each an input pair, layout valid
+    k2 = np.repeat(np.arange(1, 61, dtype=np.uint32), 10)
+    v2 = gen.values(10, k2.size)
+    t2 = hc.Table("multi", 512, scheme="linear", window=16)
+    hc.hc_insert_grouped(t2.handle, d(k2), d(v2))
+    assert t2.size() == 512
+    slots = h(t2.dump_slots())
+    stored = {(int(s & 0xFFFFFFFF), int(s >> 32)) for s in slots if s != 0}
+    assert len(stored) == 512 and stored <= set(zip(k2.tolist(), v2.tolist()))
+    check_layout(t2, oracle.MULTI)
+
+
+def test_grouped_insert_needs_multi_value(hc):
+    t = hc.Table("single", 1024)
+    k = d(np.arange(1, 10, dtype=np.uint32))
+    with pytest.raises(hc.HcError) as e:
+        hc.hc_insert_grouped(t.handle, k, k)
+    assert e.value.code == hc.E_KIND
