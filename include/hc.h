@@ -106,6 +106,18 @@ void hc_default_params(hc_params* params);
  * P > 2^31), HC_E_NOMEM. */
 hc_err hc_create(hc_table* out, uint32_t kind, uint64_t capacity, const hc_params* params);
 
+/* Bytes of slot memory a table of this capacity and these params needs (8 * C after the
+ * rounding of hc_create), for hc_create_in.  params may be NULL (defaults). */
+hc_err hc_table_bytes(uint64_t capacity, const hc_params* params, uint64_t* h_out);
+
+/* As hc_create, but the slot array is caller-owned device memory on the current device
+ * (e.g. a torch tensor): d_slots must be 256-byte aligned and hold slot_bytes >= hc_table_bytes
+ * bytes; it is cleared here (the call synchronises) and never freed by the library.  The caller
+ * keeps it alive until hc_destroy.  Errors as hc_create, plus HC_E_ARG for a NULL, misaligned or
+ * too small array. */
+hc_err hc_create_in(hc_table* out, uint32_t kind, void* d_slots, uint64_t slot_bytes, uint64_t capacity,
+                    const hc_params* params);
+
 /* Release the table and its device memory (synchronises the device). */
 hc_err hc_destroy(hc_table table);
 
@@ -150,14 +162,19 @@ hc_err hc_count_values(hc_table table, const uint32_t* d_keys, uint64_t n, uint3
 hc_err hc_retrieve_all(hc_table table, const uint32_t* d_keys, uint64_t n, const uint64_t* d_offsets,
                        uint32_t* d_values_out, uint32_t group, void* stream);
 
-/* Multi-value insert of n pairs grouped by key (not in the paper: the paper's per-pair insert,
- * hc_insert, makes the i-th copy of a key scan past the i-1 earlier ones, so a key with m copies
- * costs about m^2/(2W) window visits, Sec. V-B).  The pairs are sorted by key in a workspace and each
- * key's run claims its slots in one pass along its window sequence (runs of 2048 or more pairs by a
- * block of 1024 threads); the stored multiset, the layout invariant and every later result equal
- * those of hc_insert.  Pairs with reserved keys are skipped; pairs that find no reusable slot are
- * dropped (hc_size tells how many were stored).  Needs a workspace of about 48 bytes per pair
- * (allocated by the table; growing it synchronises the device).  Multi-value tables only. */
+/* Insert of n keys grouped by key, for batches in which some keys repeat very often (not in the
+ * paper).  The batch is sorted by key in a workspace (about 48 bytes per element, allocated by the
+ * table; growing it synchronises the device) and handled run by run:
+ *  - multi-value tables: the paper's per-pair insert, hc_insert, makes the i-th copy of a key scan past
+ *    the i-1 earlier ones, so a key with m copies costs about m^2/(2W) window visits (Sec. V-B); here
+ *    each key's run claims its slots in one pass along its window sequence (long runs spread over the
+ *    whole device).  The stored multiset, the layout invariant and every later result equal those of
+ *    hc_insert.  d_values: n values, pair i = (d_keys[i], d_values[i]).
+ *  - counting tables: each distinct key is inserted once, its count raised by its number of
+ *    occurrences (one atomic per distinct key instead of one per occurrence).  d_values must be NULL.
+ * Keys 0 and 0xFFFFFFFF are skipped; elements that find no reusable slot are dropped (hc_size tells
+ * how many pairs / distinct keys are stored).  No per-element status.  n < 2^32.  Single-value
+ * tables: HC_E_KIND. */
 hc_err hc_insert_grouped(hc_table table, const uint32_t* d_keys, const uint32_t* d_values, uint64_t n, void* stream);
 
 /* Live entries (single-value / counting: keys; multi-value: pairs).  Synchronises the stream. */
@@ -171,6 +188,22 @@ hc_err hc_capacity(hc_table table, uint64_t* h_out);
 
 /* Table geometry and the device address of its slot array. */
 hc_err hc_info(hc_table table, hc_table_info* h_out);
+
+/* Full scan of the slot array (a diagnostic, not on the hot path).  The probe length of a
+ * live slot is the number of windows a retrieval of its key visits up to and including the
+ * slot's window: its index l in the key's window sequence (Sec. II), plus one.  It grows with
+ * the load factor (Sec. IV-B); live counts the same entries as hc_size. */
+#define HC_PROBE_BUCKETS 16
+typedef struct {
+  uint64_t live;        /* slots holding a key */
+  uint64_t tombstones;  /* erased slots (Sec. IV-B5) */
+  uint64_t empty;
+  uint64_t max_probe;   /* largest probe length over live slots (<= P) */
+  uint64_t probe_sum;   /* sum of probe lengths over live slots */
+  uint64_t probe_hist[HC_PROBE_BUCKETS];  /* live slots with probe length in [2^b, 2^(b+1)); last bucket open */
+} hc_table_stats;
+/* Synchronises the stream.  Errors: HC_E_ARG (NULL output), HC_E_NOMEM. */
+hc_err hc_stats(hc_table table, hc_table_stats* h_out, void* stream);
 
 /* Copy the C slot words into caller memory d_dst (C uint64, device), on the stream. */
 hc_err hc_dump_slots(hc_table table, uint64_t* d_dst, void* stream);

@@ -43,6 +43,15 @@ class HcTableInfo(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("d_slots", ctypes.c_void_p)]
 
 
+PROBE_BUCKETS = 16
+
+
+class HcTableStats(ctypes.Structure):
+    _fields_ = [("live", ctypes.c_uint64), ("tombstones", ctypes.c_uint64), ("empty", ctypes.c_uint64),
+                ("max_probe", ctypes.c_uint64), ("probe_sum", ctypes.c_uint64),
+                ("probe_hist", ctypes.c_uint64 * PROBE_BUCKETS)]
+
+
 class HcBatchOp(ctypes.Structure):
     _fields_ = [("table", ctypes.c_void_p), ("op", ctypes.c_uint32), ("group", ctypes.c_uint32),
                 ("d_keys", ctypes.c_void_p), ("d_values", ctypes.c_void_p), ("d_values_out", ctypes.c_void_p),
@@ -70,6 +79,9 @@ _p, _u32, _u64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
 _SIGS = {
     "hc_default_params": ([ctypes.POINTER(HcParams)], None),
     "hc_create": ([ctypes.POINTER(_p), _u32, _u64, ctypes.POINTER(HcParams)], ctypes.c_int),
+    "hc_create_in": ([ctypes.POINTER(_p), _u32, _p, _u64, _u64, ctypes.POINTER(HcParams)], ctypes.c_int),
+    "hc_table_bytes": ([_u64, ctypes.POINTER(HcParams), ctypes.POINTER(_u64)], ctypes.c_int),
+    "hc_stats": ([_p, ctypes.POINTER(HcTableStats), _p], ctypes.c_int),
     "hc_destroy": ([_p], ctypes.c_int),
     "hc_clear": ([_p, _p], ctypes.c_int),
     "hc_insert": ([_p, _p, _p, _u64, _p, _u32, _p], ctypes.c_int),
@@ -162,6 +174,28 @@ def hc_create(kind: int, capacity: int, params: HcParams | None = None) -> int:
     return h.value
 
 
+def hc_table_bytes(capacity: int, params: HcParams | None = None) -> int:
+    out = ctypes.c_uint64(0)
+    _check(_lib.hc_table_bytes(capacity, ctypes.byref(params) if params else None, ctypes.byref(out)),
+           "hc_table_bytes")
+    return out.value
+
+
+def hc_create_in(kind: int, slots, capacity: int, params: HcParams | None = None) -> int:
+    """Table over caller-owned device memory ``slots`` (a tensor the caller keeps alive)."""
+    h = ctypes.c_void_p()
+    nbytes = slots.numel() * slots.element_size()
+    _check(_lib.hc_create_in(ctypes.byref(h), kind, slots.data_ptr(), nbytes, capacity,
+                             ctypes.byref(params) if params else None), "hc_create_in")
+    return h.value
+
+
+def hc_stats(h: int, stream=None) -> HcTableStats:
+    out = HcTableStats()
+    _check(_lib.hc_stats(h, ctypes.byref(out), _stream(stream)), "hc_stats")
+    return out
+
+
 def hc_destroy(h: int):
     _check(_lib.hc_destroy(h), "hc_destroy")
 
@@ -207,7 +241,7 @@ def hc_retrieve_all(h: int, keys, offsets, values_out, group: int = 0, stream=No
                                 _u32t(values_out, "values_out"), group, _stream(stream)), "hc_retrieve_all")
 
 
-def hc_insert_grouped(h: int, keys, values, stream=None):
+def hc_insert_grouped(h: int, keys, values=None, stream=None):
     n = keys.numel()
     _check(_lib.hc_insert_grouped(h, _u32t(keys, "keys"), _u32t(values, "values", n), n, _stream(stream)),
            "hc_insert_grouped")
@@ -442,16 +476,22 @@ class Table:
     """A table handle with allocation of outputs.  ``kind``: 'single' | 'multi' | 'counting'."""
 
     def __init__(self, kind="single", capacity=1 << 20, scheme="double", window=16, group=4,
-                 seed=None, device=None):
+                 seed=None, device=None, slots=None):
+        """``slots``: optional caller-owned uint8/uint64 device tensor holding the slot array
+        (hc_create_in); the Table keeps a reference to it."""
         self.kind = KINDS[kind] if isinstance(kind, str) else int(kind)
         p = hc_default_params()
         p.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
         p.window, p.group = window, group
         if seed is not None:
             p.seed = seed & (2**64 - 1)
+        if slots is not None:
+            device = slots.device
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.slots = slots
         with torch.cuda.device(self.device):
-            self.handle = hc_create(self.kind, capacity, p)
+            self.handle = hc_create(self.kind, capacity, p) if slots is None else \
+                hc_create_in(self.kind, slots, capacity, p)
         info = hc_info(self.handle)
         self.capacity, self.windows, self.window = int(info.capacity), int(info.windows), int(info.window)
         self.scheme, self.seed, self.group = int(info.scheme), int(info.seed), int(info.group)
@@ -505,6 +545,11 @@ class Table:
 
     def load_factor(self, stream=None) -> float:
         return hc_load_factor(self.handle, stream)
+
+    def stats(self, stream=None) -> dict:
+        st = hc_stats(self.handle, stream)
+        return {"live": st.live, "tombstones": st.tombstones, "empty": st.empty, "max_probe": st.max_probe,
+                "probe_sum": st.probe_sum, "probe_hist": list(st.probe_hist)}
 
     def dump_slots(self, stream=None):
         out = torch.empty(self.capacity, dtype=torch.uint64, device=self.device)

@@ -8,13 +8,26 @@
 // stored multiset and the same layout invariant (no empty position before any
 // stored position of a key) while removing the quadratic term:
 //   * grouped insert: pairs are sorted by key; each run of one key claims its m
-//     slots in one pass along the sequence (a wavefront per run, or a whole block
-//     of 1024 threads for runs of at least HEAVY pairs), claiming reusable slots in
-//     sequence order with a CAS to a placeholder and then writing the run's values
-//     in the order of the successful claims;
+//     slots in one pass along the sequence (a wavefront per run).  A run of at
+//     least HEAVY_RUN pairs is first spread over the whole grid in claim rounds:
+//     a round hands out, in segments of one block step, exactly as many further
+//     windows of the key's sequence as the values still to be placed could fill
+//     (remaining / W), so every reusable slot in them is certainly needed and is
+//     claimed, whatever block gets there first; what is left after the rounds is
+//     claimed by one block walking on from where they ended.  Claims CAS the
+//     reusable word to a placeholder (k, 0); the block then writes values, taken
+//     from the run by a per-run counter, with atomic exchanges;
 //   * long queries: count and write passes give up after `budget` windows and
-//     hand the query to a kernel in which a block of 1024 threads scans 4096 slots
-//     per step.
+//     hand the query to rounds in which blocks scan segments of its sequence in
+//     parallel (4^r segments per open query in round r).  Speculative segments
+//     past the end of a key's copies find no match, since no copy of a key lies
+//     after a window holding an empty slot, so counts add up exactly; a query whose
+//     segments all missed an empty window goes on to the next round.  There are
+//     enough rounds for their segments to cover a whole sequence.
+//   * counting tables: the sorted keys are reduced to (key, run length) and each
+//     distinct key is inserted once with its run length as the increment, so a
+//     key that makes up a large part of a batch costs one atomic, not millions on
+//     the same slot.
 #include "hc_group.hpp"
 #include "hc_kernels.hpp"
 #include "hc_launch.hpp"
@@ -26,6 +39,9 @@ constexpr int GB = 1024;              // threads per block of the run / long-que
 constexpr int GB_WAVES = GB / 64;
 constexpr int GB_SPL = 4;             // slots per lane in block mode
 constexpr uint32_t RUN_GRAB = 16;     // light runs taken per wavefront atomic
+constexpr int IROUNDS = 10;           // claim rounds of heavy runs
+constexpr uint64_t ROUND_MIN = 4ull * GB * GB_SPL;  // heavy runs with fewer values left finish in one block
+constexpr int QROUNDS_MAX = 16;       // long-query rounds; round r gives each open query 4^r segments
 
 struct KeySeq {
   uint32_t w0, step;
@@ -72,15 +88,16 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t x, uint32_t* total, uint
 
 // ---- grouped insert -------------------------------------------------------------
 
-// Claim m slots for key k with a whole block; the run's values are vals[0..m).
+// Claim m slots for key k with a whole block, walking its sequence from window l0
+// (every reusable slot before l0 is already taken); the values are vals[0..m).
 template <int W>
 __device__ void claim_run_block(const TableView& t, uint32_t k, const uint32_t* __restrict__ vals, uint64_t m,
-                                uint64_t& added, uint32_t* lds) {
+                                uint64_t l0, uint64_t& added, uint32_t* lds) {
   constexpr uint32_t WPS_B = GB * GB_SPL / W;  // sequence windows per step
   const KeySeq q = key_seq(t, k);
   const uint32_t widx = (threadIdx.x * GB_SPL) / W, j0 = (threadIdx.x * GB_SPL) % W;
   uint64_t claimed = 0;
-  for (uint64_t lbase = 0; claimed < m && lbase < t.P; lbase += WPS_B) {
+  for (uint64_t lbase = l0; claimed < m && lbase < t.P; lbase += WPS_B) {
     const uint64_t l = lbase + widx;
     uint64_t first = 0, word[GB_SPL];
     uint32_t reuse = 0, emptym = 0;
@@ -199,26 +216,162 @@ __global__ __launch_bounds__(256) void k_heavy_list(const uint64_t* __restrict__
     heavy[atomicAdd(nheavy, 1ull)] = (uint32_t)r;
 }
 
+// Per heavy run: next sequence window of the current round, windows in it, values placed.
+struct HeavyState {
+  uint64_t* pos;
+  uint64_t* nw;
+  unsigned long long* used;
+  uint64_t* seg;  // exclusive prefix of the round's segments per heavy run; seg[H] = total
+};
+
+// Plan one claim round (one block): advance every heavy run past the previous
+// round's windows and give it remaining / W more, in segments of one block step.
+template <int W>
+__global__ __launch_bounds__(GB) void k_heavy_plan(TableView t, const uint32_t* __restrict__ keys,
+                                                   const uint64_t* __restrict__ starts,
+                                                   const uint32_t* __restrict__ heavy,
+                                                   const unsigned long long* __restrict__ nheavy, HeavyState hs,
+                                                   int first) {
+  constexpr uint64_t SEGW = GB * GB_SPL / W;
+  __shared__ uint32_t lds[GB_WAVES];
+  const uint64_t H = *nheavy;
+  uint64_t carry = 0;
+  for (uint64_t b = 0; b < H; b += GB) {
+    const uint64_t h = b + threadIdx.x;
+    uint32_t segs = 0;
+    if (h < H) {
+      const uint64_t r = heavy[h], st = starts[r], m = starts[r + 1] - st;
+      uint64_t pos = 0, used = 0;
+      if (!first) {
+        pos = hs.pos[h] + hs.nw[h];
+        used = hs.used[h];
+      } else {
+        hs.used[h] = 0;
+      }
+      const uint64_t rem = m - used;
+      uint64_t nw = 0;
+      if (!reserved_key(keys[st]) && rem >= ROUND_MIN && pos < t.P) {
+        nw = rem / W;
+        if (nw > t.P - pos) nw = t.P - pos;
+      }
+      hs.pos[h] = pos;
+      hs.nw[h] = nw;
+      segs = (uint32_t)((nw + SEGW - 1) / SEGW);
+    }
+    uint32_t tot;
+    const uint32_t ex = block_scan(segs, &tot, lds);
+    if (h < H) hs.seg[h] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) hs.seg[H] = carry;
+}
+
+// One claim round: blocks take segments of any heavy run; each claims every
+// reusable slot of its segment and takes that many of the run's values.
+template <int W>
+__global__ __launch_bounds__(GB) void k_heavy_round(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys,
+                                                    const uint32_t* __restrict__ vals,
+                                                    const uint64_t* __restrict__ starts,
+                                                    const uint32_t* __restrict__ heavy,
+                                                    const unsigned long long* __restrict__ nheavy, HeavyState hs) {
+  constexpr uint64_t SEGW = GB * GB_SPL / W;
+  __shared__ uint32_t lds[GB_WAVES];
+  __shared__ unsigned long long s_item, s_base;
+  __shared__ uint32_t s_h;
+  const uint64_t H = *nheavy, T = hs.seg[H];
+  const uint32_t widx = (threadIdx.x * GB_SPL) / W, j0 = (threadIdx.x * GB_SPL) % W;
+  uint64_t added = 0;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const unsigned long long it = atomicAdd(ctl.counters, 1ull);
+      s_item = it;
+      if (it < T) {  // the heavy run owning segment `it`: last h with seg[h] <= it
+        uint64_t lo = 0, hi = H - 1;
+        while (lo < hi) {
+          const uint64_t mid = (lo + hi + 1) / 2;
+          if (hs.seg[mid] <= it) lo = mid;
+          else hi = mid - 1;
+        }
+        s_h = (uint32_t)lo;
+      }
+    }
+    __syncthreads();
+    const uint64_t it = s_item;
+    const uint32_t h = s_h;
+    __syncthreads();
+    if (it >= T) break;
+    const uint64_t r = heavy[h], st = starts[r], m = starts[r + 1] - st;
+    const uint32_t k = keys[st];
+    const KeySeq q = key_seq(t, k);
+    const uint64_t lend = hs.pos[h] + hs.nw[h];
+    const uint64_t l = hs.pos[h] + (it - hs.seg[h]) * SEGW + widx;
+    uint64_t first = 0;
+    uint32_t succ = 0;
+    if (l < lend) {
+      uint64_t word[GB_SPL];
+      first = (uint64_t)window_at(t, q, l) * W + j0;
+      load_slots<GB_SPL>(t.slots, first, word);
+#pragma unroll
+      for (int j = 0; j < GB_SPL; ++j) {
+        const uint32_t key = slot_key(word[j]);
+        if (key == KEY_EMPTY || key == KEY_TOMB) {
+          const uint64_t expect = key == KEY_EMPTY ? WORD_EMPTY : WORD_TOMB;
+          const uint64_t rw = atomicCAS((unsigned long long*)&t.slots[first + j], (unsigned long long)expect,
+                                        (unsigned long long)make_slot(k, 0u));
+          succ |= (uint32_t)(rw == expect) << j;
+        }
+      }
+    }
+    uint32_t stot;
+    const uint32_t sex = block_scan((uint32_t)__popc(succ), &stot, lds);
+    if (threadIdx.x == 0) {
+      s_base = stot ? atomicAdd(hs.used + h, (unsigned long long)stot) : 0ull;
+      added += stot;
+    }
+    __syncthreads();
+    // the round gave out at most (values left) slots, so base + stot <= m
+    uint64_t rank = s_base + sex;
+#pragma unroll
+    for (int j = 0; j < GB_SPL; ++j) {
+      if ((succ >> j) & 1u) {
+        if (rank < m)
+          atomicExch((unsigned long long*)&t.slots[first + j], (unsigned long long)make_slot(k, vals[st + rank]));
+        ++rank;
+      }
+    }
+    __syncthreads();
+  }
+  wave_add_to(t.size, (long long)added);
+  if (threadIdx.x == 0) {
+    if (atomicAdd(ctl.counters + 1, 1ull) == (unsigned long long)gridDim.x - 1) {
+      atomicExch(ctl.counters, 0ull);
+      atomicExch(ctl.counters + 1, 0ull);
+    }
+  }
+}
+
 template <int W>
 __global__ __launch_bounds__(GB) void k_claim_runs(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys,
                                                    const uint32_t* __restrict__ vals,
                                                    const uint64_t* __restrict__ starts,
                                                    const uint64_t* __restrict__ nruns,
                                                    const uint32_t* __restrict__ heavy,
-                                                   const unsigned long long* __restrict__ nheavy) {
+                                                   const unsigned long long* __restrict__ nheavy, HeavyState hs) {
   __shared__ uint32_t lds[GB_WAVES];
   __shared__ unsigned long long s_item;
   const uint64_t R = *nruns, H = *nheavy;
   uint64_t added = 0;
-  for (;;) {  // heavy runs, one block each, biggest work first in list order
+  for (;;) {  // what the rounds left of each heavy run, one block each
     if (threadIdx.x == 0) s_item = atomicAdd(ctl.counters, 1ull);
     __syncthreads();
     const uint64_t h = s_item;
     __syncthreads();
     if (h >= H) break;
     const uint64_t r = heavy[h], st = starts[r], m = starts[r + 1] - st;
+    const uint64_t used = hs.used[h];
     const uint32_t k = keys[st];
-    if (!reserved_key(k)) claim_run_block<W>(t, k, vals + st, m, added, lds);
+    if (!reserved_key(k) && used < m)
+      claim_run_block<W>(t, k, vals + st + used, m - used, hs.pos[h] + hs.nw[h], added, lds);
   }
   const uint32_t lane = __lane_id();
   for (;;) {  // light runs, one wavefront each, RUN_GRAB runs per atomic
@@ -244,61 +397,140 @@ __global__ __launch_bounds__(GB) void k_claim_runs(TableView t, WorkCtl ctl, con
   }
 }
 
+// ---- counting tables: one insert per distinct key ------------------------------------
+
+// (key, run length) of every run.
+__global__ __launch_bounds__(256) void k_run_lengths(const uint32_t* __restrict__ keys,
+                                                     const uint64_t* __restrict__ starts,
+                                                     const uint64_t* __restrict__ nruns, uint64_t max_runs,
+                                                     uint32_t* __restrict__ ukeys, uint32_t* __restrict__ ucount) {
+  const uint64_t r = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r < max_runs && r < *nruns) {
+    ukeys[r] = keys[starts[r]];
+    ucount[r] = (uint32_t)(starts[r + 1] - starts[r]);
+  }
+}
+
+template <int G, int W>
+__global__ __launch_bounds__(BLOCK) void k_insert_counts(TableView t, WorkCtl ctl, const uint32_t* __restrict__ ukeys,
+                                                         const uint32_t* __restrict__ ucount,
+                                                         const uint64_t* __restrict__ nruns) {
+  InsertUnique<G, W, KIND_COUNT> op;
+  op.t = t;
+  op.keys = ukeys;
+  op.values = ucount;
+  op.status = nullptr;
+  drive<G>(*nruns, ctl, op);
+}
+
 // ---- long queries -----------------------------------------------------------------
 
 __global__ __launch_bounds__(256) void k_zero_u64(unsigned long long* p, uint32_t count) {
   if (threadIdx.x < count) p[threadIdx.x] = 0ull;
 }
 
-// Continue the count of long queries from window `budget`: offsets[i] holds the
-// count so far and receives the full count (counts[i] too when given).
+// Scan windows [l, l + 1 window of this thread) ... of one segment: the thread's
+// GB_SPL slots of window l (if l < lend), its match mask and whether the window
+// part holds an empty slot.
 template <int W>
-__global__ __launch_bounds__(GB) void k_long_count(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys,
-                                                   const uint64_t* __restrict__ list,
-                                                   const unsigned long long* __restrict__ nlong, uint32_t budget,
-                                                   uint64_t* __restrict__ offsets, uint32_t* __restrict__ counts) {
-  constexpr uint32_t WPS_B = GB * GB_SPL / W;
-  __shared__ uint32_t lds[GB_WAVES];
-  __shared__ unsigned long long s_item;
-  __shared__ uint32_t s_first_empty;
-  const uint64_t L = *nlong;
+__device__ __forceinline__ uint32_t seg_slots(const TableView& t, const KeySeq& q, uint32_t k, uint64_t l,
+                                              uint64_t lend, uint32_t j0, uint64_t (&word)[GB_SPL], bool& empty) {
+  uint32_t mm = 0;
+  empty = false;
+  if (l < lend) {
+    load_slots<GB_SPL>(t.slots, (uint64_t)window_at(t, q, l) * W + j0, word);
+#pragma unroll
+    for (int j = 0; j < GB_SPL; ++j) {
+      mm |= (uint32_t)(slot_key(word[j]) == k) << j;
+      empty |= slot_key(word[j]) == KEY_EMPTY;
+    }
+  }
+  return mm;
+}
+
+// The matches of one segment, added to the count or written through the
+// query's cursor.  Returns (all threads) whether the query is finished: the
+// segment met a window with an empty slot, reached the end of the sequence, or
+// (write) the query's values are all written.
+template <int W, int MODE>
+__device__ __forceinline__ bool seg_visit(const TableView& t, const KeySeq& q, uint32_t k, uint64_t l0, uint64_t lend,
+                                          uint64_t i, unsigned long long* cursor, uint64_t* __restrict__ offsets,
+                                          uint32_t* __restrict__ out, uint64_t base, uint64_t limit, uint32_t* lds,
+                                          unsigned long long* s_base) {
   const uint32_t widx = (threadIdx.x * GB_SPL) / W, j0 = (threadIdx.x * GB_SPL) % W;
+  uint64_t word[GB_SPL];
+  bool empty;
+  const uint32_t mm = seg_slots<W>(t, q, k, l0 + widx, lend, j0, word, empty);
+  // matches (< 2^13 per block) in the low 16 bits, windows with an empty slot above
+  uint32_t tot;
+  const uint32_t ex = block_scan((uint32_t)__popc(mm) | ((uint32_t)empty << 16), &tot, lds) & 0xFFFFu;
+  const uint32_t nm = tot & 0xFFFFu;
+  bool fin = (tot >> 16) != 0 || lend >= t.P;
+  if constexpr (MODE == 0) {
+    if (threadIdx.x == 0 && nm) atomicAdd((unsigned long long*)&offsets[i], (unsigned long long)nm);
+  } else {
+    if (threadIdx.x == 0) *s_base = nm ? atomicAdd(cursor, (unsigned long long)nm) : atomicAdd(cursor, 0ull);
+    __syncthreads();
+    const uint64_t b = *s_base;
+    uint64_t rank = b + ex;
+#pragma unroll
+    for (int j = 0; j < GB_SPL; ++j) {
+      if ((mm >> j) & 1u) {
+        if (rank < limit) out[base + rank] = slot_value(word[j]);
+        ++rank;
+      }
+    }
+    fin = fin || b + nm >= limit;
+    __syncthreads();
+  }
+  return fin;
+}
+
+// One round: every open entry gets S segments of SEGW windows from its next
+// window on.  The last segment of an entry to finish decides whether it goes on.
+template <int W, int MODE>
+__global__ __launch_bounds__(GB) void k_long_round(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys,
+                                                   LongState ls, uint32_t round, uint64_t* __restrict__ offsets,
+                                                   uint32_t* __restrict__ out) {
+  constexpr uint64_t SEGW = GB * GB_SPL / W;
+  __shared__ uint32_t lds[GB_WAVES];
+  __shared__ unsigned long long s_item, s_base;
+  const uint64_t S = 1ull << (2 * round);
+  const uint32_t* lin = ls.lists[round & 1];
+  uint32_t* lout = ls.lists[(round + 1) & 1];
+  const uint64_t N = ls.nopen[round] * S;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(ctl.counters, 1ull);
     __syncthreads();
-    const uint64_t it = s_item;
+    const uint64_t item = s_item;
     __syncthreads();
-    if (it >= L) break;
-    const uint64_t i = list[it];
+    if (item >= N) break;
+    const uint32_t e = lin[item / S];
+    const uint64_t seg = item % S;
+    const uint64_t i = MODE == 0 ? ls.entries[e] : ls.entries[2 * e];
     const uint32_t k = keys[i];
     const KeySeq q = key_seq(t, k);
-    uint64_t cnt = offsets[i];
-    for (uint64_t lbase = budget; lbase < t.P; lbase += WPS_B) {
-      if (threadIdx.x == 0) s_first_empty = 0xFFFFFFFFu;
-      __syncthreads();
-      const uint64_t l = lbase + widx;
-      uint32_t matches = 0;
-      if (l < t.P) {
-        uint64_t word[GB_SPL];
-        load_slots<GB_SPL>(t.slots, (uint64_t)window_at(t, q, l) * W + j0, word);
-        bool empty = false;
-#pragma unroll
-        for (int j = 0; j < GB_SPL; ++j) {
-          matches += slot_key(word[j]) == k;
-          empty |= slot_key(word[j]) == KEY_EMPTY;
-        }
-        if (empty) atomicMin(&s_first_empty, widx);
-      }
-      __syncthreads();
-      const uint32_t fe = s_first_empty;
-      uint32_t tot;
-      block_scan((l < t.P && widx <= fe) ? matches : 0u, &tot, lds);
-      cnt += tot;
-      if (fe != 0xFFFFFFFFu) break;
+    const uint64_t l0 = ls.base[e] + seg * SEGW;
+    uint64_t lend = l0 + SEGW;
+    if (lend > t.P) lend = t.P;
+    uint64_t obase = 0, limit = 0;
+    if constexpr (MODE == 1) {
+      obase = offsets[i];
+      limit = offsets[i + 1] - obase;
     }
+    const bool fin = l0 < t.P && seg_visit<W, MODE>(t, q, k, l0, lend, i,
+                                                     (unsigned long long*)(ls.entries + 2 * e + 1), offsets, out,
+                                                     obase, limit, lds, &s_base);
     if (threadIdx.x == 0) {
-      offsets[i] = cnt;
-      if (counts != nullptr) counts[i] = (uint32_t)cnt;
+      if (fin || l0 >= t.P) atomicOr(ls.flag + e, 1u);
+      if (atomicAdd(ls.done + e, 1u) == (uint32_t)(S - 1)) {  // every segment of this round is done
+        const uint64_t nb = ls.base[e] + S * SEGW;
+        if (atomicOr(ls.flag + e, 0u) == 0u && nb < t.P) {
+          atomicExch((unsigned long long*)(ls.base + e), (unsigned long long)nb);
+          atomicExch(ls.done + e, 0u);
+          lout[atomicAdd(ls.nopen + round + 1, 1ull)] = e;
+        }
+      }
     }
     __syncthreads();
   }
@@ -310,67 +542,27 @@ __global__ __launch_bounds__(GB) void k_long_count(TableView t, WorkCtl ctl, con
   }
 }
 
-// Continue the write of long queries from window `budget`: list holds (i, written).
-template <int W>
-__global__ __launch_bounds__(GB) void k_long_write(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys,
-                                                   const uint64_t* __restrict__ list,
-                                                   const unsigned long long* __restrict__ nlong, uint32_t budget,
-                                                   const uint64_t* __restrict__ offsets, uint32_t* __restrict__ out) {
-  constexpr uint32_t WPS_B = GB * GB_SPL / W;
-  __shared__ uint32_t lds[GB_WAVES];
-  __shared__ unsigned long long s_item;
-  __shared__ uint32_t s_first_empty;
-  const uint64_t L = *nlong;
-  const uint32_t widx = (threadIdx.x * GB_SPL) / W, j0 = (threadIdx.x * GB_SPL) % W;
-  for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(ctl.counters, 1ull);
-    __syncthreads();
-    const uint64_t it = s_item;
-    __syncthreads();
-    if (it >= L) break;
-    const uint64_t i = list[2 * it];
-    uint64_t written = list[2 * it + 1];
-    const uint32_t k = keys[i];
-    const KeySeq q = key_seq(t, k);
-    const uint64_t base = offsets[i], limit = offsets[i + 1] - base;
-    for (uint64_t lbase = budget; lbase < t.P && written < limit; lbase += WPS_B) {
-      if (threadIdx.x == 0) s_first_empty = 0xFFFFFFFFu;
-      __syncthreads();
-      const uint64_t l = lbase + widx;
-      uint64_t word[GB_SPL];
-      uint32_t mm = 0;
-      if (l < t.P) {
-        load_slots<GB_SPL>(t.slots, (uint64_t)window_at(t, q, l) * W + j0, word);
-        bool empty = false;
-#pragma unroll
-        for (int j = 0; j < GB_SPL; ++j) {
-          mm |= (uint32_t)(slot_key(word[j]) == k) << j;
-          empty |= slot_key(word[j]) == KEY_EMPTY;
-        }
-        if (empty) atomicMin(&s_first_empty, widx);
-      }
-      __syncthreads();
-      const uint32_t fe = s_first_empty;
-      if (!(l < t.P && widx <= fe)) mm = 0;
-      uint32_t tot;
-      uint64_t rank = written + block_scan((uint32_t)__popc(mm), &tot, lds);
-#pragma unroll
-      for (int j = 0; j < GB_SPL; ++j) {
-        if ((mm >> j) & 1u) {
-          if (rank < limit) out[base + rank] = slot_value(word[j]);
-          ++rank;
-        }
-      }
-      written += tot;
-      if (fe != 0xFFFFFFFFu) break;
-    }
-    __syncthreads();
+// Round state of every handed-over entry; round 0 lists all of them.
+__global__ __launch_bounds__(256) void k_long_init(LongState ls, uint32_t budget) {
+  const uint64_t L = *ls.nlong;
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  for (uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x; e < L; e += stride) {
+    ls.base[e] = budget;
+    ls.flag[e] = 0u;
+    ls.done[e] = 0u;
+    ls.lists[0][e] = (uint32_t)e;
   }
-  if (threadIdx.x == 0) {
-    if (atomicAdd(ctl.counters + 1, 1ull) == (unsigned long long)gridDim.x - 1) {
-      atomicExch(ctl.counters, 0ull);
-      atomicExch(ctl.counters + 1, 0ull);
-    }
+  if (blockIdx.x == 0 && threadIdx.x <= QROUNDS_MAX) ls.nopen[threadIdx.x] = threadIdx.x == 0 ? L : 0ull;
+}
+
+// counts[i] of the handed-over queries, once their offsets hold the full counts.
+__global__ __launch_bounds__(256) void k_long_counts_out(LongState ls, const uint64_t* __restrict__ offsets,
+                                                         uint32_t* __restrict__ counts) {
+  const uint64_t L = *ls.nlong;
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  for (uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x; e < L; e += stride) {
+    const uint64_t i = ls.entries[e];
+    counts[i] = (uint32_t)offsets[i];
   }
 }
 
@@ -393,48 +585,79 @@ static unsigned block_grid(const void* kernel, uint64_t items) {
   return (unsigned)(g == 0 ? 1 : g);
 }
 
+static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
 uint64_t grouped_workspace_bytes(uint64_t n) {
   const uint64_t hist = sort_pairs_workspace(n);
   const uint64_t scan_n = (hist > n + 1 ? hist : n + 1);
-  return 16 * n + 8 * hist + 8 * scan_tiles_needed(scan_n) + 8 * (n + 1) + 8 * (n + 2) + 4 * (n / HEAVY_RUN + 1) +
-         256 + 6 * 256;
+  const uint64_t hmax = n / HEAVY_RUN + 1;
+  return 4 * align256(4 * n) + align256(8 * hist) + align256(8 * scan_tiles_needed(scan_n)) + align256(8 * (n + 1)) +
+         align256(8 * (n + 2)) + align256(4 * hmax) + 256 + 3 * align256(8 * hmax) + align256(8 * (hmax + 1)) + 256;
 }
 
-hc_err launch_grouped_insert(const TableView& t, uint32_t W, const uint32_t* keys, const uint32_t* values, uint64_t n,
-                             void* ws, hipStream_t s) {
+hc_err launch_grouped_insert(const TableView& t, int kind, uint32_t G, uint32_t W, const uint32_t* keys,
+                             const uint32_t* values, uint64_t n, void* ws, hipStream_t s) {
   if (n == 0) return HC_OK;
-  auto align = [](uint64_t x) { return (x + 255) & ~255ull; };
+  const bool counting = kind == KIND_COUNT;
   char* p = (char*)ws;
-  uint32_t* kc = (uint32_t*)p; p += align(4 * n);
-  uint32_t* vc = (uint32_t*)p; p += align(4 * n);
-  uint32_t* kt = (uint32_t*)p; p += align(4 * n);
-  uint32_t* vt = (uint32_t*)p; p += align(4 * n);
+  uint32_t* kc = (uint32_t*)p; p += align256(4 * n);
+  uint32_t* vc = (uint32_t*)p; p += align256(4 * n);
+  uint32_t* kt = (uint32_t*)p; p += align256(4 * n);
+  uint32_t* vt = (uint32_t*)p; p += align256(4 * n);
   const uint64_t hist_n = sort_pairs_workspace(n);
-  uint64_t* hist = (uint64_t*)p; p += align(8 * hist_n);
+  uint64_t* hist = (uint64_t*)p; p += align256(8 * hist_n);
   const uint64_t scan_n = (hist_n > n + 1 ? hist_n : n + 1);
-  uint64_t* tiles = (uint64_t*)p; p += align(8 * scan_tiles_needed(scan_n));
-  uint64_t* flags = (uint64_t*)p; p += align(8 * (n + 1));
-  uint64_t* starts = (uint64_t*)p; p += align(8 * (n + 2));
-  uint32_t* heavy = (uint32_t*)p; p += align(4 * (n / HEAVY_RUN + 1));
-  unsigned long long* nheavy = (unsigned long long*)p;
+  uint64_t* tiles = (uint64_t*)p; p += align256(8 * scan_tiles_needed(scan_n));
+  uint64_t* flags = (uint64_t*)p; p += align256(8 * (n + 1));
+  uint64_t* starts = (uint64_t*)p; p += align256(8 * (n + 2));
+  const uint64_t hmax = n / HEAVY_RUN + 1;
+  uint32_t* heavy = (uint32_t*)p; p += align256(4 * hmax);
+  unsigned long long* nheavy = (unsigned long long*)p; p += 256;
+  HeavyState hs;
+  hs.pos = (uint64_t*)p; p += align256(8 * hmax);
+  hs.nw = (uint64_t*)p; p += align256(8 * hmax);
+  hs.used = (unsigned long long*)p; p += align256(8 * hmax);
+  hs.seg = (uint64_t*)p;
   hipError_t e = hipMemcpyAsync(kc, keys, 4 * n, hipMemcpyDeviceToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(vc, values, 4 * n, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess && !counting) e = hipMemcpyAsync(vc, values, 4 * n, hipMemcpyDeviceToDevice, s);
   if (e != hipSuccess) return fail(HC_E_DEVICE, "grouped insert copy: %s", hipGetErrorString(e));
-  if (hc_err r = sort_pairs(kc, vc, kt, vt, n, hist, tiles, s); r != HC_OK) return r;
+  if (hc_err r = sort_pairs(kc, counting ? nullptr : vc, kt, counting ? nullptr : vt, n, hist, tiles, s); r != HC_OK)
+    return r;
   const unsigned g256 = (unsigned)((n + 256) / 256);
   hipLaunchKernelGGL(k_run_flags, dim3(g256), dim3(256), 0, s, kc, n, flags, nheavy);
   if (hc_err r = check_launch("run flags"); r != HC_OK) return r;
   if (hc_err r = exclusive_scan_inplace(flags, n, tiles, s); r != HC_OK) return r;
   hipLaunchKernelGGL(k_run_starts, dim3(g256), dim3(256), 0, s, flags, n, starts);
   if (hc_err r = check_launch("run starts"); r != HC_OK) return r;
+  if (counting) {
+    // kt / vt: distinct keys and their run lengths; flags + n: the number of runs
+    hipLaunchKernelGGL(k_run_lengths, dim3(g256), dim3(256), 0, s, kc, starts, flags + n, n, kt, vt);
+    if (hc_err r = check_launch("run lengths"); r != HC_OK) return r;
+    return dispatch_gw(G, W, [&](auto g, auto w) -> hc_err {
+      constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
+      auto k = k_insert_counts<GG, WW>;
+      const unsigned grid = grid_for(k, n, GG);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n / 8, GG, grid), kt, vt, flags + n);
+      return check_launch("insert counts");
+    });
+  }
   hipLaunchKernelGGL(k_heavy_list, dim3(g256), dim3(256), 0, s, starts, flags + n, n, heavy, nheavy);
   if (hc_err r = check_launch("heavy runs"); r != HC_OK) return r;
   return dispatch_w(W, [&](auto w) -> hc_err {
     constexpr int WW = decltype(w)::value;
+    auto kr = k_heavy_round<WW>;
+    const unsigned rgrid = block_grid(reinterpret_cast<const void*>(kr), ~0ull);
+    for (int round = 0; round < IROUNDS; ++round) {
+      hipLaunchKernelGGL(k_heavy_plan<WW>, dim3(1), dim3(GB), 0, s, t, kc, starts, heavy, nheavy, hs, round == 0);
+      if (hc_err r = check_launch("heavy plan"); r != HC_OK) return r;
+      WorkCtl ctl = work_for(0, 64, rgrid * (GB / 256));
+      hipLaunchKernelGGL(kr, dim3(rgrid), dim3(GB), 0, s, t, ctl, kc, vc, starts, heavy, nheavy, hs);
+      if (hc_err r = check_launch("heavy round"); r != HC_OK) return r;
+    }
     auto k = k_claim_runs<WW>;
     const unsigned grid = block_grid(reinterpret_cast<const void*>(k), ~0ull);
     WorkCtl ctl = work_for(0, 64, grid * (GB / 256));  // a launch slot (counters 0..2 reset by the kernel)
-    hipLaunchKernelGGL(k, dim3(grid), dim3(GB), 0, s, t, ctl, kc, vc, starts, flags + n, heavy, nheavy);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(GB), 0, s, t, ctl, kc, vc, starts, flags + n, heavy, nheavy, hs);
     return check_launch("claim runs");
   });
 }
@@ -444,30 +667,57 @@ hc_err launch_zero_u64(unsigned long long* p, uint32_t count, hipStream_t s) {
   return check_launch("zero");
 }
 
-hc_err launch_long_count(const TableView& t, uint32_t W, const uint32_t* keys, const uint64_t* list,
-                         const unsigned long long* nlong, uint64_t max_long, uint32_t budget, uint64_t* offsets,
-                         uint32_t* counts, hipStream_t s) {
-  return dispatch_w(W, [&](auto w) -> hc_err {
-    constexpr int WW = decltype(w)::value;
-    auto k = k_long_count<WW>;
-    const unsigned grid = block_grid(reinterpret_cast<const void*>(k), max_long);
-    WorkCtl ctl = work_for(0, 64, grid * (GB / 256));
-    hipLaunchKernelGGL(k, dim3(grid), dim3(GB), 0, s, t, ctl, keys, list, nlong, budget, offsets, counts);
-    return check_launch("long count");
-  });
+uint64_t long_workspace_bytes(uint64_t n, int mode) {
+  return 256 + align256((mode == 0 ? 8 : 16) * n) + align256(8 * n) + 4 * align256(4 * n) + 256;
 }
 
-hc_err launch_long_write(const TableView& t, uint32_t W, const uint32_t* keys, const uint64_t* list,
-                         const unsigned long long* nlong, uint64_t max_long, uint32_t budget, const uint64_t* offsets,
-                         uint32_t* out, hipStream_t s) {
-  return dispatch_w(W, [&](auto w) -> hc_err {
+LongState long_layout(void* ws, uint64_t n, int mode) {
+  char* p = (char*)ws;
+  LongState ls;
+  ls.nlong = (const unsigned long long*)p;
+  ls.nopen = (unsigned long long*)p + 1;  // QROUNDS_MAX + 1 words after the entry count
+  p += 256;
+  ls.entries = (uint64_t*)p; p += align256((mode == 0 ? 8 : 16) * n);
+  ls.base = (uint64_t*)p; p += align256(8 * n);
+  ls.flag = (uint32_t*)p; p += align256(4 * n);
+  ls.done = (uint32_t*)p; p += align256(4 * n);
+  ls.lists[0] = (uint32_t*)p; p += align256(4 * n);
+  ls.lists[1] = (uint32_t*)p;
+  return ls;
+}
+
+hc_err launch_long_queries(const TableView& t, uint32_t W, int mode, const uint32_t* keys, const LongState& ls,
+                           uint64_t n, uint32_t budget, uint64_t* offsets, uint32_t* counts, uint32_t* out,
+                           hipStream_t s) {
+  const unsigned ig = (unsigned)((n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024);
+  hipLaunchKernelGGL(k_long_init, dim3(ig ? ig : 1), dim3(256), 0, s, ls, budget);
+  if (hc_err r = check_launch("long init"); r != HC_OK) return r;
+  hc_err r = dispatch_w(W, [&](auto w) -> hc_err {
     constexpr int WW = decltype(w)::value;
-    auto k = k_long_write<WW>;
-    const unsigned grid = block_grid(reinterpret_cast<const void*>(k), max_long);
-    WorkCtl ctl = work_for(0, 64, grid * (GB / 256));
-    hipLaunchKernelGGL(k, dim3(grid), dim3(GB), 0, s, t, ctl, keys, list, nlong, budget, offsets, out);
-    return check_launch("long write");
+    auto body = [&](auto mc) -> hc_err {
+      constexpr int MODE = decltype(mc)::value;
+      auto kr = k_long_round<WW, MODE>;
+      const unsigned grid = block_grid(reinterpret_cast<const void*>(kr), ~0ull);
+      // rounds 0..R-1 give an entry (4^R - 1) / 3 segments in all: enough for the whole sequence
+      const uint64_t segw = GB * GB_SPL / WW, need = (t.P + segw - 1) / segw;
+      uint32_t rounds = 1;
+      for (uint64_t cover = 1; cover < need; cover = 4 * cover + 1) ++rounds;
+      if (rounds > (uint32_t)QROUNDS_MAX) return fail(HC_E_ARG, "sequence too long for the long-query rounds");
+      for (uint32_t round = 0; round < rounds; ++round) {
+        WorkCtl ctl = work_for(0, 64, grid * (GB / 256));
+        hipLaunchKernelGGL(kr, dim3(grid), dim3(GB), 0, s, t, ctl, keys, ls, round, offsets, out);
+        if (hc_err e = check_launch("long round"); e != HC_OK) return e;
+      }
+      return HC_OK;
+    };
+    return mode == 0 ? body(ic<0>{}) : body(ic<1>{});
   });
+  if (r != HC_OK) return r;
+  if (mode == 0 && counts != nullptr) {
+    hipLaunchKernelGGL(k_long_counts_out, dim3(ig ? ig : 1), dim3(256), 0, s, ls, offsets, counts);
+    return check_launch("long counts");
+  }
+  return HC_OK;
 }
 
 }  // namespace hc

@@ -13,14 +13,26 @@ constexpr uint64_t HEAVY_RUN = 2048;   // runs at least this long are claimed by
 constexpr uint32_t LONG_BUDGET = 64;   // windows a group scans before handing a query over
 
 uint64_t grouped_workspace_bytes(uint64_t n);
-hc_err launch_grouped_insert(const TableView& t, uint32_t W, const uint32_t* keys, const uint32_t* values, uint64_t n,
-                             void* ws, hipStream_t s);
+// kind: KIND_MULTI (pairs) or KIND_COUNT (keys; values unused); G: group of the counting insert.
+hc_err launch_grouped_insert(const TableView& t, int kind, uint32_t G, uint32_t W, const uint32_t* keys,
+                             const uint32_t* values, uint64_t n, void* ws, hipStream_t s);
 hc_err launch_zero_u64(unsigned long long* p, uint32_t count, hipStream_t s);
-hc_err launch_long_count(const TableView& t, uint32_t W, const uint32_t* keys, const uint64_t* list,
-                         const unsigned long long* nlong, uint64_t max_long, uint32_t budget, uint64_t* offsets,
-                         uint32_t* counts, hipStream_t s);
-hc_err launch_long_write(const TableView& t, uint32_t W, const uint32_t* keys, const uint64_t* list,
-                         const unsigned long long* nlong, uint64_t max_long, uint32_t budget, const uint64_t* offsets,
-                         uint32_t* out, hipStream_t s);
+
+// Queries handed over by the count (mode 0) or write (mode 1) pass after `budget`
+// windows, and the state of the rounds that finish them, all in one workspace.
+struct LongState {
+  const unsigned long long* nlong;  // entries handed over (word 0 of the workspace)
+  unsigned long long* nopen;        // open entries at the start of each round
+  uint64_t* entries;                // mode 0: query index; mode 1: (query index, values written)
+  uint64_t* base;                   // next window of the entry's sequence
+  uint32_t* flag;                   // 1 once the entry is finished
+  uint32_t* done;                   // segments of the current round finished
+  uint32_t* lists[2];               // open entries of the current and the next round
+};
+uint64_t long_workspace_bytes(uint64_t n, int mode);
+LongState long_layout(void* ws, uint64_t n, int mode);
+hc_err launch_long_queries(const TableView& t, uint32_t W, int mode, const uint32_t* keys, const LongState& ls,
+                           uint64_t n, uint32_t budget, uint64_t* offsets, uint32_t* counts, uint32_t* out,
+                           hipStream_t s);
 
 }  // namespace hc

@@ -18,6 +18,7 @@
 #include "hc_batch.hpp"
 #include "hc_device.hpp"
 #include "hc_group.hpp"
+#include "hc_stats.hpp"
 #include "hc_launch.hpp"
 #include "hc_sort.hpp"
 
@@ -39,107 +40,10 @@ struct hc_table_s {
   uint64_t tiles_cap;     // entries allocated in d_tiles
   void* d_ws;             // workspace of the multi-value passes (long-query lists, grouped insert)
   uint64_t ws_bytes;
+  bool owns_slots;        // false: caller-owned slot array (hc_create_in)
 };
 
 namespace hc {
-
-static thread_local std::string g_last_error;
-
-hc_err fail(hc_err e, const char* fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
-  va_end(ap);
-  g_last_error = buf;
-  return e;
-}
-
-static hc_err hip_fail(hipError_t e, const char* what) {
-  return fail(HC_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
-}
-
-hc_err check_launch(const char* what) {
-  const hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(e, what);
-  return HC_OK;
-}
-
-int device_cu_count() {
-  static int cached[64] = {0};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-  if (cached[dev] == 0) {
-    int cu = 0;
-    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) cu = 256;
-    cached[dev] = cu;
-  }
-  return cached[dev];
-}
-
-int blocks_per_cu_threads(const void* kernel, int threads) {
-  static std::mutex mu;
-  static std::unordered_map<const void*, int> cache;
-  std::lock_guard<std::mutex> lock(mu);
-  auto it = cache.find(kernel);
-  if (it != cache.end()) return it->second;
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess || nb <= 0) nb = 1;
-  cache.emplace(kernel, nb);
-  return nb;
-}
-
-int blocks_per_cu(const void* kernel) { return blocks_per_cu_threads(kernel, BLOCK); }
-
-// Launch-slot ring: per device, LAUNCH_SLOTS pairs of work counters, one pair per
-// launch in round-robin order.  A launch's last wavefront resets its pair, so a
-// pair is free again once its launch has finished; launches that run
-// concurrently on one device (at most LAUNCH_SLOTS of them) use distinct pairs.
-constexpr uint32_t LAUNCH_SLOTS = 1024;
-constexpr uint32_t SLOT_WORDS = 16;  // 128 bytes per pair: no two pairs share a cache line
-
-struct DeviceRing {
-  unsigned long long* d_ring = nullptr;
-  std::atomic<uint32_t> next{0};
-};
-static DeviceRing g_rings[64];
-static std::mutex g_ring_mu;
-
-static hc_err ensure_ring(int dev) {
-  if (dev < 0 || dev >= 64) return fail(HC_E_DEVICE, "device %d out of range", dev);
-  std::lock_guard<std::mutex> lock(g_ring_mu);
-  if (g_rings[dev].d_ring) return HC_OK;
-  unsigned long long* p = nullptr;
-  hipError_t e = hipMalloc((void**)&p, (size_t)LAUNCH_SLOTS * SLOT_WORDS * sizeof(unsigned long long));
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(HC_E_NOMEM, "hipMalloc of the launch-slot ring failed");
-  }
-  e = hipMemset(p, 0, (size_t)LAUNCH_SLOTS * SLOT_WORDS * sizeof(unsigned long long));
-  if (e == hipSuccess) e = hipDeviceSynchronize();
-  if (e != hipSuccess) {
-    (void)hipFree(p);
-    return hip_fail(e, "launch-slot ring init");
-  }
-  g_rings[dev].d_ring = p;
-  return HC_OK;
-}
-
-WorkCtl work_for(uint64_t n, int G, unsigned grid) {
-  int dev = 0;
-  (void)hipGetDevice(&dev);
-  DeviceRing& r = g_rings[dev];
-  const uint32_t slot = r.next.fetch_add(1, std::memory_order_relaxed) % LAUNCH_SLOTS;
-  WorkCtl c;
-  c.counters = r.d_ring + (size_t)slot * SLOT_WORDS;
-  const uint64_t gpw = 64 / G;  // groups per wavefront
-  const uint64_t waves = (uint64_t)grid * (BLOCK / 64);
-  uint64_t ch = (n + 2 * waves - 1) / (2 * waves);
-  if (ch < gpw) ch = gpw;
-  if (ch > 64 * gpw) ch = 64 * gpw;
-  c.chunk = (uint32_t)ch;
-  return c;
-}
 
 // ---- table fill ----------------------------------------------------------------
 
@@ -444,31 +348,45 @@ void hc_default_params(hc_params* p) {
   p->seed = 0x5EED0F0C0A5CAD1Eull;
 }
 
-hc_err hc_create(hc_table* out, uint32_t kind, uint64_t capacity, const hc_params* params) {
-  if (out == nullptr) return fail(HC_E_ARG, "out is NULL");
-  *out = nullptr;
-  hc_params p;
-  hc_default_params(&p);
-  if (params) p = *params;
-  if (kind > 2) return fail(HC_E_ARG, "unknown table kind %u", kind);
-  if (p.scheme > 2) return fail(HC_E_ARG, "unknown probing scheme %u", p.scheme);
-  if (!(p.window == 8 || p.window == 16 || p.window == 32 || p.window == 64))
-    return fail(HC_E_ARG, "window %u is not one of 8, 16, 32, 64", p.window);
-  if (!is_pow2(p.group) || p.group > 64) return fail(HC_E_ARG, "group size %u is not a power of two in [1, 64]", p.group);
-  if (p.reserved != 0) return fail(HC_E_ARG, "params.reserved must be 0");
+// Validated parameters and the rounded window count P (Sec. IV-B2 cycle-free rule).
+static hc_err table_geometry(uint64_t capacity, const hc_params* params, hc_params* p, uint64_t* P_out) {
+  hc_default_params(p);
+  if (params) *p = *params;
+  if (p->scheme > 2) return fail(HC_E_ARG, "unknown probing scheme %u", p->scheme);
+  if (!(p->window == 8 || p->window == 16 || p->window == 32 || p->window == 64))
+    return fail(HC_E_ARG, "window %u is not one of 8, 16, 32, 64", p->window);
+  if (!is_pow2(p->group) || p->group > 64)
+    return fail(HC_E_ARG, "group size %u is not a power of two in [1, 64]", p->group);
+  if (p->reserved != 0) return fail(HC_E_ARG, "params.reserved must be 0");
   if (capacity == 0) return fail(HC_E_ARG, "capacity must be positive");
   if (capacity > (1ull << 40)) return fail(HC_E_ARG, "capacity %llu too large", (unsigned long long)capacity);
-
-  uint64_t P = (capacity + p.window - 1) / p.window;
-  if (p.scheme == HC_QUADRATIC) {
+  uint64_t P = (capacity + p->window - 1) / p->window;
+  if (p->scheme == HC_QUADRATIC) {
     uint64_t q = 1;
     while (q < P) q <<= 1;
     P = q;
-  } else if (p.scheme == HC_DOUBLE && !is_pow2(P)) {
+  } else if (p->scheme == HC_DOUBLE && !is_pow2(P)) {
     while (!is_prime(P)) ++P;
   }
   if (P > (1ull << 31)) return fail(HC_E_ARG, "window count %llu exceeds 2^31", (unsigned long long)P);
+  *P_out = P;
+  return HC_OK;
+}
 
+static hc_err create_table(hc_table* out, uint32_t kind, uint64_t capacity, const hc_params* params,
+                           void* ext_slots, uint64_t ext_bytes) {
+  if (out == nullptr) return fail(HC_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (kind > 2) return fail(HC_E_ARG, "unknown table kind %u", kind);
+  hc_params p;
+  uint64_t P = 0;
+  if (hc_err r = table_geometry(capacity, params, &p, &P); r != HC_OK) return r;
+  if (ext_slots != nullptr) {
+    if ((reinterpret_cast<uintptr_t>(ext_slots) & 255) != 0) return fail(HC_E_ARG, "slot array is not 256-byte aligned");
+    if (ext_bytes < P * p.window * sizeof(uint64_t))
+      return fail(HC_E_ARG, "slot array holds %llu bytes, the table needs %llu", (unsigned long long)ext_bytes,
+                  (unsigned long long)(P * p.window * sizeof(uint64_t)));
+  }
   hc_table_s* t = new (std::nothrow) hc_table_s();
   if (!t) return fail(HC_E_NOMEM, "host allocation failed");
   if (hipGetDevice(&t->device) != hipSuccess) {
@@ -486,17 +404,21 @@ hc_err hc_create(hc_table* out, uint32_t kind, uint64_t capacity, const hc_param
   t->P = P;
   t->C = P * p.window;
   t->seed = p.seed;
-  hipError_t e = hipMalloc((void**)&t->slots, t->C * sizeof(uint64_t));
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    delete t;
-    return fail(HC_E_NOMEM, "hipMalloc of %llu slots failed: %s", (unsigned long long)P * p.window,
-                hipGetErrorString(e));
+  t->owns_slots = ext_slots == nullptr;
+  if (ext_slots != nullptr) {
+    t->slots = static_cast<uint64_t*>(ext_slots);
+  } else {
+    hipError_t e = hipMalloc((void**)&t->slots, t->C * sizeof(uint64_t));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      delete t;
+      return fail(HC_E_NOMEM, "hipMalloc of %llu slots failed: %s", (unsigned long long)t->C, hipGetErrorString(e));
+    }
   }
-  e = hipMalloc((void**)&t->d_size, 256);
+  hipError_t e = hipMalloc((void**)&t->d_size, 256);
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    (void)hipFree(t->slots);
+    if (t->owns_slots) (void)hipFree(t->slots);
     delete t;
     return fail(HC_E_NOMEM, "hipMalloc of the size counter failed");
   }
@@ -506,7 +428,7 @@ hc_err hc_create(hc_table* out, uint32_t kind, uint64_t capacity, const hc_param
     if (e != hipSuccess) r = hip_fail(e, "hc_create: synchronise");
   }
   if (r != HC_OK) {
-    (void)hipFree(t->slots);
+    if (t->owns_slots) (void)hipFree(t->slots);
     (void)hipFree(t->d_size);
     delete t;
     return r;
@@ -515,12 +437,34 @@ hc_err hc_create(hc_table* out, uint32_t kind, uint64_t capacity, const hc_param
   return HC_OK;
 }
 
+hc_err hc_create(hc_table* out, uint32_t kind, uint64_t capacity, const hc_params* params) {
+  return create_table(out, kind, capacity, params, nullptr, 0);
+}
+
+hc_err hc_create_in(hc_table* out, uint32_t kind, void* d_slots, uint64_t slot_bytes, uint64_t capacity,
+                    const hc_params* params) {
+  if (d_slots == nullptr) {
+    if (out) *out = nullptr;
+    return fail(HC_E_ARG, "slot array is NULL");
+  }
+  return create_table(out, kind, capacity, params, d_slots, slot_bytes);
+}
+
+hc_err hc_table_bytes(uint64_t capacity, const hc_params* params, uint64_t* h_out) {
+  if (h_out == nullptr) return fail(HC_E_ARG, "out is NULL");
+  hc_params p;
+  uint64_t P = 0;
+  if (hc_err r = table_geometry(capacity, params, &p, &P); r != HC_OK) return r;
+  *h_out = P * p.window * sizeof(uint64_t);
+  return HC_OK;
+}
+
 hc_err hc_destroy(hc_table t) {
   if (t == nullptr) return HC_OK;
   hc_err r = set_device(t);
   if (r != HC_OK) return r;
   hipError_t e = hipDeviceSynchronize();
-  if (t->slots) (void)hipFree(t->slots);
+  if (t->slots && t->owns_slots) (void)hipFree(t->slots);
   if (t->d_size) (void)hipFree(t->d_size);
   if (t->d_tiles) (void)hipFree(t->d_tiles);
   if (t->d_ws) (void)hipFree(t->d_ws);
@@ -615,16 +559,15 @@ hc_err hc_count_values(hc_table t, const uint32_t* d_keys, uint64_t n, uint32_t*
     t->tiles_cap = need;
   }
   if (n > 0) {
-    // queries still open after LONG_BUDGET windows are finished by the block-wide kernel
-    if ((r = ensure_ws(t, 256 + 8 * n)) != HC_OK) return r;
-    unsigned long long* nlong = (unsigned long long*)t->d_ws;
-    uint64_t* list = (uint64_t*)((char*)t->d_ws + 256);
-    if ((r = launch_zero_u64(nlong, 1, s)) != HC_OK) return r;
-    if ((r = launch_count_multi(view_of(t), g, t->window, d_keys, n, d_counts, d_offsets, nullptr, LONG_BUDGET, list,
-                                nlong, s)) != HC_OK)
+    // queries still open after LONG_BUDGET windows are finished by block-wide segment rounds
+    if ((r = ensure_ws(t, long_workspace_bytes(n, 0))) != HC_OK) return r;
+    const LongState ls = long_layout(t->d_ws, n, 0);
+    if ((r = launch_zero_u64((unsigned long long*)ls.nlong, 1, s)) != HC_OK) return r;
+    if ((r = launch_count_multi(view_of(t), g, t->window, d_keys, n, d_counts, d_offsets, nullptr, LONG_BUDGET,
+                                ls.entries, (unsigned long long*)ls.nlong, s)) != HC_OK)
       return r;
-    if ((r = launch_long_count(view_of(t), t->window, d_keys, list, nlong, n, LONG_BUDGET, d_offsets, d_counts, s)) !=
-        HC_OK)
+    if ((r = launch_long_queries(view_of(t), t->window, 0, d_keys, ls, n, LONG_BUDGET, d_offsets, d_counts, nullptr,
+                                 s)) != HC_OK)
       return r;
   }
   if ((r = exclusive_scan_inplace(d_offsets, n, t->d_tiles, s)) != HC_OK) return r;
@@ -647,26 +590,33 @@ hc_err hc_retrieve_all(hc_table t, const uint32_t* d_keys, uint64_t n, const uin
   if (d_keys == nullptr || d_offsets == nullptr) return fail(HC_E_ARG, "keys or offsets is NULL");
   if ((r = set_device(t)) != HC_OK) return r;
   hipStream_t s = (hipStream_t)stream;
-  if ((r = ensure_ws(t, 256 + 16 * n)) != HC_OK) return r;
-  unsigned long long* nlong = (unsigned long long*)t->d_ws;
-  uint64_t* list = (uint64_t*)((char*)t->d_ws + 256);
-  if ((r = launch_zero_u64(nlong, 1, s)) != HC_OK) return r;
-  if ((r = launch_write_multi(view_of(t), g, t->window, d_keys, n, d_offsets, d_values_out, LONG_BUDGET, list, nlong,
-                              s)) != HC_OK)
+  if ((r = ensure_ws(t, long_workspace_bytes(n, 1))) != HC_OK) return r;
+  const LongState ls = long_layout(t->d_ws, n, 1);
+  if ((r = launch_zero_u64((unsigned long long*)ls.nlong, 1, s)) != HC_OK) return r;
+  if ((r = launch_write_multi(view_of(t), g, t->window, d_keys, n, d_offsets, d_values_out, LONG_BUDGET, ls.entries,
+                              (unsigned long long*)ls.nlong, s)) != HC_OK)
     return r;
-  return launch_long_write(view_of(t), t->window, d_keys, list, nlong, n, LONG_BUDGET, d_offsets, d_values_out, s);
+  // the write rounds only read the offsets
+  return launch_long_queries(view_of(t), t->window, 1, d_keys, ls, n, LONG_BUDGET, const_cast<uint64_t*>(d_offsets),
+                             nullptr, d_values_out, s);
 }
 
 hc_err hc_insert_grouped(hc_table t, const uint32_t* d_keys, const uint32_t* d_values, uint64_t n, void* stream) {
   hc_err r = check_table(t);
   if (r != HC_OK) return r;
-  if (t->kind != HC_MULTI_VALUE) return fail(HC_E_KIND, "grouped insert needs a multi-value table");
+  if (t->kind == HC_SINGLE_VALUE) return fail(HC_E_KIND, "grouped insert needs a multi-value or counting table");
   if (n == 0) return HC_OK;
-  if (d_keys == nullptr || d_values == nullptr) return fail(HC_E_ARG, "keys or values is NULL");
+  if (d_keys == nullptr) return fail(HC_E_ARG, "keys is NULL");
+  if (t->kind == HC_COUNTING) {
+    if (d_values != nullptr) return fail(HC_E_ARG, "counting tables take no values");
+  } else if (d_values == nullptr) {
+    return fail(HC_E_ARG, "values is NULL");
+  }
   if (n > 0xFFFFFFFFull) return fail(HC_E_ARG, "grouped insert takes at most 2^32-1 pairs");
   if ((r = set_device(t)) != HC_OK) return r;
   if ((r = ensure_ws(t, grouped_workspace_bytes(n))) != HC_OK) return r;
-  return launch_grouped_insert(view_of(t), t->window, d_keys, d_values, n, t->d_ws, (hipStream_t)stream);
+  return launch_grouped_insert(view_of(t), (int)t->kind, t->group, t->window, d_keys, d_values, n, t->d_ws,
+                               (hipStream_t)stream);
 }
 
 hc_err hc_size(hc_table t, uint64_t* h_out, void* stream) {
@@ -711,6 +661,30 @@ hc_err hc_info(hc_table t, hc_table_info* h_out) {
   h_out->capacity = t->C;
   h_out->seed = t->seed;
   h_out->d_slots = t->slots;
+  return HC_OK;
+}
+
+hc_err hc_stats(hc_table t, hc_table_stats* h_out, void* stream) {
+  hc_err r = check_table(t);
+  if (r != HC_OK) return r;
+  if (h_out == nullptr) return fail(HC_E_ARG, "out is NULL");
+  static_assert(HC_PROBE_BUCKETS == STATS_BUCKETS, "histogram width");
+  static_assert(sizeof(hc_table_stats) == (5 + STATS_BUCKETS) * sizeof(uint64_t), "stats layout");
+  if ((r = set_device(t)) != HC_OK) return r;
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long* d = nullptr;
+  hipError_t e = hipMalloc((void**)&d, sizeof(hc_table_stats));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(HC_E_NOMEM, "hipMalloc of the statistics failed");
+  }
+  r = launch_zero_u64(d, 5 + STATS_BUCKETS, s);
+  if (r == HC_OK) r = launch_stats(view_of(t), t->window, d, s);
+  if (e == hipSuccess && r == HC_OK) e = hipMemcpyAsync(h_out, d, sizeof(hc_table_stats), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && r == HC_OK) e = hipStreamSynchronize(s);
+  (void)hipFree(d);
+  if (r != HC_OK) return r;
+  if (e != hipSuccess) return hip_fail(e, "hc_stats");
   return HC_OK;
 }
 
@@ -851,6 +825,6 @@ const char* hc_error_string(hc_err err) {
   return "unknown error";
 }
 
-const char* hc_last_error(void) { return g_last_error.c_str(); }
+const char* hc_last_error(void) { return hc::last_error_text(); }
 
 }  // extern "C"

@@ -245,7 +245,7 @@ struct InsertUnique {
 
   __device__ __forceinline__ void load(uint64_t op) {
     k_nx = keys[op];
-    v_nx = (KIND == KIND_COUNT) ? 1u : values[op];
+    v_nx = (KIND == KIND_COUNT && values == nullptr) ? 1u : values[op];  // counting: increment
   }
   __device__ __forceinline__ void begin(uint64_t op) {
     i = op;
@@ -259,7 +259,7 @@ struct InsertUnique {
     return true;
   }
   __device__ __forceinline__ void update(uint64_t idx) {  // the key is present at idx
-    if constexpr (KIND == KIND_COUNT) atomicAdd((unsigned long long*)&t.slots[idx], 1ull << 32);
+    if constexpr (KIND == KIND_COUNT) atomicAdd((unsigned long long*)&t.slots[idx], (unsigned long long)v << 32);
     else atomicExch((unsigned long long*)&t.slots[idx], (unsigned long long)make_slot(k, v));
   }
   // CAS a reusable slot: 1 claimed, 2 found the key there (updated), 3 lost to another key.

@@ -13,6 +13,10 @@ namespace hc {
 
 // Record a message for hc_last_error() (thread-local) and return `e`.
 hc_err fail(hc_err e, const char* fmt, ...);
+hc_err hip_fail(hipError_t e, const char* what);  // HC_E_DEVICE with the HIP error text
+const char* last_error_text();
+// Allocate the device's launch-slot ring (once per device; synchronises the first time).
+hc_err ensure_ring(int dev);
 
 // Number of compute units of the current device (cached per device).
 int device_cu_count();

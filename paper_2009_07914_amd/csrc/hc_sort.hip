@@ -49,7 +49,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
     uint32_t k = 0, v = 0, d = 0;
     if (valid) {
       k = keys_in[i];
-      v = vals_in[i];
+      if (vals_in != nullptr) v = vals_in[i];
       d = (k >> shift) & 255u;
     }
     uint64_t same = __ballot(valid);
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint32_t* __res
       uint64_t pos = run[d] + rank_w;
       for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
       keys_out[pos] = k;
-      vals_out[pos] = v;
+      if (vals_out != nullptr) vals_out[pos] = v;
     }
     __syncthreads();
     uint64_t add = 0;

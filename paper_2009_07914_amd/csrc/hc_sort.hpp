@@ -15,7 +15,7 @@ hc_err exclusive_scan_inplace(uint64_t* a, uint64_t n, uint64_t* tiles, hipStrea
 
 // Stable sort of (keys, vals) by key, in place (keys_tmp / vals_tmp: n entries
 // each; hist: sort_pairs_workspace(n) entries; scan_tiles: scan_tiles_needed of
-// the histogram size).
+// the histogram size).  vals and vals_tmp both NULL: keys only.
 uint64_t sort_pairs_workspace(uint64_t n);
 hc_err sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp, uint64_t n,
                   uint64_t* hist, uint64_t* scan_tiles, hipStream_t stream);

@@ -64,3 +64,32 @@ def test_no_oracle_in_product_path():
                 assert "import oracle" not in src and "from oracle" not in src and "liboracle" not in src, f
     deps = subprocess.run(["objdump", "-p", LIB], capture_output=True, text=True).stdout
     assert "liboracle" not in deps
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("scheme", ctypes.c_uint32), ("window", ctypes.c_uint32), ("group", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+
+
+def test_table_bytes_and_create_in_arguments(lib):
+    import oracle
+    lib.hc_default_params.argtypes = [ctypes.POINTER(_Params)]
+    lib.hc_table_bytes.argtypes = [ctypes.c_uint64, ctypes.POINTER(_Params), ctypes.POINTER(ctypes.c_uint64)]
+    lib.hc_create_in.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint64,
+                                 ctypes.c_uint64, ctypes.POINTER(_Params)]
+    p = _Params()
+    lib.hc_default_params(ctypes.byref(p))
+    out = ctypes.c_uint64()
+    for scheme in (0, 1, 2):
+        for w in (8, 16, 32, 64):
+            for cap in (1, 1000, 4096, 100003):
+                p.scheme, p.window = scheme, w
+                assert lib.hc_table_bytes(cap, ctypes.byref(p), ctypes.byref(out)) == 0
+                assert out.value == 8 * w * oracle.round_windows(cap, w, scheme)
+    p.scheme, p.window = 2, 16
+    lib.hc_table_bytes(1000, ctypes.byref(p), ctypes.byref(out))
+    h = ctypes.c_void_p()
+    assert lib.hc_create_in(ctypes.byref(h), 0, None, 1 << 20, 1000, ctypes.byref(p)) == 1         # NULL array
+    assert lib.hc_create_in(ctypes.byref(h), 0, 0x10010, 1 << 20, 1000, ctypes.byref(p)) == 1      # misaligned
+    assert lib.hc_create_in(ctypes.byref(h), 0, 0x10000, out.value - 8, 1000, ctypes.byref(p)) == 1  # too small
+    assert h.value is None

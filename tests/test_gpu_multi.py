@@ -171,9 +171,93 @@ def test_grouped_insert_reserved_and_overfull(hc):
     check_layout(t2, oracle.MULTI)
 
 
-def test_grouped_insert_needs_multi_value(hc):
+def test_grouped_insert_needs_multi_value_or_counting(hc):
     t = hc.Table("single", 1024)
     k = d(np.arange(1, 10, dtype=np.uint32))
     with pytest.raises(hc.HcError) as e:
         hc.hc_insert_grouped(t.handle, k, k)
     assert e.value.code == hc.E_KIND
+    c = hc.Table("counting", 1024)
+    with pytest.raises(hc.HcError) as e:
+        hc.hc_insert_grouped(c.handle, k, k)
+    assert e.value.code == hc.E_ARG
+
+
+@pytest.mark.parametrize("group", [1, 4, 16])
+@pytest.mark.parametrize("scheme,window", [("linear", 16), ("quadratic", 8), ("double", 16), ("double", 64)])
+def test_grouped_counting_matches_oracle(hc, group, scheme, window):
+    """Zipf(1.1) keys (2^18 over 2^12): one insert per distinct key with its multiplicity as increment;
+    then per-key inserts, erases and a second grouped batch on top, against the oracle's per-key counts."""
+    w = gen.multi_value_zipf_workload(1 << 18, 1 << 12, 1.1, 61 + window + group)
+    t = hc.Table("counting", 1 << 14, scheme=scheme, window=window, group=group)
+    orc = oracle.OracleTable(oracle.COUNT, t.capacity)
+    hc.hc_insert_grouped(t.handle, d(w["keys"]))
+    orc.insert(w["keys"])
+    assert t.size() == orc.size()
+    v, f = t.retrieve(d(w["queries"]))
+    vo, fo = orc.retrieve(w["queries"])
+    assert np.array_equal(h(v), vo) and np.array_equal(h(f), fo)
+    check_layout(t, oracle.COUNT)
+    t.insert(d(w["keys"][:3000]), None)  # per-key path on top: counts go on from the grouped ones
+    orc.insert(w["keys"][:3000])
+    er = w["queries"][::7]
+    assert np.array_equal(h(t.erase(d(er), status=True)), orc.erase(er))
+    hc.hc_insert_grouped(t.handle, d(w["keys"][: 1 << 16]))  # present keys add, erased ones reuse tombstones
+    orc.insert(w["keys"][: 1 << 16])
+    assert t.size() == orc.size()
+    v, f = t.retrieve(d(w["queries"]))
+    vo, fo = orc.retrieve(w["queries"])
+    assert np.array_equal(h(v), vo) and np.array_equal(h(f), fo)
+    check_layout(t, oracle.COUNT)
+
+
+def test_grouped_counting_reserved_and_full(hc):
+    keys = np.concatenate([np.full(70000, 9, np.uint32), np.array([0, 0xFFFFFFFF] * 5, np.uint32),
+                           np.repeat(np.arange(100, 2100, dtype=np.uint32), 3)])
+    keys = keys[gen.permutation(5, keys.size).astype(np.int64)]
+    t = hc.Table("counting", 1 << 13, scheme="double", window=16)
+    hc.hc_insert_grouped(t.handle, d(keys))
+    orc = oracle.OracleTable(oracle.COUNT, t.capacity)
+    orc.insert(keys)
+    q = np.concatenate([np.array([9, 0, 0xFFFFFFFF, 5], np.uint32), np.arange(100, 2100, dtype=np.uint32)])
+    v, f = t.retrieve(d(q))
+    vo, fo = orc.retrieve(q)
+    assert np.array_equal(h(v), vo) and np.array_equal(h(f), fo)
+    assert int(h(v)[0]) == 70000 and t.size() == 2001
+    # full: 3000 distinct keys into 1024 slots -> 1024 stored, each with its exact multiplicity
+    k2 = np.repeat(np.arange(1, 3001, dtype=np.uint32), 4)
+    k2 = k2[gen.permutation(6, k2.size).astype(np.int64)]
+    t2 = hc.Table("counting", 1024, scheme="linear", window=16)
+    hc.hc_insert_grouped(t2.handle, d(k2))
+    assert t2.size() == 1024
+    slots = h(t2.dump_slots())
+    assert np.all(slots != 0) and np.all((slots >> 32) == 4)
+    assert np.unique(slots & 0xFFFFFFFF).size == 1024
+    check_layout(t2, oracle.COUNT)
+
+
+@pytest.mark.parametrize("window", [16, 64])
+def test_grouped_many_rounds_against_grouping(hc, window):
+    """A hot key with ~430 K copies (2^21 pairs, Zipf(1.1) over 2^8 keys, table 2^22 slots): heavy runs go
+    through several claim rounds and the long queries through several segment rounds.  The per-pair
+    oracle is quadratic here, so counts and segments are checked against a sort of the input pairs."""
+    w = gen.multi_value_zipf_workload(1 << 21, 1 << 8, 1.1, 97)
+    t = hc.Table("multi", 1 << 22, scheme="double", window=window, group=8)
+    hc.hc_insert_grouped(t.handle, d(w["keys"]), d(w["values"]))
+    assert t.size() == w["keys"].size
+    q = w["queries"]
+    counts, offsets, total = t.count_values(d(q))
+    u, c = np.unique(w["keys"], return_counts=True)
+    expect = np.zeros(q.size, np.int64)
+    pos = np.searchsorted(u, q)
+    expect[pos < u.size] = np.where(u[np.minimum(pos, u.size - 1)] == q, c[np.minimum(pos, u.size - 1)], 0)[pos < u.size]
+    assert np.array_equal(h(counts).astype(np.int64), expect) and total == w["keys"].size
+    assert int(expect.max()) > 400000
+    _, vals = t.retrieve_all(d(q))
+    vals, off = h(vals), h(offsets).astype(np.int64)
+    order = np.lexsort((w["values"], w["keys"]))
+    sk, sv = w["keys"][order], w["values"][order]
+    for i in range(q.size):
+        lo, hi = np.searchsorted(sk, q[i], "left"), np.searchsorted(sk, q[i], "right")
+        assert np.array_equal(np.sort(vals[off[i]:off[i + 1]]), sv[lo:hi])
+    check_layout(t, oracle.MULTI)

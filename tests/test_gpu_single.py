@@ -219,3 +219,73 @@ def test_same_kind_overlap_on_two_streams(hc):
     assert np.array_equal(h(outa), va) and np.array_equal(h(outb), vb)
     assert h(fa).all() and h(fb).all()
     check_layout(t, oracle.SINGLE)
+
+
+def _walk_probe_lengths(slots, P, W, scheme, seed):
+    """Windows a retrieval visits to reach each live slot, by walking the oracle's window sequence."""
+    out = []
+    for i in np.nonzero((slots & 0xFFFFFFFF) != 0)[0]:
+        k = int(slots[i] & 0xFFFFFFFF)
+        if k == 0xFFFFFFFF:
+            continue
+        seq = oracle.window_sequence(k, P, P, scheme, seed)
+        out.append(int(np.nonzero(seq == i // W)[0][0]) + 1)
+    return np.array(out, dtype=np.int64)
+
+
+@pytest.mark.parametrize("scheme,cap", [("linear", 3000), ("quadratic", 3000), ("double", 4096), ("double", 3000)])
+@pytest.mark.parametrize("window", [8, 16, 64])
+def test_stats_full_scan(hc, scheme, cap, window):
+    """hc_stats against a walk of every live key's window sequence (power-of-two and prime P)."""
+    t = hc.Table("single", cap, scheme=scheme, window=window, group=4, seed=11)
+    w = gen.single_value_workload(t.capacity, 0.93, 12)
+    t.insert(d(w["keys"]), d(w["values"]))
+    t.erase(d(w["keys"][::9]))
+    st = t.stats()
+    slots = h(t.dump_slots())
+    probes = _walk_probe_lengths(slots, t.windows, t.window, t.scheme, t.seed)
+    assert st["live"] == probes.size == t.size()
+    assert st["tombstones"] == int(((slots & 0xFFFFFFFF) == 0xFFFFFFFF).sum())
+    assert st["empty"] == t.capacity - st["live"] - st["tombstones"]
+    assert st["max_probe"] == probes.max() and st["probe_sum"] == probes.sum()
+    hist = np.bincount(np.minimum(np.floor(np.log2(probes)).astype(np.int64), hc.PROBE_BUCKETS - 1),
+                       minlength=hc.PROBE_BUCKETS)
+    assert st["probe_hist"] == hist.tolist()
+
+
+def test_stats_multi_value_long_sequences(hc):
+    """A multi-value table with a key of ~20 K copies: probe lengths in the hundreds of windows."""
+    w = gen.multi_value_zipf_workload(1 << 16, 1 << 6, 1.1, 14)
+    for scheme in ("linear", "quadratic", "double"):
+        t = hc.Table("multi", 1 << 17, scheme=scheme, window=16)
+        hc.hc_insert_grouped(t.handle, d(w["keys"]), d(w["values"]))
+        st = t.stats()
+        rc, lay = oracle.check_layout(h(t.dump_slots()), t.windows, t.window, t.scheme, t.seed, oracle.MULTI)
+        assert rc == 0
+        assert st["live"] == lay["live"] == w["keys"].size
+        assert st["max_probe"] == lay["max_windows"] and st["probe_sum"] == lay["sum_windows"]
+        assert st["max_probe"] > 500 and sum(st["probe_hist"]) == st["live"]
+
+
+def test_create_in_caller_memory(hc):
+    p = hc.hc_default_params()
+    p.scheme, p.window = hc.SCHEMES["double"], 16
+    nbytes = hc.hc_table_bytes(5000, p)
+    assert nbytes == 8 * 16 * oracle.round_windows(5000, 16, hc.SCHEMES["double"])
+    mem = torch.full((nbytes // 8 + 3,), 0x1234, dtype=torch.uint64, device="cuda")
+    t = hc.Table("single", 5000, scheme="double", window=16, slots=mem)
+    assert t.capacity * 8 == nbytes and int((mem[: t.capacity] != 0).sum()) == 0  # cleared
+    assert int(mem[-1]) == 0x1234  # nothing written past the table
+    w = gen.single_value_workload(t.capacity, 0.9, 15)
+    orc = oracle.OracleTable(oracle.SINGLE, t.capacity)
+    assert np.array_equal(h(t.insert(d(w["keys"]), d(w["values"]), status=True)), orc.insert(w["keys"], w["values"]))
+    v, f = t.retrieve(d(w["queries"]))
+    vo, fo = orc.retrieve(w["queries"])
+    assert np.array_equal(h(v), vo) and np.array_equal(h(f), fo)
+    assert torch.equal(t.dump_slots(), mem[: t.capacity])  # the table lives in the caller's tensor
+    t.close()
+    assert int((mem[: t.capacity] != 0).sum()) == w["keys"].size  # still allocated and intact after destroy
+    small = torch.zeros(nbytes // 8 - 1, dtype=torch.uint64, device="cuda")
+    with pytest.raises(hc.HcError) as e:
+        hc.Table("single", 5000, scheme="double", window=16, slots=small)
+    assert e.value.code == hc.E_ARG
