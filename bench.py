@@ -38,9 +38,11 @@ KERNEL_NAMES = {"insert": "k_insert_unique", "retrieve": "k_retrieve"}
 def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="single", choices=["single", "batched", "serving", "multi"],
+    ap.add_argument("--workload", default="single", choices=["single", "batched", "serving", "multi", "sweep"],
                     help="single: the 2^28-slot table (default); batched: 256 tables in one launch; "
-                         "serving: Poisson request stream on 16 resident tables")
+                         "serving: Poisson request stream on 16 resident tables; multi: counting and "
+                         "multi-value tables; sweep: load x scheme x group size on the 2^28-slot table")
+    ap.add_argument("--loads", default="0.5,0.8,0.9,0.95,0.99", help="sweep: load factors")
     ap.add_argument("--requests", type=int, default=1500)
     ap.add_argument("--max-log2-request", type=int, default=24)
     ap.add_argument("--zipf", action="store_true", help="serving: Zipf(1.1) keys instead of uniform")
@@ -117,6 +119,8 @@ def main():
         return bench_batched(args)
     if args.workload == "serving":
         return bench_serving(args)
+    if args.workload == "sweep":
+        return bench_sweep(args)
     if args.workload == "multi":
         return bench_multi(args)
     import numpy as np
@@ -494,6 +498,93 @@ def bench_multi(args):
                                "skewed multi-value: Zipf(1.1) over 2^22 keys, grouped insert",
                    "capacity": cap, "pairs": n},
         "modes": res,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_sweep(args):
+    """Single-value table of 2^log2 slots at each load: insert all keys, then retrieve them plus as many absent
+    ones (50/50), for every probing scheme and group size at W = 16, and W = 32 / 64 for groups of 32 and 64.
+    Each cell is checked: size = n, n queries found, and the values of a sample of present queries."""
+    import numpy as np
+    import torch
+
+    lib = os.path.join(ROOT, "paper_2009_07914_amd", "libhc.so")
+    if not os.path.exists(lib):
+        import __graft_entry__
+        __graft_entry__.build()
+    import gen
+    import paper_2009_07914_amd as hc
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    s = torch.cuda.current_stream()
+    cap = 1 << args.log2_capacity
+    cells = [(sc, 16, g) for sc in ("double", "quadratic", "linear") for g in (1, 2, 4, 8, 16, 32, 64)]
+    cells += [(sc, w, g) for sc in ("double", "quadratic", "linear") for w in (32, 64) for g in (32, 64)]
+    rows = []
+    for load in [float(x) for x in args.loads.split(",")]:
+        w = gen.single_value_workload(cap, load, gen.SEED_BASE + 1)
+        n = w["n"]
+        keys = torch.from_numpy(w["keys"]).to(dev)
+        vals = torch.from_numpy(w["values"]).to(dev)
+        q = torch.from_numpy(w["queries"]).to(dev)
+        vout = torch.empty(q.numel(), dtype=torch.uint32, device=dev)
+        fout = torch.empty(q.numel(), dtype=torch.uint8, device=dev)
+        samp = np.linspace(0, q.numel() - 1, 1 << 16).astype(np.int64)
+        src = w["query_src"][samp].astype(np.int64)
+        exp_v = np.where(src < n, w["values"][np.minimum(src, n - 1)], 0).astype(np.uint32)
+        exp_f = (src < n).astype(np.uint8)
+        samp_t = torch.from_numpy(samp).to(dev)
+        reps = 2 if load < 0.95 else 1
+        tables = {}
+        for scheme, W, G in cells:
+            if (scheme, W) not in tables:
+                tables.clear()
+                torch.cuda.empty_cache()
+                tables[(scheme, W)] = hc.Table("single", cap, scheme=scheme, window=W, group=4, device=dev)
+            t = tables[(scheme, W)]
+            ins, ret = [], []
+            for rep in range(1 + reps):
+                t.clear()
+                e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+                e[0].record(s)
+                hc.hc_insert(t.handle, keys, vals, None, G, s)
+                e[1].record(s)
+                hc.hc_retrieve(t.handle, q, vout, fout, G, s)
+                e[2].record(s)
+                torch.cuda.synchronize()
+                if rep:
+                    ins.append(e[0].elapsed_time(e[1]))
+                    ret.append(e[1].elapsed_time(e[2]))
+            ok = (t.size() == n and int(fout.sum(dtype=torch.int64).item()) == n
+                  and np.array_equal(vout[samp_t].cpu().numpy(), exp_v)
+                  and np.array_equal(fout[samp_t].cpu().numpy(), exp_f))
+            ti, tr = statistics.mean(ins), statistics.mean(ret)
+            row = {"load": load, "scheme": scheme, "W": W, "G": G, "insert_ms": round(ti, 3),
+                   "retrieve_ms": round(tr, 3), "insert_gops": round(n / ti / 1e6, 3),
+                   "retrieve_gops": round(q.numel() / tr / 1e6, 3), "ok": ok}
+            rows.append(row)
+            print("# " + json.dumps(row), flush=True)
+            assert ok, f"sweep cell failed its check: {row}"
+        tables.clear()
+        del keys, vals, q, vout, fout, w
+        torch.cuda.empty_cache()
+    best = {}
+    for r in rows:
+        for kind in ("insert", "retrieve"):
+            k = f"{r['load']}/{kind}"
+            if k not in best or r[f"{kind}_gops"] > best[k][f"{kind}_gops"]:
+                best[k] = r
+    out = {
+        "metric": "G inserts/s and G retrievals/s per (load, scheme, W, group size)", "value": None,
+        "unit": "G ops/s", "n_gpus": 1, "steps": 2, "warmup": 1, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"single-value table, 2^{args.log2_capacity} slots, uniform distinct uint32 keys, "
+                               "loads " + args.loads + "; retrieve 50% present / 50% absent"},
+        "best": {k: {"scheme": v["scheme"], "W": v["W"], "G": v["G"],
+                     "gops": v[k.split("/")[1] + "_gops"]} for k, v in best.items()},
+        "cells": rows,
     }
     print(json.dumps(out), flush=True)
 

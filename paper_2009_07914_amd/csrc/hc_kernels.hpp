@@ -225,6 +225,122 @@ __device__ __forceinline__ void drive_range(uint64_t begin, uint64_t end, Op& op
 }
 
 // ------------------------------------------------------------------------------
+// drive() with the outputs staged per wavefront.  The elements a wavefront hands
+// out are numbered in hand-out order (seq); a group finishing element `seq`
+// puts its result into the wavefront's LDS ring at seq % RB.  Whenever the 64
+// oldest ring entries are all finished, the wavefront writes them back together,
+// 64 lanes to 64 output elements: the elements of one chunk are consecutive, so
+// these are whole cache lines, written once, instead of lines completed piecemeal
+// over many iterations (and evicted half-written in between).  Before handing out
+// an element that would overrun the ring, the oldest 64 entries are written back
+// as they are; a result that arrives after its entry was written back (seq below
+// the flush mark) goes straight to memory.
+// ------------------------------------------------------------------------------
+template <int RB>
+struct OutRing {
+  uint64_t idx[RB];   // element index of each entry
+  uint32_t val[RB];
+  uint8_t found[RB];
+  uint8_t done[RB];   // 0 pending, 1 finished, 2 no element
+};
+
+template <int G, int RB, typename Op>
+__device__ __forceinline__ void drive_staged(uint64_t n, const WorkCtl& ctl, Op& op, OutRing<RB>& ring) {
+  static_assert(RB % 64 == 0 && RB >= 128, "ring of whole 64-entry blocks, at least two");
+  const GroupCtx<G>& g = op.ln.g;
+  const uint32_t chunk = ctl.chunk;
+  uint64_t cur = 0;
+  uint32_t used = chunk;
+  uint64_t hcount = 0;  // elements handed out (wavefront-uniform)
+  uint64_t flushed = 0; // ring entries below this are written back (wavefront-uniform, multiple of 64)
+#pragma unroll
+  for (int j = 0; j < RB / 64; ++j) ring.done[j * 64 + g.lane] = 0;
+  auto write_back = [&](bool only_full) -> bool {  // the block [flushed, flushed + 64)
+    const uint64_t e = flushed + g.lane;
+    const uint32_t r = (uint32_t)(e % RB);
+    const bool handed = e < hcount;
+    const uint8_t st = handed ? ring.done[r] : (uint8_t)0;
+    if (only_full && (flushed + 64 > hcount || __ballot(st != 0) != ~0ull)) return false;
+    if (st == 1) {
+      const uint64_t i = ring.idx[r];
+      if (op.values_out != nullptr) op.values_out[i] = ring.val[r];
+      if (op.found_out != nullptr) op.found_out[i] = ring.found[r];
+    }
+    if (handed) ring.done[r] = 0;
+    flushed += 64;
+    op.flushed = flushed;
+    return true;
+  };
+  auto reserve = [&](bool want_group, uint64_t& seq_out) -> uint64_t {
+    const uint64_t want = __ballot(want_group && g.glane == 0);
+    if (want == 0) return ~0ull;
+    const uint32_t cnt = (uint32_t)__popcll(want);
+    const uint32_t rank = (uint32_t)__popcll(want & ((1ull << g.lane) - 1ull));
+    while (hcount + cnt > flushed + RB) write_back(false);  // make room: at most once (cnt <= 64)
+    const uint32_t room = chunk - used;
+    uint64_t nxt = cur;
+    if (cnt > room) {
+      unsigned long long c = 0;
+      if (g.lane == 0) c = atomicAdd(ctl.counters, 1ull);
+      nxt = ((uint64_t)__shfl((uint32_t)(c >> 32), 0, 64) << 32) | __shfl((uint32_t)c, 0, 64);
+    }
+    const uint64_t idx = (rank < room) ? cur * chunk + used + rank : nxt * chunk + (rank - room);
+    if (cnt > room) {
+      cur = nxt;
+      used = cnt - room;
+    } else {
+      used += cnt;
+    }
+    if ((want >> g.lane) & 1ull) {
+      const uint32_t r = (uint32_t)((hcount + rank) % RB);
+      ring.idx[r] = idx;
+      ring.done[r] = idx < n ? 0 : 2;
+    }
+    seq_out = g.bcast64(hcount + rank, 0);
+    hcount += cnt;
+    return g.bcast64(idx, 0);
+  };
+  op.ring_val = ring.val;
+  op.ring_found = ring.found;
+  op.ring_done = ring.done;
+  op.flushed = 0;
+  uint64_t seq_next = 0;
+  uint64_t i_next = reserve(true, seq_next);
+  bool has_next = i_next < n;
+  if (has_next) op.load(i_next);
+  bool active = false;
+  for (;;) {
+    const bool start = !active && has_next;
+    if (start) {
+      op.seq = seq_next;
+      op.begin(i_next);
+      active = true;
+    }
+    uint64_t sq = 0;
+    const uint64_t r = reserve(start, sq);
+    if (start) {
+      i_next = r;
+      seq_next = sq;
+      has_next = r < n;
+      if (has_next) op.load(r);
+    }
+    if (__ballot(active) == 0) break;
+    if (active && op.step()) active = false;
+    while (write_back(true)) {
+    }
+  }
+  while (flushed < hcount) write_back(false);
+  op.end();
+  if (g.lane == 0) {
+    const unsigned long long waves = (unsigned long long)gridDim.x * (BLOCK / 64);
+    if (atomicAdd(ctl.counters + 1, 1ull) == waves - 1) {
+      atomicExch(ctl.counters, 0ull);
+      atomicExch(ctl.counters + 1, 0ull);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------
 // Single-value and counting insert (Sec. IV-B2 steps 1-7; Sec. IV-B3).
 // ------------------------------------------------------------------------------
 template <int G, int W, int KIND>
@@ -420,6 +536,12 @@ struct Retrieve {
   uint64_t i = 0;
   uint32_t k = 0, lbase = 0, k_nx = 0;
   Seq s{};
+  // output staging (drive_staged); ring_val == nullptr: results go straight to memory
+  uint32_t* ring_val = nullptr;
+  uint8_t* ring_found = nullptr;
+  uint8_t* ring_done = nullptr;
+  uint64_t seq = 0, flushed = 0;
+  static constexpr uint32_t RING = 128;
 
   __device__ __forceinline__ void load(uint64_t op) { k_nx = keys[op]; }
   __device__ __forceinline__ void begin(uint64_t op) {
@@ -427,11 +549,19 @@ struct Retrieve {
     k = k_nx;
     ln.start(t, k, s, lbase);
   }
-  __device__ __forceinline__ bool miss() {
-    if (ln.g.glane == 0) {
-      if (values_out != nullptr) values_out[i] = 0u;
-      if (found_out != nullptr) found_out[i] = 0;
+  __device__ __forceinline__ void emit(uint32_t v, uint8_t f) {
+    if (ring_val != nullptr && seq >= flushed) {
+      const uint32_t r = (uint32_t)(seq % RING);
+      ring_val[r] = v;
+      ring_found[r] = f;
+      ring_done[r] = 1;
+    } else {
+      if (values_out != nullptr) values_out[i] = v;
+      if (found_out != nullptr) found_out[i] = f;
     }
+  }
+  __device__ __forceinline__ bool miss() {
+    if (ln.g.glane == 0) emit(0u, 0);
     return true;
   }
   __device__ __forceinline__ bool step() {
@@ -441,11 +571,7 @@ struct Retrieve {
     load_step<G, W>(t, ln, s, lbase, k, win);
     const uint64_t b_match = g.bits(win.match != 0);
     if (b_match) {
-      if (g.glane == (uint32_t)ffs64(b_match)) {
-        const uint64_t w = pick_lowest<SPL>(win.word, win.match);
-        if (values_out != nullptr) values_out[i] = slot_value(w);
-        if (found_out != nullptr) found_out[i] = 1;
-      }
+      if (g.glane == (uint32_t)ffs64(b_match)) emit(slot_value(pick_lowest<SPL>(win.word, win.match)), 1);
       return true;
     }
     if (g.bits(win.empty != 0) || ln.exhausted(t, lbase)) return miss();
@@ -459,12 +585,14 @@ template <int G, int W>
 __global__ __launch_bounds__(BLOCK) void k_retrieve(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys, uint64_t n,
                                                     uint32_t* __restrict__ values_out,
                                                     uint8_t* __restrict__ found_out) {
-  Retrieve<G, W> op;
+  using R = Retrieve<G, W>;
+  __shared__ OutRing<R::RING> rings[BLOCK / 64];
+  R op;
   op.t = t;
   op.keys = keys;
   op.values_out = values_out;
   op.found_out = found_out;
-  drive<G>(n, ctl, op);
+  drive_staged<G, R::RING>(n, ctl, op, rings[threadIdx.x >> 6]);
 }
 
 // ------------------------------------------------------------------------------
