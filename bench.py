@@ -558,7 +558,7 @@ def bench_sweep(args):
                     ins.append(e[0].elapsed_time(e[1]))
                     ret.append(e[1].elapsed_time(e[2]))
             ok = (t.size() == n and int(fout.sum(dtype=torch.int64).item()) == n
-                  and np.array_equal(vout[samp_t].cpu().numpy(), exp_v)
+                  and np.array_equal(vout.view(torch.int32)[samp_t].cpu().numpy().view(np.uint32), exp_v)
                   and np.array_equal(fout[samp_t].cpu().numpy(), exp_f))
             ti, tr = statistics.mean(ins), statistics.mean(ret)
             row = {"load": load, "scheme": scheme, "W": W, "G": G, "insert_ms": round(ti, 3),
