@@ -8,7 +8,9 @@
 // stored multiset and the same layout invariant (no empty position before any
 // stored position of a key) while removing the quadratic term:
 //   * grouped insert: pairs are sorted by key; each run of one key claims its m
-//     slots in one pass along the sequence (a wavefront per run).  A run of at
+//     slots in one pass along the sequence: a group of the bulk driver per short
+//     run (16 runs in flight per wavefront at g = 4), a wavefront per run of
+//     SMALL_RUN or more pairs.  A run of at
 //     least HEAVY_RUN pairs is first spread over the whole grid in claim rounds:
 //     a round hands out, in segments of one block step, exactly as many further
 //     windows of the key's sequence as the values still to be placed could fill
@@ -38,7 +40,8 @@ namespace hc {
 constexpr int GB = 1024;              // threads per block of the run / long-query kernels
 constexpr int GB_WAVES = GB / 64;
 constexpr int GB_SPL = 4;             // slots per lane in block mode
-constexpr uint32_t RUN_GRAB = 16;     // light runs taken per wavefront atomic
+constexpr uint32_t RUN_GRAB = 4;      // medium runs taken per wavefront atomic
+constexpr uint64_t SMALL_RUN = 128;   // shorter runs are claimed by one group of the bulk driver
 constexpr int IROUNDS = 10;           // claim rounds of heavy runs
 constexpr uint64_t ROUND_MIN = 4ull * GB * GB_SPL;  // heavy runs with fewer values left finish in one block
 constexpr int QROUNDS_MAX = 16;       // long-query rounds; round r gives each open query 4^r segments
@@ -91,7 +94,7 @@ __device__ __forceinline__ uint32_t block_scan(uint32_t x, uint32_t* total, uint
 // Claim m slots for key k with a whole block, walking its sequence from window l0
 // (every reusable slot before l0 is already taken); the values are vals[0..m).
 template <int W>
-__device__ void claim_run_block(const TableView& t, uint32_t k, const uint32_t* __restrict__ vals, uint64_t m,
+__device__ __forceinline__ void claim_run_block(const TableView& t, uint32_t k, const uint32_t* __restrict__ vals, uint64_t m,
                                 uint64_t l0, uint64_t& added, uint32_t* lds) {
   constexpr uint32_t WPS_B = GB * GB_SPL / W;  // sequence windows per step
   const KeySeq q = key_seq(t, k);
@@ -149,10 +152,41 @@ __device__ void claim_run_block(const TableView& t, uint32_t k, const uint32_t* 
   if (threadIdx.x == 0) added += claimed;
 }
 
-// Claim m slots for key k with one wavefront (one slot per lane).
+// Runs still short of their pairs after LONG_BUDGET windows (their sequence runs
+// through a long stretch of full windows): the walk is handed over to find
+// rounds, which look for the first window with a reusable slot in parallel.
+struct WalkState {
+  unsigned long long* nwalk;  // entries handed over
+  unsigned long long* nopen;  // open entries at the start of each find round
+  uint64_t* entry;            // run index (low 32 bits) and pairs placed (high 32 bits)
+  uint64_t* base;             // next window of the sequence to look at
+  unsigned long long* found;  // first window with a reusable slot (~0: none yet)
+  uint32_t* done;             // segments of the current round finished
+  uint32_t* lists[2];
+  uint64_t cap;               // list capacity (nwalk may count past it)
+};
+
+// Where the claim kernels append hand-overs.
+struct WalkOut {
+  unsigned long long* nwalk;
+  uint64_t* entry;
+  uint64_t* base;
+  uint64_t cap;
+};
+
+// Returns false when the list is full: the caller then walks on itself.
+__device__ __forceinline__ bool walk_hand_over(const WalkOut& wo, uint64_t r, uint64_t claimed, uint64_t next_l) {
+  const unsigned long long e = atomicAdd(wo.nwalk, 1ull);
+  if (e >= wo.cap) return false;
+  wo.entry[e] = r | (claimed << 32);
+  wo.base[e] = next_l;
+  return true;
+}
+
+// Claim m slots for key k (run r) with one wavefront (one slot per lane).
 template <int W>
-__device__ void claim_run_wave(const TableView& t, uint32_t k, const uint32_t* __restrict__ vals, uint64_t m,
-                               uint64_t& added) {
+__device__ __forceinline__ void claim_run_wave(const TableView& t, uint32_t k, const uint32_t* __restrict__ vals, uint64_t m,
+                               uint64_t r, const WalkOut& ws, uint64_t& added) {
   constexpr uint32_t WPS_W = 64 / W;  // W <= 64
   const uint32_t lane = __lane_id();
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -160,6 +194,11 @@ __device__ void claim_run_wave(const TableView& t, uint32_t k, const uint32_t* _
   const uint32_t widx = lane / W, j = lane % W;
   uint64_t claimed = 0;
   for (uint64_t lbase = 0; claimed < m && lbase < t.P; lbase += WPS_W) {
+    if (lbase == LONG_BUDGET) {  // hand the rest of the walk over (once)
+      uint32_t ok = 0;
+      if (lane == 0) ok = walk_hand_over(ws, r, claimed, lbase);
+      if (__shfl(ok, 0, 64)) break;
+    }
     const uint64_t l = lbase + widx;
     uint64_t idx = 0, word = 0;
     bool reuse = false;
@@ -194,9 +233,13 @@ __device__ void claim_run_wave(const TableView& t, uint32_t k, const uint32_t* _
 }
 
 __global__ __launch_bounds__(256) void k_run_flags(const uint32_t* __restrict__ keys, uint64_t n,
-                                                   uint64_t* __restrict__ flags, unsigned long long* nheavy) {
+                                                   uint64_t* __restrict__ flags, unsigned long long* nlists) {
   const uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i == 0) *nheavy = 0ull;
+  if (i == 0) {  // heavy list, medium list and hand-over list lengths
+    nlists[0] = 0ull;
+    nlists[1] = 0ull;
+    nlists[2] = 0ull;
+  }
   if (i < n) flags[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1ull : 0ull;
 }
 
@@ -208,12 +251,221 @@ __global__ __launch_bounds__(256) void k_run_starts(const uint64_t* __restrict__
   if (i == n) starts[scan[n]] = n;
 }
 
-__global__ __launch_bounds__(256) void k_heavy_list(const uint64_t* __restrict__ starts,
-                                                    const uint64_t* __restrict__ nruns, uint64_t max_runs,
-                                                    uint32_t* __restrict__ heavy, unsigned long long* nheavy) {
+// Lists of heavy runs (>= HEAVY_RUN pairs) and medium runs (SMALL_RUN .. HEAVY_RUN - 1).
+__global__ __launch_bounds__(256) void k_run_lists(const uint64_t* __restrict__ starts,
+                                                   const uint64_t* __restrict__ nruns, uint64_t max_runs,
+                                                   uint32_t* __restrict__ heavy, unsigned long long* nheavy,
+                                                   uint32_t* __restrict__ medium, unsigned long long* nmedium) {
   const uint64_t r = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  if (r < max_runs && r < *nruns && starts[r + 1] - starts[r] >= HEAVY_RUN)
-    heavy[atomicAdd(nheavy, 1ull)] = (uint32_t)r;
+  if (r < max_runs && r < *nruns) {
+    const uint64_t m = starts[r + 1] - starts[r];
+    if (m >= HEAVY_RUN) heavy[atomicAdd(nheavy, 1ull)] = (uint32_t)r;
+    else if (m >= SMALL_RUN) medium[atomicAdd(nmedium, 1ull)] = (uint32_t)r;
+  }
+}
+
+// Short runs: one group per run in the bulk driver.  Each step claims, in
+// position order, the first (pairs still to place) reusable slots of the step's
+// window(s); claims lost to other keys are replaced by later reusable slots of
+// the same window before the sequence moves on, so no empty slot is left before
+// a stored pair.
+template <int G, int W>
+struct ClaimRun {
+  using L = Lane<G, W>;
+  static constexpr int SPL = L::SPL;
+  L ln;
+  TableView t;
+  const uint32_t* __restrict__ keys;
+  const uint32_t* __restrict__ vals;
+  const uint64_t* __restrict__ starts;
+  WalkOut ws;
+  uint64_t st = 0, m = 0, claimed = 0, st_nx = 0, en_nx = 0, run = 0;
+  uint32_t k = 0, lbase = 0, k_nx = 0;
+  Seq s{};
+  long long added = 0;
+
+  __device__ __forceinline__ void load(uint64_t r) {
+    st_nx = starts[r];
+    en_nx = starts[r + 1];
+    k_nx = keys[st_nx];
+  }
+  __device__ __forceinline__ void begin(uint64_t r) {
+    run = r;
+    st = st_nx;
+    m = en_nx - st_nx;
+    k = k_nx;
+    claimed = 0;
+    ln.start(t, k, s, lbase);
+  }
+  __device__ __forceinline__ bool step() {
+    const auto& g = ln.g;
+    if (m >= SMALL_RUN || reserved_key(k)) return true;
+    Window<SPL> win;
+    load_step<G, W>(t, ln, s, lbase, k, win);
+    MaskT<SPL> reuse = win.empty | win.tomb;
+    for (;;) {  // attempted slots leave `reuse`, so every round shrinks it
+      const uint32_t c = popcount(reuse);
+      if (g.sum(c) == 0) break;
+      const uint64_t need = m - claimed;
+      uint32_t rank = g.exclusive_scan(c);
+      MaskT<SPL> tried = 0, succ = 0;
+#pragma unroll
+      for (int j = 0; j < SPL; ++j) {
+        if ((reuse >> j) & 1) {
+          if (rank < need) {
+            const uint64_t expect = ((win.empty >> j) & 1) ? WORD_EMPTY : WORD_TOMB;
+            const uint64_t r = atomicCAS((unsigned long long*)&t.slots[win.first + j], (unsigned long long)expect,
+                                         (unsigned long long)make_slot(k, 0u));
+            tried |= (MaskT<SPL>)1 << j;
+            if (r == expect) succ |= (MaskT<SPL>)1 << j;
+          }
+          ++rank;
+        }
+      }
+      reuse &= ~tried;
+      const uint32_t sc = popcount(succ);
+      uint32_t vr = g.exclusive_scan(sc);
+      const uint32_t stot = g.sum(sc);
+#pragma unroll
+      for (int j = 0; j < SPL; ++j) {
+        if ((succ >> j) & 1) {
+          atomicExch((unsigned long long*)&t.slots[win.first + j],
+                     (unsigned long long)make_slot(k, vals[st + claimed + vr]));
+          ++vr;
+        }
+      }
+      claimed += stot;
+      if (g.glane == 0) added += stot;
+      if (claimed >= m) return true;
+    }
+    if (ln.exhausted(t, lbase)) return true;  // table full: the rest of the run is dropped
+    if (lbase + L::WPS == LONG_BUDGET) {      // a long walk: handed over to the find rounds (once)
+      uint32_t ok = 0;
+      if (g.glane == 0) ok = walk_hand_over(ws, run, claimed, lbase + L::WPS);
+      if (g.bcast(ok, 0)) return true;
+    }
+    ln.advance(t, s, lbase);
+    return false;
+  }
+  __device__ __forceinline__ void end() { wave_add_to(t.size, added); }
+};
+
+template <int G, int W>
+__global__ __launch_bounds__(BLOCK) void k_claim_small(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys,
+                                                       const uint32_t* __restrict__ vals,
+                                                       const uint64_t* __restrict__ starts,
+                                                       const uint64_t* __restrict__ nruns, WalkOut ws) {
+  ClaimRun<G, W> op;
+  op.t = t;
+  op.keys = keys;
+  op.vals = vals;
+  op.starts = starts;
+  op.ws = ws;
+  drive<G>(*nruns, ctl, op);
+}
+
+// One find round: every open entry gets 4^round segments of SEGW windows from its
+// next window on; found[e] becomes the first window of the segments holding a
+// reusable slot.  Windows found full stay full (claims only fill slots), so the
+// claim can start there.
+template <int W>
+__global__ __launch_bounds__(GB) void k_walk_round(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys,
+                                                   const uint64_t* __restrict__ starts, WalkState ws,
+                                                   uint32_t round) {
+  constexpr uint64_t SEGW = GB * GB_SPL / W;
+  __shared__ unsigned long long s_item, s_min;
+  const uint64_t S = 1ull << (2 * round);
+  const uint32_t* lin = ws.lists[round & 1];
+  uint32_t* lout = ws.lists[(round + 1) & 1];
+  const uint64_t N = ws.nopen[round] * S;
+  const uint32_t widx = (threadIdx.x * GB_SPL) / W, j0 = (threadIdx.x * GB_SPL) % W;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      s_item = atomicAdd(ctl.counters, 1ull);
+      s_min = ~0ull;
+    }
+    __syncthreads();
+    const uint64_t item = s_item;
+    if (item >= N) break;
+    const uint32_t e = lin[item / S];
+    const uint64_t seg = item % S;
+    const uint32_t r = (uint32_t)ws.entry[e];
+    const uint32_t k = keys[starts[r]];
+    const KeySeq q = key_seq(t, k);
+    const uint64_t l = ws.base[e] + seg * SEGW + widx;
+    if (l < t.P && l < ws.base[e] + (seg + 1) * SEGW) {
+      uint64_t word[GB_SPL];
+      load_slots<GB_SPL>(t.slots, (uint64_t)window_at(t, q, l) * W + j0, word);
+      bool reusable = false;
+#pragma unroll
+      for (int jj = 0; jj < GB_SPL; ++jj) {
+        const uint32_t kk = slot_key(word[jj]);
+        reusable |= kk == KEY_EMPTY || kk == KEY_TOMB;
+      }
+      if (reusable) atomicMin(&s_min, (unsigned long long)l);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (s_min != ~0ull) atomicMin(ws.found + e, s_min);
+      if (atomicAdd(ws.done + e, 1u) == (uint32_t)(S - 1)) {  // every segment of this round is done
+        const uint64_t nb = ws.base[e] + S * SEGW;
+        if (atomicMin(ws.found + e, ~0ull) == ~0ull && nb < t.P) {
+          atomicExch((unsigned long long*)(ws.base + e), (unsigned long long)nb);
+          atomicExch(ws.done + e, 0u);
+          lout[atomicAdd(ws.nopen + round + 1, 1ull)] = e;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (atomicAdd(ctl.counters + 1, 1ull) == (unsigned long long)gridDim.x - 1) {
+      atomicExch(ctl.counters, 0ull);
+      atomicExch(ctl.counters + 1, 0ull);
+    }
+  }
+}
+
+// Round state of every handed-over walk; round 0 lists all of them.
+__global__ __launch_bounds__(256) void k_walk_init(WalkState ws) {
+  const uint64_t L = *ws.nwalk < ws.cap ? *ws.nwalk : ws.cap;
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  for (uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x; e < L; e += stride) {
+    ws.found[e] = ~0ull;
+    ws.done[e] = 0u;
+    ws.lists[0][e] = (uint32_t)e;
+  }
+  if (blockIdx.x == 0 && threadIdx.x <= QROUNDS_MAX) ws.nopen[threadIdx.x] = threadIdx.x == 0 ? L : 0ull;
+}
+
+// The handed-over runs: one block each claims the rest from the window found.
+template <int W>
+__global__ __launch_bounds__(GB) void k_walk_claim(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys,
+                                                   const uint32_t* __restrict__ vals,
+                                                   const uint64_t* __restrict__ starts, WalkState ws) {
+  __shared__ uint32_t lds[GB_WAVES];
+  __shared__ unsigned long long s_item;
+  const uint64_t L = *ws.nwalk < ws.cap ? *ws.nwalk : ws.cap;
+  uint64_t added = 0;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(ctl.counters, 1ull);
+    __syncthreads();
+    const uint64_t e = s_item;
+    __syncthreads();
+    if (e >= L) break;
+    const uint64_t r = (uint32_t)ws.entry[e], claimed = ws.entry[e] >> 32;
+    const uint64_t st = starts[r], m = starts[r + 1] - st, f = ws.found[e];
+    if (f != ~0ull)  // else no reusable slot left anywhere on the sequence: the rest is dropped
+      claim_run_block<W>(t, keys[st], vals + st + claimed, m - claimed, f, added, lds);
+  }
+  __syncthreads();
+  wave_add_to(t.size, (long long)added);
+  if (threadIdx.x == 0) {
+    if (atomicAdd(ctl.counters + 1, 1ull) == (unsigned long long)gridDim.x - 1) {
+      atomicExch(ctl.counters, 0ull);
+      atomicExch(ctl.counters + 1, 0ull);
+    }
+  }
 }
 
 // Per heavy run: next sequence window of the current round, windows in it, values placed.
@@ -356,10 +608,12 @@ __global__ __launch_bounds__(GB) void k_claim_runs(TableView t, WorkCtl ctl, con
                                                    const uint64_t* __restrict__ starts,
                                                    const uint64_t* __restrict__ nruns,
                                                    const uint32_t* __restrict__ heavy,
-                                                   const unsigned long long* __restrict__ nheavy, HeavyState hs) {
+                                                   const unsigned long long* __restrict__ nheavy, HeavyState hs,
+                                                   const uint32_t* __restrict__ medium,
+                                                   const unsigned long long* __restrict__ nmedium, WalkOut ws) {
   __shared__ uint32_t lds[GB_WAVES];
   __shared__ unsigned long long s_item;
-  const uint64_t R = *nruns, H = *nheavy;
+  const uint64_t M = *nmedium, H = *nheavy;
   uint64_t added = 0;
   for (;;) {  // what the rounds left of each heavy run, one block each
     if (threadIdx.x == 0) s_item = atomicAdd(ctl.counters, 1ull);
@@ -374,16 +628,16 @@ __global__ __launch_bounds__(GB) void k_claim_runs(TableView t, WorkCtl ctl, con
       claim_run_block<W>(t, k, vals + st + used, m - used, hs.pos[h] + hs.nw[h], added, lds);
   }
   const uint32_t lane = __lane_id();
-  for (;;) {  // light runs, one wavefront each, RUN_GRAB runs per atomic
+  for (;;) {  // medium runs, one wavefront each, RUN_GRAB runs per atomic
     unsigned long long c = 0;
     if (lane == 0) c = atomicAdd(ctl.counters + 2, 1ull);
     c = __builtin_amdgcn_readfirstlane((uint32_t)c);
-    const uint64_t r0 = (uint64_t)c * RUN_GRAB;
-    if (r0 >= R) break;
-    for (uint64_t r = r0; r < r0 + RUN_GRAB && r < R; ++r) {
-      const uint64_t st = starts[r], m = starts[r + 1] - st;
+    const uint64_t i0 = (uint64_t)c * RUN_GRAB;
+    if (i0 >= M) break;
+    for (uint64_t i = i0; i < i0 + RUN_GRAB && i < M; ++i) {
+      const uint64_t r = medium[i], st = starts[r], m = starts[r + 1] - st;
       const uint32_t k = keys[st];
-      if (m < HEAVY_RUN && !reserved_key(k)) claim_run_wave<W>(t, k, vals + st, m, added);
+      if (!reserved_key(k)) claim_run_wave<W>(t, k, vals + st, m, r, ws, added);
     }
   }
   __syncthreads();
@@ -587,19 +841,33 @@ static unsigned block_grid(const void* kernel, uint64_t items) {
 
 static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 
+// Entries of the hand-over list: runs whose walk outlasts LONG_BUDGET windows are
+// rare; past this many, groups walk on themselves.
+static uint64_t walk_capacity(uint64_t n) { return n / 16 + 1024; }
+
+// Windows covered by rounds 0..R-1 of 4^r segments: enough rounds for a whole sequence.
+static uint32_t rounds_to_cover(uint64_t P, uint64_t segw) {
+  const uint64_t need = (P + segw - 1) / segw;
+  uint32_t rounds = 1;
+  for (uint64_t cover = 1; cover < need; cover = 4 * cover + 1) ++rounds;
+  return rounds;
+}
+
 uint64_t grouped_workspace_bytes(uint64_t n) {
   const uint64_t hist = sort_pairs_workspace(n);
   const uint64_t scan_n = (hist > n + 1 ? hist : n + 1);
   const uint64_t hmax = n / HEAVY_RUN + 1;
+  const uint64_t mmax = n / SMALL_RUN + 1, wmax = walk_capacity(n);
   return 4 * align256(4 * n) + align256(8 * hist) + align256(8 * scan_tiles_needed(scan_n)) + align256(8 * (n + 1)) +
-         align256(8 * (n + 2)) + align256(4 * hmax) + 256 + 3 * align256(8 * hmax) + align256(8 * (hmax + 1)) + 256;
+         align256(8 * (n + 2)) + align256(4 * hmax) + align256(4 * mmax) + 256 + 3 * align256(8 * hmax) +
+         align256(8 * (hmax + 1)) + 3 * align256(8 * wmax) + 3 * align256(4 * wmax) + 256;
 }
 
 hc_err launch_grouped_insert(const TableView& t, int kind, uint32_t G, uint32_t W, const uint32_t* keys,
-                             const uint32_t* values, uint64_t n, void* ws, hipStream_t s) {
+                             const uint32_t* values, uint64_t n, void* work, hipStream_t s) {
   if (n == 0) return HC_OK;
   const bool counting = kind == KIND_COUNT;
-  char* p = (char*)ws;
+  char* p = (char*)work;
   uint32_t* kc = (uint32_t*)p; p += align256(4 * n);
   uint32_t* vc = (uint32_t*)p; p += align256(4 * n);
   uint32_t* kt = (uint32_t*)p; p += align256(4 * n);
@@ -612,7 +880,21 @@ hc_err launch_grouped_insert(const TableView& t, int kind, uint32_t G, uint32_t 
   uint64_t* starts = (uint64_t*)p; p += align256(8 * (n + 2));
   const uint64_t hmax = n / HEAVY_RUN + 1;
   uint32_t* heavy = (uint32_t*)p; p += align256(4 * hmax);
-  unsigned long long* nheavy = (unsigned long long*)p; p += 256;
+  uint32_t* medium = (uint32_t*)p; p += align256(4 * (n / SMALL_RUN + 1));
+  unsigned long long* nheavy = (unsigned long long*)p;  // nheavy, nmedium, nwalk, nopen[QROUNDS_MAX + 1]
+  unsigned long long* nmedium = nheavy + 1;
+  p += 256;
+  WalkState wk;
+  wk.nwalk = nheavy + 2;
+  wk.nopen = nheavy + 3;
+  wk.cap = walk_capacity(n);
+  wk.entry = (uint64_t*)p; p += align256(8 * wk.cap);
+  wk.base = (uint64_t*)p; p += align256(8 * wk.cap);
+  wk.found = (unsigned long long*)p; p += align256(8 * wk.cap);
+  wk.done = (uint32_t*)p; p += align256(4 * wk.cap);
+  wk.lists[0] = (uint32_t*)p; p += align256(4 * wk.cap);
+  wk.lists[1] = (uint32_t*)p; p += align256(4 * wk.cap);
+  const WalkOut wo{wk.nwalk, wk.entry, wk.base, wk.cap};
   HeavyState hs;
   hs.pos = (uint64_t*)p; p += align256(8 * hmax);
   hs.nw = (uint64_t*)p; p += align256(8 * hmax);
@@ -641,9 +923,9 @@ hc_err launch_grouped_insert(const TableView& t, int kind, uint32_t G, uint32_t 
       return check_launch("insert counts");
     });
   }
-  hipLaunchKernelGGL(k_heavy_list, dim3(g256), dim3(256), 0, s, starts, flags + n, n, heavy, nheavy);
-  if (hc_err r = check_launch("heavy runs"); r != HC_OK) return r;
-  return dispatch_w(W, [&](auto w) -> hc_err {
+  hipLaunchKernelGGL(k_run_lists, dim3(g256), dim3(256), 0, s, starts, flags + n, n, heavy, nheavy, medium, nmedium);
+  if (hc_err r = check_launch("run lists"); r != HC_OK) return r;
+  hc_err r = dispatch_w(W, [&](auto w) -> hc_err {
     constexpr int WW = decltype(w)::value;
     auto kr = k_heavy_round<WW>;
     const unsigned rgrid = block_grid(reinterpret_cast<const void*>(kr), ~0ull);
@@ -657,8 +939,39 @@ hc_err launch_grouped_insert(const TableView& t, int kind, uint32_t G, uint32_t 
     auto k = k_claim_runs<WW>;
     const unsigned grid = block_grid(reinterpret_cast<const void*>(k), ~0ull);
     WorkCtl ctl = work_for(0, 64, grid * (GB / 256));  // a launch slot (counters 0..2 reset by the kernel)
-    hipLaunchKernelGGL(k, dim3(grid), dim3(GB), 0, s, t, ctl, kc, vc, starts, flags + n, heavy, nheavy, hs);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(GB), 0, s, t, ctl, kc, vc, starts, flags + n, heavy, nheavy, hs, medium,
+                       nmedium, wo);
     return check_launch("claim runs");
+  });
+  if (r != HC_OK) return r;
+  r = dispatch_gw(G, W, [&](auto g, auto w) -> hc_err {
+    constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
+    auto k = k_claim_small<GG, WW>;
+    const unsigned grid = grid_for(k, n, GG);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n / 8, GG, grid), kc, vc, starts, flags + n, wo);
+    return check_launch("claim short runs");
+  });
+  if (r != HC_OK) return r;
+  // long walks: find rounds, then one block per run from the first window with room
+  const unsigned ig = (unsigned)((wk.cap + 255) / 256 < 1024 ? (wk.cap + 255) / 256 : 1024);
+  hipLaunchKernelGGL(k_walk_init, dim3(ig), dim3(256), 0, s, wk);
+  if (hc_err e2 = check_launch("walk init"); e2 != HC_OK) return e2;
+  return dispatch_w(W, [&](auto w) -> hc_err {
+    constexpr int WW = decltype(w)::value;
+    auto kr = k_walk_round<WW>;
+    const unsigned grid = block_grid(reinterpret_cast<const void*>(kr), ~0ull);
+    const uint32_t rounds = rounds_to_cover(t.P, GB * GB_SPL / WW);
+    if (rounds > (uint32_t)QROUNDS_MAX) return fail(HC_E_ARG, "sequence too long for the find rounds");
+    for (uint32_t round = 0; round < rounds; ++round) {
+      WorkCtl ctl = work_for(0, 64, grid * (GB / 256));
+      hipLaunchKernelGGL(kr, dim3(grid), dim3(GB), 0, s, t, ctl, kc, starts, wk, round);
+      if (hc_err e2 = check_launch("walk round"); e2 != HC_OK) return e2;
+    }
+    auto kc2 = k_walk_claim<WW>;
+    const unsigned cgrid = block_grid(reinterpret_cast<const void*>(kc2), ~0ull);
+    WorkCtl ctl = work_for(0, 64, cgrid * (GB / 256));
+    hipLaunchKernelGGL(kc2, dim3(cgrid), dim3(GB), 0, s, t, ctl, kc, vc, starts, wk);
+    return check_launch("walk claim");
   });
 }
 
@@ -699,9 +1012,7 @@ hc_err launch_long_queries(const TableView& t, uint32_t W, int mode, const uint3
       auto kr = k_long_round<WW, MODE>;
       const unsigned grid = block_grid(reinterpret_cast<const void*>(kr), ~0ull);
       // rounds 0..R-1 give an entry (4^R - 1) / 3 segments in all: enough for the whole sequence
-      const uint64_t segw = GB * GB_SPL / WW, need = (t.P + segw - 1) / segw;
-      uint32_t rounds = 1;
-      for (uint64_t cover = 1; cover < need; cover = 4 * cover + 1) ++rounds;
+      const uint32_t rounds = rounds_to_cover(t.P, GB * GB_SPL / WW);
       if (rounds > (uint32_t)QROUNDS_MAX) return fail(HC_E_ARG, "sequence too long for the long-query rounds");
       for (uint32_t round = 0; round < rounds; ++round) {
         WorkCtl ctl = work_for(0, 64, grid * (GB / 256));
