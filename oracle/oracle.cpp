@@ -305,41 +305,61 @@ void orc_window_sequence(uint32_t k, uint64_t count, uint64_t P, int scheme, uin
  */
 int orc_check_layout(const uint64_t* slots, uint64_t P, uint32_t W, int scheme, uint64_t seed, int kind,
                      uint64_t* stats) {
+  // The offending slot reported is the lowest-indexed one; at one slot the
+  // encoding is checked first, then uniqueness, then the position.
+  uint64_t bad = ~0ull;
+  int code = 0;
+  auto note = [&](uint64_t i, int c) {
+    if (i < bad || (i == bad && c < code)) { bad = i; code = c; }
+  };
   uint64_t live_n = 0, tombs = 0, maxw = 0, sumw = 0;
-  stats[4] = ~0ull;
-  std::unordered_set<uint32_t> seen;
+  std::unordered_map<uint32_t, std::vector<uint64_t>> copies;  // slots of each stored key
   const uint64_t C = P * W;
   for (uint64_t i = 0; i < C; ++i) {
     const uint32_t k = (uint32_t)slots[i];
     const uint32_t v = (uint32_t)(slots[i] >> 32);
-    if (k == KEY_EMPTY) { if (v != 0) { stats[4] = i; return 1; } continue; }
-    if (k == KEY_TOMB) { if (v != 0) { stats[4] = i; return 1; } ++tombs; continue; }
+    if (k == KEY_EMPTY) { if (v != 0) note(i, 1); continue; }
+    if (k == KEY_TOMB) { if (v != 0) note(i, 1); ++tombs; continue; }
     ++live_n;
-    if (kind != KIND_MULTI) {
-      if (!seen.insert(k).second) { stats[4] = i; return 3; }
-    }
-    const uint64_t target_w = i / W, target_j = i % W;
-    bool reached = false;
-    for (uint64_t l = 0; l < P; ++l) {
+    std::vector<uint64_t>& c = copies[k];
+    if (kind != KIND_MULTI && !c.empty()) { note(i, 3); continue; }
+    c.push_back(i);
+  }
+  // Each key's sequence is walked once, up to its last stored slot.  A stored
+  // slot is out of place if an empty slot comes before it in the sequence
+  // (windows in sequence order, slots in index order inside a window), or if
+  // the sequence never reaches its window.
+  for (auto& kv : copies) {
+    const uint32_t k = kv.first;
+    std::unordered_map<uint64_t, std::vector<uint64_t>> in_window;
+    for (uint64_t i : kv.second) in_window[i / W].push_back(i);
+    uint64_t remaining = kv.second.size();
+    bool empty_before = false;  // an empty slot in an earlier window of the sequence
+    for (uint64_t l = 0; l < P && remaining > 0; ++l) {
       const uint64_t w = orc_window_at(k, l, P, scheme, seed);
-      const uint64_t jmax = (w == target_w) ? target_j : W;
-      for (uint64_t j = 0; j < jmax; ++j) {
-        if (slots[w * W + j] == 0) { stats[4] = i; return 2; }
+      auto it = in_window.find(w);
+      if (it != in_window.end()) {
+        for (uint64_t i : it->second) {
+          bool behind_empty = empty_before;
+          for (uint64_t j = w * W; j < i && !behind_empty; ++j) behind_empty = slots[j] == 0;
+          if (behind_empty) note(i, 2);
+          maxw = std::max<uint64_t>(maxw, l + 1);
+          sumw += l + 1;
+          --remaining;
+        }
+        in_window.erase(it);
       }
-      if (w == target_w) {
-        reached = true;
-        maxw = std::max<uint64_t>(maxw, l + 1);
-        sumw += l + 1;
-        break;
-      }
+      for (uint64_t j = 0; j < W && !empty_before; ++j) empty_before = slots[w * W + j] == 0;
     }
-    if (!reached) { stats[4] = i; return 4; }
+    for (auto& rest : in_window)
+      for (uint64_t i : rest.second) note(i, 4);
   }
   stats[0] = live_n;
   stats[1] = tombs;
   stats[2] = maxw;
   stats[3] = sumw;
-  return 0;
+  stats[4] = bad;
+  return code;
 }
 
 /*
