@@ -49,8 +49,9 @@ extern "C" {
 
 typedef struct hc_table_s* hc_table;
 
-/* Table kinds (Sec. IV: SingleValueHashTable, MultiValueHashTable, CountingHashTable). */
-enum { HC_SINGLE_VALUE = 0, HC_MULTI_VALUE = 1, HC_COUNTING = 2 };
+/* Table kinds (Sec. IV: SingleValueHashTable, MultiValueHashTable, CountingHashTable,
+ * BucketListHashTable; the last is made by hc_create_bucket_list). */
+enum { HC_SINGLE_VALUE = 0, HC_MULTI_VALUE = 1, HC_COUNTING = 2, HC_BUCKET_LIST = 3 };
 
 /* Outer probing schemes over windows (Sec. II):
  *   linear     w_l = (h + l) mod P
@@ -117,6 +118,50 @@ hc_err hc_table_bytes(uint64_t capacity, const hc_params* params, uint64_t* h_ou
  * too small array. */
 hc_err hc_create_in(hc_table* out, uint32_t kind, void* d_slots, uint64_t slot_bytes, uint64_t capacity,
                     const hc_params* params);
+
+/* ---- bucket list tables (Sec. IV-C) ------------------------------------------------
+ * A multi-value table that stores each distinct key once: the key's slot in a
+ * cooperative-probing table holds its number of values, and the values live in a list of
+ * buckets taken from one preallocated pool.  Bucket i holds s_i values: s_0 = s0,
+ * s_i = min(ceil(growth * s_{i-1}), smax) (the paper's growth rule, capped); every bucket
+ * but the first begins with the pool offset of the bucket before it.  A key's values sit in
+ * its list in insertion-ticket order.  Pool memory of erased keys is not reused before
+ * hc_clear.
+ *   hc_insert: pairs as for a multi-value table (status OK, FULL when the key table or the
+ *              pool is full, INVALID_KEY); values are required.
+ *   hc_retrieve: d_values_out = the key's number of values, found = key present.
+ *   hc_count_values / hc_retrieve_all: as for multi-value tables (values in list order).
+ *   hc_erase: removes the key and all its values.  hc_size: values stored.
+ * Not supported: hc_insert_grouped, batched launches and the server (HC_E_KIND). */
+typedef struct {
+  uint64_t pool_values;  /* pool size in 32-bit words (values and links); 0: 4 per key slot */
+  uint32_t s0;           /* first bucket size, >= 1 */
+  uint32_t smax;         /* largest bucket size, s0 <= smax <= 2^24 */
+  double growth;         /* growth factor lambda in [1, 64]; with 1 every bucket holds s0 (needs s0 = smax) */
+} hc_bucket_params;
+
+void hc_default_bucket_params(hc_bucket_params* params); /* pool 0 (4 per slot), s0 1, smax 65536, growth 2 */
+
+/* Create a bucket list table for at least key_capacity distinct keys (rounded as hc_create).
+ * params / bparams may be NULL (defaults).  Errors: HC_E_ARG (bad parameters, or a size ramp
+ * from s0 to smax longer than 4096 buckets), HC_E_NOMEM. */
+hc_err hc_create_bucket_list(hc_table* out, uint64_t key_capacity, const hc_params* params,
+                             const hc_bucket_params* bparams);
+
+typedef struct {
+  uint64_t values;      /* values stored (hc_size) */
+  uint64_t pool_used;   /* pool words handed out (values, links and the unused tail of last buckets) */
+  uint64_t pool_words;  /* pool size */
+  uint32_t smax;
+  uint32_t reserved;
+} hc_bucket_usage_t;
+
+/* Pool usage of a bucket list table (synchronises the stream); storage density follows from it. */
+hc_err hc_bucket_usage(hc_table table, hc_bucket_usage_t* h_out, void* stream);
+
+/* Copy the pool (pool_words uint32) and the per-slot last-bucket offsets (C uint32) to caller
+ * device memory, on the stream (for inspection). */
+hc_err hc_dump_buckets(hc_table table, uint32_t* d_pool_dst, uint32_t* d_last_dst, void* stream);
 
 /* Release the table and its device memory (synchronises the device). */
 hc_err hc_destroy(hc_table table);

@@ -29,7 +29,8 @@ E_OK, E_ARG, E_NOMEM, E_KIND, E_DEVICE = 0, 1, 2, 3, 4
 OP_INSERT, OP_RETRIEVE, OP_ERASE = 0, 1, 2
 
 SCHEMES = {"linear": LINEAR, "quadratic": QUADRATIC, "double": DOUBLE}
-KINDS = {"single": SINGLE_VALUE, "multi": MULTI_VALUE, "counting": COUNTING}
+BUCKET_LIST = 3
+KINDS = {"single": SINGLE_VALUE, "multi": MULTI_VALUE, "counting": COUNTING, "bucket": BUCKET_LIST}
 
 
 class HcParams(ctypes.Structure):
@@ -44,6 +45,16 @@ class HcTableInfo(ctypes.Structure):
 
 
 PROBE_BUCKETS = 16
+
+
+class HcBucketParams(ctypes.Structure):
+    _fields_ = [("pool_values", ctypes.c_uint64), ("s0", ctypes.c_uint32), ("smax", ctypes.c_uint32),
+                ("growth", ctypes.c_double)]
+
+
+class HcBucketUsage(ctypes.Structure):
+    _fields_ = [("values", ctypes.c_uint64), ("pool_used", ctypes.c_uint64), ("pool_words", ctypes.c_uint64),
+                ("smax", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class HcTableStats(ctypes.Structure):
@@ -82,6 +93,11 @@ _SIGS = {
     "hc_create_in": ([ctypes.POINTER(_p), _u32, _p, _u64, _u64, ctypes.POINTER(HcParams)], ctypes.c_int),
     "hc_table_bytes": ([_u64, ctypes.POINTER(HcParams), ctypes.POINTER(_u64)], ctypes.c_int),
     "hc_stats": ([_p, ctypes.POINTER(HcTableStats), _p], ctypes.c_int),
+    "hc_default_bucket_params": ([ctypes.POINTER(HcBucketParams)], None),
+    "hc_create_bucket_list": ([ctypes.POINTER(_p), _u64, ctypes.POINTER(HcParams), ctypes.POINTER(HcBucketParams)],
+                              ctypes.c_int),
+    "hc_bucket_usage": ([_p, ctypes.POINTER(HcBucketUsage), _p], ctypes.c_int),
+    "hc_dump_buckets": ([_p, _p, _p, _p], ctypes.c_int),
     "hc_destroy": ([_p], ctypes.c_int),
     "hc_clear": ([_p, _p], ctypes.c_int),
     "hc_insert": ([_p, _p, _p, _u64, _p, _u32, _p], ctypes.c_int),
@@ -194,6 +210,30 @@ def hc_stats(h: int, stream=None) -> HcTableStats:
     out = HcTableStats()
     _check(_lib.hc_stats(h, ctypes.byref(out), _stream(stream)), "hc_stats")
     return out
+
+
+def hc_default_bucket_params() -> HcBucketParams:
+    p = HcBucketParams()
+    _lib.hc_default_bucket_params(ctypes.byref(p))
+    return p
+
+
+def hc_create_bucket_list(key_capacity: int, params: HcParams | None = None,
+                          bparams: HcBucketParams | None = None) -> int:
+    h = ctypes.c_void_p()
+    _check(_lib.hc_create_bucket_list(ctypes.byref(h), key_capacity, ctypes.byref(params) if params else None,
+                                      ctypes.byref(bparams) if bparams else None), "hc_create_bucket_list")
+    return h.value
+
+
+def hc_bucket_usage(h: int, stream=None) -> HcBucketUsage:
+    out = HcBucketUsage()
+    _check(_lib.hc_bucket_usage(h, ctypes.byref(out), _stream(stream)), "hc_bucket_usage")
+    return out
+
+
+def hc_dump_buckets(h: int, pool, last, stream=None):
+    _check(_lib.hc_dump_buckets(h, _u32t(pool, "pool"), _u32t(last, "last"), _stream(stream)), "hc_dump_buckets")
 
 
 def hc_destroy(h: int):
@@ -476,9 +516,10 @@ class Table:
     """A table handle with allocation of outputs.  ``kind``: 'single' | 'multi' | 'counting'."""
 
     def __init__(self, kind="single", capacity=1 << 20, scheme="double", window=16, group=4,
-                 seed=None, device=None, slots=None):
+                 seed=None, device=None, slots=None, bucket=None):
         """``slots``: optional caller-owned uint8/uint64 device tensor holding the slot array
-        (hc_create_in); the Table keeps a reference to it."""
+        (hc_create_in); the Table keeps a reference to it.  ``kind="bucket"``: a bucket list table
+        for ``capacity`` keys; ``bucket`` = dict(pool_values=, s0=, smax=, growth=) overrides."""
         self.kind = KINDS[kind] if isinstance(kind, str) else int(kind)
         p = hc_default_params()
         p.scheme = SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)
@@ -490,8 +531,15 @@ class Table:
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.slots = slots
         with torch.cuda.device(self.device):
-            self.handle = hc_create(self.kind, capacity, p) if slots is None else \
-                hc_create_in(self.kind, slots, capacity, p)
+            if self.kind == BUCKET_LIST:
+                bp = hc_default_bucket_params()
+                for key, val in (bucket or {}).items():
+                    setattr(bp, key, val)
+                self.handle = hc_create_bucket_list(capacity, p, bp)
+                self.bucket = {"pool_values": bp.pool_values, "s0": bp.s0, "smax": bp.smax, "growth": bp.growth}
+            else:
+                self.handle = hc_create(self.kind, capacity, p) if slots is None else \
+                    hc_create_in(self.kind, slots, capacity, p)
         info = hc_info(self.handle)
         self.capacity, self.windows, self.window = int(info.capacity), int(info.windows), int(info.window)
         self.scheme, self.seed, self.group = int(info.scheme), int(info.seed), int(info.group)
@@ -545,6 +593,17 @@ class Table:
 
     def load_factor(self, stream=None) -> float:
         return hc_load_factor(self.handle, stream)
+
+    def bucket_usage(self, stream=None) -> dict:
+        u = hc_bucket_usage(self.handle, stream)
+        return {"values": u.values, "pool_used": u.pool_used, "pool_words": u.pool_words, "smax": u.smax}
+
+    def dump_buckets(self, stream=None):
+        u = hc_bucket_usage(self.handle, stream)
+        pool = torch.empty(u.pool_words, dtype=torch.uint32, device=self.device)
+        last = torch.empty(self.capacity, dtype=torch.uint32, device=self.device)
+        hc_dump_buckets(self.handle, pool, last, stream)
+        return pool, last
 
     def stats(self, stream=None) -> dict:
         st = hc_stats(self.handle, stream)

@@ -1,0 +1,498 @@
+// Bucket list hash table (Sec. IV-C).
+//
+// Each distinct key occupies one slot of a cooperative-probing table; the
+// slot's value half counts the key's values, and per slot `last` holds the pool
+// offset of the key's last bucket.  Bucket i holds s_i values, s_0 given,
+// s_i = ceil(growth * s_{i-1}) up to a cap; every bucket but the first starts
+// with the pool offset of the bucket before it, so a list is walked from its
+// last bucket back to the first.  The pool is one preallocated array handed out
+// by an atomic counter.
+//
+// The paper appends under a per-key handle lock taken with CAS, with busy waiting
+// while another thread holds it.  A bulk insert here needs no lock and no
+// waiting, and leaves the same lists:
+//   1. every pair probes for its key (claiming a slot with count 1 if absent,
+//      else adding 1 to the count with one 64-bit atomic): the count before the
+//      add is the pair's ticket, its rank among all values of the key.  The first
+//      ticket of each key in the batch is recorded with an atomic minimum on a
+//      per-slot stamp tagged with the batch number, whose first writer also lists
+//      the key as touched;
+//   2. for every touched key one thread takes the buckets its new tickets need
+//      from the pool in one allocation, links them (previous-bucket offsets) and
+//      moves `last`; if the pool is exhausted the count is cut back to what the
+//      existing buckets hold (a key left with none becomes a tombstone);
+//   3. every pair writes its value where its ticket falls: ticket t lies in the
+//      bucket i with S(i) <= t < S(i+1), S(i) = s_0 + ... + s_{i-1}.
+// Values of a key therefore appear in its list in ticket order.
+#include <cmath>
+
+#include "hc_bucket.hpp"
+#include "hc_kernels.hpp"
+#include "hc_launch.hpp"
+
+namespace hc {
+
+// ---- bucket geometry ----------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t bl_S(const BucketView& b, uint64_t i) {  // values in buckets 0..i-1
+  return (i <= b.m) ? b.cum[i] : b.cum[b.m] + (i - b.m) * (uint64_t)b.smax;
+}
+
+__device__ __forceinline__ uint64_t bl_bucket_of(const BucketView& b, uint64_t t) {  // S(i) <= t < S(i+1)
+  const uint64_t ramp = b.cum[b.m];
+  if (t >= ramp) return b.m + (t - ramp) / b.smax;
+  uint32_t lo = 0, hi = b.m - 1;  // cum[0] = 0 <= t < cum[m]
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) / 2;
+    if (b.cum[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint64_t bl_buckets(const BucketView& b, uint64_t c) {  // buckets holding c values
+  return c == 0 ? 0 : bl_bucket_of(b, c - 1) + 1;
+}
+
+// Pool words of buckets [b0, b1): their values plus one link word for each i >= 1.
+__device__ __forceinline__ uint64_t bl_words(const BucketView& b, uint64_t b0, uint64_t b1) {
+  if (b1 <= b0) return 0;
+  const uint64_t links = b1 - (b0 > 1 ? b0 : 1);
+  return bl_S(b, b1) - bl_S(b, b0) + (b1 >= 1 ? links : 0);
+}
+
+// ---- phase 1: key probe, tickets ------------------------------------------------------
+
+template <int G, int W>
+struct BlTicket {
+  using L = Lane<G, W>;
+  static constexpr int SPL = L::SPL;
+  L ln;
+  TableView t;
+  BucketView b;
+  const uint32_t* __restrict__ keys;
+  uint64_t* __restrict__ pos;     // per pair: slot of its key
+  uint32_t* __restrict__ ticket;  // per pair: rank among the key's values
+  uint8_t* __restrict__ st;       // per pair: ST_OK provisional, or the final failure
+  uint64_t i = 0, cand_idx = 0;
+  uint32_t k = 0, lbase = 0, k_nx = 0;
+  Seq s{};
+  bool cand = false;
+  long long added = 0;
+
+  __device__ __forceinline__ void load(uint64_t op) { k_nx = keys[op]; }
+  __device__ __forceinline__ void begin(uint64_t op) {
+    i = op;
+    k = k_nx;
+    ln.start(t, k, s, lbase);
+    cand = false;
+  }
+  __device__ __forceinline__ bool fail(uint8_t code) {
+    if (ln.g.glane == 0) st[i] = code;
+    return true;
+  }
+  // One lane: the pair now holds ticket tk at slot idx.
+  __device__ __forceinline__ void record(uint64_t idx, uint32_t tk) {
+    pos[i] = idx;
+    ticket[i] = tk;
+    st[i] = ST_OK;
+    const unsigned long long mark = ((unsigned long long)(~b.epoch) << 32) | tk;
+    const unsigned long long old = atomicMin(b.stamp + idx, mark);
+    if ((uint32_t)(old >> 32) != ~b.epoch) b.touched[atomicAdd(b.touched_n, 1ull)] = idx;  // first of this batch
+  }
+  __device__ __forceinline__ void add_one(uint64_t idx) {
+    const uint64_t old = atomicAdd((unsigned long long*)&t.slots[idx], 1ull << 32);
+    record(idx, slot_value(old));
+  }
+  // CAS a reusable slot: 1 claimed (ticket 0), 2 the key was there (ticket taken), 3 lost to another key.
+  __device__ __forceinline__ uint32_t claim(uint64_t idx, uint64_t expect) {
+    const uint64_t r = atomicCAS((unsigned long long*)&t.slots[idx], (unsigned long long)expect,
+                                 (unsigned long long)make_slot(k, 1u));
+    if (r == expect) {
+      ++added;
+      record(idx, 0u);
+      return 1;
+    }
+    if (slot_key(r) == k) {
+      add_one(idx);
+      return 2;
+    }
+    return 3;
+  }
+  __device__ __forceinline__ bool step() {
+    const auto& g = ln.g;
+    if (reserved_key(k)) return fail(ST_INVALID_KEY);
+    Window<SPL> win;
+    load_step<G, W>(t, ln, s, lbase, k, win);
+    const uint64_t b_match = g.bits(win.match != 0);
+    if (b_match) {
+      if (g.glane == (uint32_t)ffs64(b_match)) add_one(win.first + lowbit(win.match));
+      return true;
+    }
+    const bool any_empty = g.bits(win.empty != 0) != 0;
+    MaskT<SPL> reuse = win.empty | win.tomb;
+    uint64_t b_reuse = g.bits(reuse != 0);
+    const bool lastw = ln.exhausted(t, lbase);
+    if (any_empty || lastw) {
+      if (cand) {  // a tombstone from an earlier window comes first
+        uint32_t outcome = 0;
+        if (g.glane == 0) outcome = claim(cand_idx, WORD_TOMB);
+        outcome = g.bcast(outcome, 0);
+        if (outcome != 3) return true;
+        ln.start(t, k, s, lbase);
+        cand = false;
+        return false;
+      }
+      while (b_reuse) {
+        const uint32_t r = (uint32_t)ffs64(b_reuse);
+        uint32_t outcome = 0;
+        if (g.glane == r) {
+          const int j = lowbit(reuse);
+          const uint64_t expect = ((win.empty >> j) & 1) ? WORD_EMPTY : WORD_TOMB;
+          reuse &= reuse - 1;
+          outcome = claim(win.first + j, expect);
+        }
+        outcome = g.bcast(outcome, r);
+        if (outcome != 3) return true;
+        b_reuse = g.bits(reuse != 0);
+      }
+      if (lastw) return fail(ST_FULL);
+    } else if (!cand && b_reuse) {
+      const uint32_t r = (uint32_t)ffs64(b_reuse);
+      cand_idx = g.bcast64(win.first + lowbit(reuse), r);
+      cand = true;
+    }
+    ln.advance(t, s, lbase);
+    return false;
+  }
+  __device__ __forceinline__ void end() {}  // the size counts values (phase 3)
+};
+
+template <int G, int W>
+__global__ __launch_bounds__(BLOCK) void k_bl_ticket(TableView t, WorkCtl ctl, BucketView b,
+                                                     const uint32_t* __restrict__ keys, uint64_t n,
+                                                     uint64_t* __restrict__ pos, uint32_t* __restrict__ ticket,
+                                                     uint8_t* __restrict__ st) {
+  BlTicket<G, W> op;
+  op.t = t;
+  op.b = b;
+  op.keys = keys;
+  op.pos = pos;
+  op.ticket = ticket;
+  op.st = st;
+  drive<G>(n, ctl, op);
+}
+
+// ---- phase 2: buckets per touched key -------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_bl_alloc(TableView t, BucketView b) {
+  const uint64_t T = *b.touched_n;
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  for (uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x; e < T; e += stride) {
+    const uint64_t p = b.touched[e];
+    const uint64_t c0 = (uint32_t)b.stamp[p];  // first ticket of this batch = count before it
+    const uint64_t word = t.slots[p];
+    const uint64_t c1 = slot_value(word);     // count after phase 1
+    const uint64_t b0 = bl_buckets(b, c0), b1 = bl_buckets(b, c1);
+    const uint32_t old_last = b.last[p];
+    uint32_t first_new = 0xFFFFFFFFu;
+    if (b1 > b0) {
+      const uint64_t words = bl_words(b, b0, b1);
+      const unsigned long long base = atomicAdd(b.pool_next, (unsigned long long)words);
+      if (base + words > b.pool_cap || base + words > 0xFFFFFFFFull) {
+        // pool exhausted: keep what the existing buckets hold; a key left with no value leaves the table
+        const uint64_t keep = bl_S(b, b0);
+        atomicExch((unsigned long long*)&t.slots[p],
+                   (unsigned long long)(keep ? make_slot(slot_key(word), (uint32_t)keep) : WORD_TOMB));
+      } else {
+        uint64_t o = base, prev = old_last;
+        for (uint64_t i = b0; i < b1; ++i) {
+          if (i >= 1) b.pool[o] = (uint32_t)prev;
+          prev = o;
+          o += bl_S(b, i + 1) - bl_S(b, i) + (i >= 1 ? 1 : 0);
+        }
+        b.last[p] = (uint32_t)prev;
+        first_new = (uint32_t)base;
+      }
+    }
+    b.batch[p] = (uint64_t)old_last | ((uint64_t)first_new << 32);
+  }
+}
+
+// ---- phase 3: values -----------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_bl_place(TableView t, BucketView b, const uint32_t* __restrict__ values,
+                                                  uint64_t n, const uint64_t* __restrict__ pos,
+                                                  const uint32_t* __restrict__ ticket, uint8_t* __restrict__ st,
+                                                  uint8_t* __restrict__ status) {
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  long long stored = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    uint8_t code = st[i];
+    if (code == ST_OK) {
+      const uint64_t p = pos[i], tk = ticket[i];
+      const uint64_t c = slot_value(t.slots[p]);
+      if (tk >= c) {
+        code = ST_FULL;
+      } else {
+        const uint64_t c0 = (uint32_t)b.stamp[p];
+        const uint64_t b0 = bl_buckets(b, c0), bi = bl_bucket_of(b, tk);
+        const uint64_t bat = b.batch[p];
+        const uint64_t o = (bi < b0) ? (uint32_t)bat : (bat >> 32) + bl_words(b, b0, bi);
+        b.pool[o + (bi >= 1 ? 1 : 0) + (tk - bl_S(b, bi))] = values[i];
+        ++stored;
+      }
+    }
+    if (status != nullptr) status[i] = code;
+  }
+  wave_add_to(t.size, stored);
+}
+
+// ---- retrieval -------------------------------------------------------------------------
+
+// Probe for the key (as a single-value lookup); count mode writes the key's
+// count, write mode walks its list back from the last bucket, the group's lanes
+// copying each bucket's values.
+template <int G, int W, bool WRITE>
+struct BlProbe {
+  using L = Lane<G, W>;
+  static constexpr int SPL = L::SPL;
+  L ln;
+  TableView t;
+  BucketView b;
+  const uint32_t* __restrict__ keys;
+  uint32_t* __restrict__ counts;
+  uint64_t* __restrict__ offsets;
+  uint32_t* __restrict__ out;
+  uint64_t i = 0, base_nx = 0, end_nx = 0, base = 0, limit = 0;
+  uint32_t k = 0, lbase = 0, k_nx = 0;
+  Seq s{};
+
+  __device__ __forceinline__ void load(uint64_t op) {
+    k_nx = keys[op];
+    if constexpr (WRITE) {
+      base_nx = offsets[op];
+      end_nx = offsets[op + 1];
+    }
+  }
+  __device__ __forceinline__ void begin(uint64_t op) {
+    i = op;
+    k = k_nx;
+    ln.start(t, k, s, lbase);
+    base = base_nx;
+    limit = end_nx - base_nx;
+  }
+  __device__ __forceinline__ bool found(uint64_t c, uint64_t p) {  // every lane of the group
+    if constexpr (!WRITE) {
+      if (ln.g.glane == 0) {
+        offsets[i] = c;
+        if (counts != nullptr) counts[i] = (uint32_t)c;
+      }
+    } else {
+      if (c == 0 || limit == 0) return true;
+      uint64_t bi = bl_bucket_of(b, c - 1);
+      uint64_t o = b.last[p];
+      for (;;) {
+        const uint64_t lo = bl_S(b, bi), hi = bl_S(b, bi + 1) < c ? bl_S(b, bi + 1) : c;
+        const uint64_t v0 = o + (bi >= 1 ? 1 : 0);
+        for (uint64_t j = ln.g.glane; j < hi - lo; j += G)
+          if (lo + j < limit) out[base + lo + j] = b.pool[v0 + j];  // never leave the segment
+        if (bi == 0) break;
+        o = b.pool[o];
+        --bi;
+      }
+    }
+    return true;
+  }
+  __device__ __forceinline__ bool step() {
+    const auto& g = ln.g;
+    if (reserved_key(k)) return found(0, 0);
+    Window<SPL> win;
+    load_step<G, W>(t, ln, s, lbase, k, win);
+    const uint64_t b_match = g.bits(win.match != 0);
+    if (b_match) {
+      const uint32_t r = (uint32_t)ffs64(b_match);
+      uint64_t c = 0, p = 0;
+      if (g.glane == r) {
+        c = slot_value(pick_lowest<SPL>(win.word, win.match));
+        p = win.first + lowbit(win.match);
+      }
+      return found(g.bcast64(c, r), g.bcast64(p, r));
+    }
+    if (g.bits(win.empty != 0) || ln.exhausted(t, lbase)) return found(0, 0);
+    ln.advance(t, s, lbase);
+    return false;
+  }
+  __device__ __forceinline__ void end() {}
+};
+
+template <int G, int W, bool WRITE>
+__global__ __launch_bounds__(BLOCK) void k_bl_probe(TableView t, WorkCtl ctl, BucketView b,
+                                                    const uint32_t* __restrict__ keys, uint64_t n,
+                                                    uint32_t* __restrict__ counts, uint64_t* __restrict__ offsets,
+                                                    uint32_t* __restrict__ out) {
+  BlProbe<G, W, WRITE> op;
+  op.t = t;
+  op.b = b;
+  op.keys = keys;
+  op.counts = counts;
+  op.offsets = offsets;
+  op.out = out;
+  drive<G>(n, ctl, op);
+}
+
+// ---- erase: the key's slot becomes a tombstone, its values leave the count ------------
+
+template <int G, int W>
+struct BlErase {
+  using L = Lane<G, W>;
+  static constexpr int SPL = L::SPL;
+  L ln;
+  TableView t;
+  const uint32_t* __restrict__ keys;
+  uint8_t* __restrict__ status;
+  uint64_t i = 0;
+  uint32_t k = 0, lbase = 0, k_nx = 0;
+  Seq s{};
+  long long added = 0;
+
+  __device__ __forceinline__ void load(uint64_t op) { k_nx = keys[op]; }
+  __device__ __forceinline__ void begin(uint64_t op) {
+    i = op;
+    k = k_nx;
+    ln.start(t, k, s, lbase);
+  }
+  __device__ __forceinline__ bool done(uint8_t code) {
+    if (status != nullptr && ln.g.glane == 0) status[i] = code;
+    return true;
+  }
+  __device__ __forceinline__ bool step() {
+    const auto& g = ln.g;
+    if (reserved_key(k)) return done(ST_INVALID_KEY);
+    Window<SPL> win;
+    load_step<G, W>(t, ln, s, lbase, k, win);
+    const uint64_t b_match = g.bits(win.match != 0);
+    if (b_match) {
+      const uint32_t r = (uint32_t)ffs64(b_match);
+      uint32_t ok = 0;
+      if (g.glane == r) {
+        const uint64_t idx = win.first + lowbit(win.match);
+        const uint64_t res = atomicExch((unsigned long long*)&t.slots[idx], (unsigned long long)WORD_TOMB);
+        if (slot_key(res) == k) {  // else erased by another group of this launch
+          ok = 1;
+          added -= (long long)slot_value(res);
+        }
+      }
+      return done(g.bcast(ok, r) ? ST_OK : ST_NOT_FOUND);
+    }
+    if (g.bits(win.empty != 0) || ln.exhausted(t, lbase)) return done(ST_NOT_FOUND);
+    ln.advance(t, s, lbase);
+    return false;
+  }
+  __device__ __forceinline__ void end() { wave_add_to(t.size, added); }
+};
+
+template <int G, int W>
+__global__ __launch_bounds__(BLOCK) void k_bl_erase(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys,
+                                                    uint64_t n, uint8_t* __restrict__ status) {
+  BlErase<G, W> op;
+  op.t = t;
+  op.keys = keys;
+  op.status = status;
+  drive<G>(n, ctl, op);
+}
+
+__global__ __launch_bounds__(256) void k_bl_reset(unsigned long long* stamp, uint64_t C) {
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < C; i += stride) stamp[i] = ~0ull;
+}
+
+// ---- host side ----------------------------------------------------------------------------
+
+bool bucket_ramp(uint32_t s0, double growth, uint32_t smax, uint64_t* cum, uint32_t* m) {
+  uint64_t s = s0, total = 0;
+  uint32_t i = 0;
+  cum[0] = 0;
+  while (s < smax) {
+    if (i >= BL_MAX_RAMP) return false;
+    total += s;
+    cum[++i] = total;
+    const double next = std::ceil(growth * (double)s);
+    s = next >= (double)smax ? smax : (uint64_t)next;
+  }
+  *m = i;
+  return true;
+}
+
+static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+uint64_t bl_insert_workspace(uint64_t n) { return align256(8 * n) + align256(4 * n) + align256(n); }
+
+static unsigned stream_grid(uint64_t n) {
+  uint64_t g = (n + 255) / 256;
+  const uint64_t cap = (uint64_t)device_cu_count() * 8;
+  if (g > cap) g = cap;
+  return (unsigned)(g ? g : 1);
+}
+
+hc_err launch_bl_insert(const TableView& t, const BucketView& b, uint32_t G, uint32_t W, const uint32_t* keys,
+                        const uint32_t* values, uint64_t n, uint8_t* status, void* ws, hipStream_t s) {
+  char* p = (char*)ws;
+  uint64_t* pos = (uint64_t*)p; p += align256(8 * n);
+  uint32_t* ticket = (uint32_t*)p; p += align256(4 * n);
+  uint8_t* st = (uint8_t*)p;
+  hc_err r = dispatch_gw(G, W, [&](auto g, auto w) -> hc_err {
+    constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
+    auto k = k_bl_ticket<GG, WW>;
+    const unsigned grid = grid_for(k, n, GG);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid), b, keys, n, pos, ticket, st);
+    return check_launch("bucket list tickets");
+  });
+  if (r != HC_OK) return r;
+  hipLaunchKernelGGL(k_bl_alloc, dim3(stream_grid(n)), dim3(256), 0, s, t, b);
+  if ((r = check_launch("bucket list allocation")) != HC_OK) return r;
+  hipLaunchKernelGGL(k_bl_place, dim3(stream_grid(n)), dim3(256), 0, s, t, b, values, n, pos, ticket, st, status);
+  return check_launch("bucket list values");
+}
+
+hc_err launch_bl_count(const TableView& t, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n, uint32_t* counts,
+                       uint64_t* offsets, hipStream_t s) {
+  return dispatch_gw(G, W, [&](auto g, auto w) -> hc_err {
+    constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
+    auto k = k_bl_probe<GG, WW, false>;
+    const unsigned grid = grid_for(k, n, GG);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid), BucketView{}, keys, n, counts,
+                       offsets, nullptr);
+    return check_launch("bucket list count");
+  });
+}
+
+hc_err launch_bl_write(const TableView& t, const BucketView& b, uint32_t G, uint32_t W, const uint32_t* keys,
+                       uint64_t n, const uint64_t* offsets, uint32_t* out, hipStream_t s) {
+  return dispatch_gw(G, W, [&](auto g, auto w) -> hc_err {
+    constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
+    auto k = k_bl_probe<GG, WW, true>;
+    const unsigned grid = grid_for(k, n, GG);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid), b, keys, n, nullptr,
+                       const_cast<uint64_t*>(offsets), out);  // the write pass only reads offsets
+    return check_launch("bucket list write");
+  });
+}
+
+hc_err launch_bl_erase(const TableView& t, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n, uint8_t* status,
+                       hipStream_t s) {
+  return dispatch_gw(G, W, [&](auto g, auto w) -> hc_err {
+    constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
+    auto k = k_bl_erase<GG, WW>;
+    const unsigned grid = grid_for(k, n, GG);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid), keys, n, status);
+    return check_launch("bucket list erase");
+  });
+}
+
+hc_err launch_bl_reset(const BucketView& b, uint64_t C, hipStream_t s) {
+  hipLaunchKernelGGL(k_bl_reset, dim3(stream_grid(C)), dim3(256), 0, s, b.stamp, C);
+  return check_launch("bucket list reset");
+}
+
+}  // namespace hc

@@ -1,0 +1,54 @@
+// Bucket list hash table (Sec. IV-C): keys in a cooperative-probing table whose
+// slot value is the key's number of values; the values in a list of buckets
+// taken from one preallocated pool (see hc_bucket.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hc.h"
+#include "hc_device.hpp"
+
+namespace hc {
+
+constexpr int KIND_BUCKET = 3;
+constexpr uint32_t BL_MAX_RAMP = 4096;  // bucket sizes listed before the cap is reached, at most
+
+// Device view of the bucket lists of one table.
+struct BucketView {
+  const uint64_t* cum;             // cum[i] = S(i), values held by buckets 0..i-1, for i = 0..m
+  uint32_t m;                      // buckets before sizes reach smax (bucket m onward holds smax values)
+  uint32_t smax;
+  uint32_t* pool;                  // bucket pool, 32-bit words
+  uint64_t pool_cap;               // words
+  unsigned long long* pool_next;   // first free word
+  uint32_t* last;                  // per key slot: pool offset of the key's last bucket
+  unsigned long long* stamp;       // per key slot: (~batch << 32) | first ticket of the key in that batch
+  uint64_t* batch;                 // per key slot: old last bucket (low 32) | first new bucket (high 32)
+  unsigned long long* touched_n;   // keys touched by the current batch
+  uint64_t* touched;               // their slot indices
+  uint32_t epoch;                  // batch number (1 ..)
+};
+
+// Bucket sizes s_0 = s0, s_i = min(ceil(growth * s_{i-1}), smax): the ramp up to
+// the cap, as cumulative sums (host side).  Returns false if the ramp is longer
+// than BL_MAX_RAMP buckets.
+bool bucket_ramp(uint32_t s0, double growth, uint32_t smax, uint64_t* cum, uint32_t* m);
+
+// Phase 1..3 of a bulk insert of n pairs (keys, values) into a bucket list table.
+// Workspace: bl_insert_workspace(n) bytes.  status optional.
+uint64_t bl_insert_workspace(uint64_t n);
+hc_err launch_bl_insert(const TableView& t, const BucketView& b, uint32_t G, uint32_t W, const uint32_t* keys,
+                        const uint32_t* values, uint64_t n, uint8_t* status, void* ws, hipStream_t s);
+// Counts of keys (into offsets[i], and counts[i] when given), before the scan.
+hc_err launch_bl_count(const TableView& t, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n, uint32_t* counts,
+                       uint64_t* offsets, hipStream_t s);
+// Values of keys into out[offsets[i] .. offsets[i+1]).
+hc_err launch_bl_write(const TableView& t, const BucketView& b, uint32_t G, uint32_t W, const uint32_t* keys,
+                       uint64_t n, const uint64_t* offsets, uint32_t* out, hipStream_t s);
+hc_err launch_bl_erase(const TableView& t, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n, uint8_t* status,
+                       hipStream_t s);
+// stamp[0..C) = ~0 (a fill kernel).
+hc_err launch_bl_reset(const BucketView& b, uint64_t C, hipStream_t s);
+
+}  // namespace hc

@@ -16,6 +16,7 @@
 
 #include "hc.h"
 #include "hc_batch.hpp"
+#include "hc_bucket.hpp"
 #include "hc_device.hpp"
 #include "hc_group.hpp"
 #include "hc_stats.hpp"
@@ -41,6 +42,16 @@ struct hc_table_s {
   void* d_ws;             // workspace of the multi-value passes (long-query lists, grouped insert)
   uint64_t ws_bytes;
   bool owns_slots;        // false: caller-owned slot array (hc_create_in)
+  // bucket list tables (kind HC_BUCKET_LIST)
+  uint64_t* d_cum = nullptr;       // cumulative bucket sizes of the ramp
+  uint32_t bl_m = 0, bl_smax = 0;
+  uint32_t* d_pool = nullptr;
+  uint64_t pool_cap = 0;
+  uint32_t* d_last = nullptr;
+  unsigned long long* d_stamp = nullptr;
+  uint64_t* d_batch = nullptr;
+  uint64_t* d_touched = nullptr;
+  uint32_t epoch = 0;
 };
 
 namespace hc {
@@ -178,6 +189,23 @@ static hc_err ensure_ws(hc_table_s* t, uint64_t bytes) {
   return HC_OK;
 }
 
+static BucketView bview_of(const hc_table_s* t) {
+  BucketView b{};
+  b.cum = t->d_cum;
+  b.m = t->bl_m;
+  b.smax = t->bl_smax;
+  b.pool = t->d_pool;
+  b.pool_cap = t->pool_cap;
+  b.pool_next = t->d_size + 1;  // size counter, pool counter, touched-key counter share one allocation
+  b.last = t->d_last;
+  b.stamp = t->d_stamp;
+  b.batch = t->d_batch;
+  b.touched_n = t->d_size + 2;
+  b.touched = t->d_touched;
+  b.epoch = t->epoch;
+  return b;
+}
+
 static TableView view_of(const hc_table_s* t) {
   TableView v;
   v.slots = t->slots;
@@ -247,7 +275,7 @@ hc_err build_plan(const hc_batch_op* ops, uint32_t count, int dev, PlanHost* out
     const hc_batch_op& o = ops[j];
     if (o.table == nullptr) return fail(HC_E_ARG, "op %u: table is NULL", j);
     const hc_table_s* t = o.table;
-    if (t->kind == HC_MULTI_VALUE)
+    if (t->kind == HC_MULTI_VALUE || t->kind == HC_BUCKET_LIST)
       return fail(HC_E_KIND, "op %u: batched operations take single-value or counting tables", j);
     if (t->device != dev) return fail(HC_E_ARG, "op %u: table lives on device %d, current device is %d", j, t->device, dev);
     if (o.op > HC_OP_ERASE) return fail(HC_E_ARG, "op %u: unknown operation %u", j, o.op);
@@ -377,7 +405,7 @@ static hc_err create_table(hc_table* out, uint32_t kind, uint64_t capacity, cons
                            void* ext_slots, uint64_t ext_bytes) {
   if (out == nullptr) return fail(HC_E_ARG, "out is NULL");
   *out = nullptr;
-  if (kind > 2) return fail(HC_E_ARG, "unknown table kind %u", kind);
+  if (kind > 3) return fail(HC_E_ARG, "unknown table kind %u", kind);
   hc_params p;
   uint64_t P = 0;
   if (hc_err r = table_geometry(capacity, params, &p, &P); r != HC_OK) return r;
@@ -438,7 +466,100 @@ static hc_err create_table(hc_table* out, uint32_t kind, uint64_t capacity, cons
 }
 
 hc_err hc_create(hc_table* out, uint32_t kind, uint64_t capacity, const hc_params* params) {
+  if (kind == HC_BUCKET_LIST) {
+    if (out) *out = nullptr;
+    return fail(HC_E_ARG, "bucket list tables are made by hc_create_bucket_list");
+  }
   return create_table(out, kind, capacity, params, nullptr, 0);
+}
+
+void hc_default_bucket_params(hc_bucket_params* p) {
+  p->pool_values = 0;  // 0: four values per key slot
+  p->s0 = 1;
+  p->smax = 1u << 16;
+  p->growth = 2.0;
+}
+
+hc_err hc_create_bucket_list(hc_table* out, uint64_t key_capacity, const hc_params* params,
+                             const hc_bucket_params* bparams) {
+  if (out == nullptr) return fail(HC_E_ARG, "out is NULL");
+  *out = nullptr;
+  hc_bucket_params bp;
+  hc_default_bucket_params(&bp);
+  if (bparams) bp = *bparams;
+  if (bp.s0 == 0 || bp.smax < bp.s0 || bp.smax > (1u << 24))
+    return fail(HC_E_ARG, "bucket sizes need 1 <= s0 <= smax <= 2^24 (s0 %u, smax %u)", bp.s0, bp.smax);
+  if (!(bp.growth >= 1.0 && bp.growth <= 64.0)) return fail(HC_E_ARG, "growth factor must lie in [1, 64]");
+  std::vector<uint64_t> cum(BL_MAX_RAMP + 1);
+  uint32_t m = 0;
+  if (!bucket_ramp(bp.s0, bp.growth, bp.smax, cum.data(), &m))
+    return fail(HC_E_ARG, "bucket sizes take more than %u steps to reach smax", BL_MAX_RAMP);
+  hc_table t = nullptr;
+  hc_err r = create_table(&t, HC_BUCKET_LIST, key_capacity, params, nullptr, 0);
+  if (r != HC_OK) return r;
+  const uint64_t pool = bp.pool_values ? bp.pool_values : 4 * t->C;
+  if (pool > 0xFFFFFFFFull) {
+    hc_destroy(t);
+    return fail(HC_E_ARG, "pool of %llu words exceeds 2^32 - 1", (unsigned long long)pool);
+  }
+  t->bl_m = m;
+  t->bl_smax = bp.smax;
+  t->pool_cap = pool;
+  hipError_t e = hipMalloc((void**)&t->d_cum, (m + 1) * sizeof(uint64_t));
+  if (e == hipSuccess) e = hipMalloc((void**)&t->d_pool, pool * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc((void**)&t->d_last, t->C * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc((void**)&t->d_stamp, t->C * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMalloc((void**)&t->d_batch, t->C * sizeof(uint64_t));
+  if (e == hipSuccess) e = hipMalloc((void**)&t->d_touched, t->C * sizeof(uint64_t));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    hc_destroy(t);
+    return fail(HC_E_NOMEM, "bucket list allocation failed");
+  }
+  e = hipMemcpy(t->d_cum, cum.data(), (m + 1) * sizeof(uint64_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hc_destroy(t);
+    return hip_fail(e, "bucket sizes upload");
+  }
+  r = hc_clear(t, nullptr);
+  if (r == HC_OK && (e = hipStreamSynchronize(nullptr)) != hipSuccess) r = hip_fail(e, "hc_create_bucket_list");
+  if (r != HC_OK) {
+    hc_destroy(t);
+    return r;
+  }
+  *out = t;
+  return HC_OK;
+}
+
+hc_err hc_bucket_usage(hc_table t, hc_bucket_usage_t* h_out, void* stream) {
+  hc_err r = check_table(t);
+  if (r != HC_OK) return r;
+  if (h_out == nullptr) return fail(HC_E_ARG, "out is NULL");
+  if (t->kind != HC_BUCKET_LIST) return fail(HC_E_KIND, "bucket usage needs a bucket list table");
+  if ((r = set_device(t)) != HC_OK) return r;
+  unsigned long long v[2] = {0, 0};
+  hipError_t e = hipMemcpyAsync(v, t->d_size, sizeof v, hipMemcpyDeviceToHost, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "hc_bucket_usage");
+  h_out->values = v[0];
+  h_out->pool_used = v[1] < t->pool_cap ? v[1] : t->pool_cap;
+  h_out->pool_words = t->pool_cap;
+  h_out->smax = t->bl_smax;
+  return HC_OK;
+}
+
+hc_err hc_dump_buckets(hc_table t, uint32_t* d_pool_dst, uint32_t* d_last_dst, void* stream) {
+  hc_err r = check_table(t);
+  if (r != HC_OK) return r;
+  if (t->kind != HC_BUCKET_LIST) return fail(HC_E_KIND, "bucket dump needs a bucket list table");
+  if (d_pool_dst == nullptr || d_last_dst == nullptr) return fail(HC_E_ARG, "destination is NULL");
+  if ((r = set_device(t)) != HC_OK) return r;
+  hipError_t e = hipMemcpyAsync(d_pool_dst, t->d_pool, t->pool_cap * sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                                (hipStream_t)stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_last_dst, t->d_last, t->C * sizeof(uint32_t), hipMemcpyDeviceToDevice, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "hc_dump_buckets");
+  return HC_OK;
 }
 
 hc_err hc_create_in(hc_table* out, uint32_t kind, void* d_slots, uint64_t slot_bytes, uint64_t capacity,
@@ -468,6 +589,9 @@ hc_err hc_destroy(hc_table t) {
   if (t->d_size) (void)hipFree(t->d_size);
   if (t->d_tiles) (void)hipFree(t->d_tiles);
   if (t->d_ws) (void)hipFree(t->d_ws);
+  for (void* q : {(void*)t->d_cum, (void*)t->d_pool, (void*)t->d_last, (void*)t->d_stamp, (void*)t->d_batch,
+                  (void*)t->d_touched})
+    if (q) (void)hipFree(q);
   delete t;
   if (e != hipSuccess) return hip_fail(e, "hc_destroy: synchronise");
   return HC_OK;
@@ -484,7 +608,13 @@ hc_err hc_clear(hc_table t, void* stream) {
   if (blocks == 0) blocks = 1;
   hipLaunchKernelGGL(k_fill_empty, dim3((unsigned)blocks), dim3(BLOCK), 0, (hipStream_t)stream,
                      reinterpret_cast<ulonglong2*>(t->slots), pairs, t->d_size);
-  return check_launch("clear");
+  if ((r = check_launch("clear")) != HC_OK) return r;
+  if (t->kind == HC_BUCKET_LIST && t->d_stamp != nullptr) {  // empty pool, fresh batch stamps (once allocated)
+    if ((r = launch_zero_u64(t->d_size + 1, 2, (hipStream_t)stream)) != HC_OK) return r;
+    if ((r = launch_bl_reset(bview_of(t), t->C, (hipStream_t)stream)) != HC_OK) return r;
+    t->epoch = 0;
+  }
+  return HC_OK;
 }
 
 hc_err hc_insert(hc_table t, const uint32_t* d_keys, const uint32_t* d_values, uint64_t n, uint8_t* d_status,
@@ -501,6 +631,17 @@ hc_err hc_insert(hc_table t, const uint32_t* d_keys, const uint32_t* d_values, u
     return fail(HC_E_ARG, "values is NULL");
   }
   if ((r = set_device(t)) != HC_OK) return r;
+  if (t->kind == HC_BUCKET_LIST) {
+    hipStream_t s = (hipStream_t)stream;
+    if (t->epoch == 0xFFFFFFFEu) {  // batch numbers run out: restart them on fresh stamps
+      if ((r = launch_bl_reset(bview_of(t), t->C, s)) != HC_OK) return r;
+      t->epoch = 0;
+    }
+    ++t->epoch;
+    if ((r = ensure_ws(t, bl_insert_workspace(n))) != HC_OK) return r;
+    if ((r = launch_zero_u64(t->d_size + 2, 1, s)) != HC_OK) return r;  // touched keys of this batch
+    return launch_bl_insert(view_of(t), bview_of(t), g, t->window, d_keys, d_values, n, d_status, t->d_ws, s);
+  }
   return launch_insert(view_of(t), (int)t->kind, g, t->window, d_keys, d_values, n, d_status, (hipStream_t)stream);
 }
 
@@ -527,6 +668,7 @@ hc_err hc_erase(hc_table t, const uint32_t* d_keys, uint64_t n, uint8_t* d_statu
   if (n == 0) return HC_OK;
   if (d_keys == nullptr) return fail(HC_E_ARG, "keys is NULL");
   if ((r = set_device(t)) != HC_OK) return r;
+  if (t->kind == HC_BUCKET_LIST) return launch_bl_erase(view_of(t), g, t->window, d_keys, n, d_status, (hipStream_t)stream);
   return launch_erase(view_of(t), (int)t->kind, g, t->window, d_keys, n, d_status, (hipStream_t)stream);
 }
 
@@ -534,7 +676,8 @@ hc_err hc_count_values(hc_table t, const uint32_t* d_keys, uint64_t n, uint32_t*
                        uint64_t* h_total, uint32_t group, void* stream) {
   hc_err r = check_table(t);
   if (r != HC_OK) return r;
-  if (t->kind != HC_MULTI_VALUE) return fail(HC_E_KIND, "count_values needs a multi-value table");
+  if (t->kind != HC_MULTI_VALUE && t->kind != HC_BUCKET_LIST)
+    return fail(HC_E_KIND, "count_values needs a multi-value or bucket list table");
   uint32_t g;
   if ((r = resolve_group(t, group, &g)) != HC_OK) return r;
   if (d_offsets == nullptr) return fail(HC_E_ARG, "offsets is NULL");
@@ -558,7 +701,9 @@ hc_err hc_count_values(hc_table t, const uint32_t* d_keys, uint64_t n, uint32_t*
     }
     t->tiles_cap = need;
   }
-  if (n > 0) {
+  if (n > 0 && t->kind == HC_BUCKET_LIST) {  // the count sits in the key's slot
+    if ((r = launch_bl_count(view_of(t), g, t->window, d_keys, n, d_counts, d_offsets, s)) != HC_OK) return r;
+  } else if (n > 0) {
     // queries still open after LONG_BUDGET windows are finished by block-wide segment rounds
     if ((r = ensure_ws(t, long_workspace_bytes(n, 0))) != HC_OK) return r;
     const LongState ls = long_layout(t->d_ws, n, 0);
@@ -583,13 +728,16 @@ hc_err hc_retrieve_all(hc_table t, const uint32_t* d_keys, uint64_t n, const uin
                        uint32_t* d_values_out, uint32_t group, void* stream) {
   hc_err r = check_table(t);
   if (r != HC_OK) return r;
-  if (t->kind != HC_MULTI_VALUE) return fail(HC_E_KIND, "retrieve_all needs a multi-value table");
+  if (t->kind != HC_MULTI_VALUE && t->kind != HC_BUCKET_LIST)
+    return fail(HC_E_KIND, "retrieve_all needs a multi-value or bucket list table");
   uint32_t g;
   if ((r = resolve_group(t, group, &g)) != HC_OK) return r;
   if (n == 0) return HC_OK;
   if (d_keys == nullptr || d_offsets == nullptr) return fail(HC_E_ARG, "keys or offsets is NULL");
   if ((r = set_device(t)) != HC_OK) return r;
   hipStream_t s = (hipStream_t)stream;
+  if (t->kind == HC_BUCKET_LIST)
+    return launch_bl_write(view_of(t), bview_of(t), g, t->window, d_keys, n, d_offsets, d_values_out, s);
   if ((r = ensure_ws(t, long_workspace_bytes(n, 1))) != HC_OK) return r;
   const LongState ls = long_layout(t->d_ws, n, 1);
   if ((r = launch_zero_u64((unsigned long long*)ls.nlong, 1, s)) != HC_OK) return r;
@@ -604,7 +752,8 @@ hc_err hc_retrieve_all(hc_table t, const uint32_t* d_keys, uint64_t n, const uin
 hc_err hc_insert_grouped(hc_table t, const uint32_t* d_keys, const uint32_t* d_values, uint64_t n, void* stream) {
   hc_err r = check_table(t);
   if (r != HC_OK) return r;
-  if (t->kind == HC_SINGLE_VALUE) return fail(HC_E_KIND, "grouped insert needs a multi-value or counting table");
+  if (t->kind == HC_SINGLE_VALUE || t->kind == HC_BUCKET_LIST)
+    return fail(HC_E_KIND, "grouped insert needs a multi-value or counting table");
   if (n == 0) return HC_OK;
   if (d_keys == nullptr) return fail(HC_E_ARG, "keys is NULL");
   if (t->kind == HC_COUNTING) {

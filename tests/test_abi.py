@@ -93,3 +93,24 @@ def test_table_bytes_and_create_in_arguments(lib):
     assert lib.hc_create_in(ctypes.byref(h), 0, 0x10010, 1 << 20, 1000, ctypes.byref(p)) == 1      # misaligned
     assert lib.hc_create_in(ctypes.byref(h), 0, 0x10000, out.value - 8, 1000, ctypes.byref(p)) == 1  # too small
     assert h.value is None
+
+
+class _BucketParams(ctypes.Structure):
+    _fields_ = [("pool_values", ctypes.c_uint64), ("s0", ctypes.c_uint32), ("smax", ctypes.c_uint32),
+                ("growth", ctypes.c_double)]
+
+
+def test_bucket_list_arguments(lib):
+    lib.hc_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p]
+    lib.hc_create_bucket_list.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint64, ctypes.c_void_p,
+                                          ctypes.POINTER(_BucketParams)]
+    lib.hc_default_bucket_params.argtypes = [ctypes.POINTER(_BucketParams)]
+    h = ctypes.c_void_p()
+    assert lib.hc_create(ctypes.byref(h), 3, 1024, None) == 1  # bucket lists have their own constructor
+    bp = _BucketParams()
+    lib.hc_default_bucket_params(ctypes.byref(bp))
+    assert (bp.s0, bp.smax, bp.growth, bp.pool_values) == (1, 1 << 16, 2.0, 0)
+    for s0, smax, growth in [(0, 8, 2.0), (9, 8, 2.0), (1, 1 << 25, 2.0), (1, 8, 0.5), (1, 8, 100.0),
+                             (1, 1 << 20, 1.0)]:  # the last never reaches smax: ramp too long
+        bad = _BucketParams(0, s0, smax, growth)
+        assert lib.hc_create_bucket_list(ctypes.byref(h), 1024, None, ctypes.byref(bad)) == 1, (s0, smax, growth)
