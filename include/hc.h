@@ -132,7 +132,8 @@ hc_err hc_create_in(hc_table* out, uint32_t kind, void* d_slots, uint64_t slot_b
  *   hc_retrieve: d_values_out = the key's number of values, found = key present.
  *   hc_count_values / hc_retrieve_all: as for multi-value tables (values in list order).
  *   hc_erase: removes the key and all its values.  hc_size: values stored.
- * Not supported: hc_insert_grouped, batched launches and the server (HC_E_KIND). */
+ *   hc_insert_grouped: the same lists, one atomic per distinct key of the batch.
+ * Not supported: batched launches and the server (HC_E_KIND). */
 typedef struct {
   uint64_t pool_values;  /* pool size in 32-bit words (values and links); 0: 4 per key slot */
   uint32_t s0;           /* first bucket size, >= 1 */
@@ -217,9 +218,11 @@ hc_err hc_retrieve_all(hc_table table, const uint32_t* d_keys, uint64_t n, const
  *    hc_insert.  d_values: n values, pair i = (d_keys[i], d_values[i]).
  *  - counting tables: each distinct key is inserted once, its count raised by its number of
  *    occurrences (one atomic per distinct key instead of one per occurrence).  d_values must be NULL.
+ *  - bucket list tables: each run of one key takes its tickets with one atomic, then buckets are
+ *    allocated and values placed as in hc_insert (same lists; values of a run in batch order).
  * Keys 0 and 0xFFFFFFFF are skipped; elements that find no reusable slot are dropped (hc_size tells
  * how many pairs / distinct keys are stored).  No per-element status.  n < 2^32.  Single-value
- * tables: HC_E_KIND. */
+ * tables: HC_E_KIND.  Workspace: about 48 bytes per element (74 for bucket lists). */
 hc_err hc_insert_grouped(hc_table table, const uint32_t* d_keys, const uint32_t* d_values, uint64_t n, void* stream);
 
 /* Live entries (single-value / counting: keys; multi-value: pairs).  Synchronises the stream. */

@@ -71,19 +71,24 @@ struct BlTicket {
   TableView t;
   BucketView b;
   const uint32_t* __restrict__ keys;
+  const uint32_t* __restrict__ incr;  // values per element (runs of a grouped insert); NULL: 1
   uint64_t* __restrict__ pos;     // per pair: slot of its key
   uint32_t* __restrict__ ticket;  // per pair: rank among the key's values
   uint8_t* __restrict__ st;       // per pair: ST_OK provisional, or the final failure
   uint64_t i = 0, cand_idx = 0;
-  uint32_t k = 0, lbase = 0, k_nx = 0;
+  uint32_t k = 0, lbase = 0, k_nx = 0, inc = 1, inc_nx = 1;
   Seq s{};
   bool cand = false;
   long long added = 0;
 
-  __device__ __forceinline__ void load(uint64_t op) { k_nx = keys[op]; }
+  __device__ __forceinline__ void load(uint64_t op) {
+    k_nx = keys[op];
+    inc_nx = incr != nullptr ? incr[op] : 1u;
+  }
   __device__ __forceinline__ void begin(uint64_t op) {
     i = op;
     k = k_nx;
+    inc = inc_nx;
     ln.start(t, k, s, lbase);
     cand = false;
   }
@@ -100,14 +105,14 @@ struct BlTicket {
     const unsigned long long old = atomicMin(b.stamp + idx, mark);
     if ((uint32_t)(old >> 32) != ~b.epoch) b.touched[atomicAdd(b.touched_n, 1ull)] = idx;  // first of this batch
   }
-  __device__ __forceinline__ void add_one(uint64_t idx) {
-    const uint64_t old = atomicAdd((unsigned long long*)&t.slots[idx], 1ull << 32);
+  __device__ __forceinline__ void add_one(uint64_t idx) {  // `inc` more values (tickets old .. old + inc - 1)
+    const uint64_t old = atomicAdd((unsigned long long*)&t.slots[idx], (unsigned long long)inc << 32);
     record(idx, slot_value(old));
   }
   // CAS a reusable slot: 1 claimed (ticket 0), 2 the key was there (ticket taken), 3 lost to another key.
   __device__ __forceinline__ uint32_t claim(uint64_t idx, uint64_t expect) {
     const uint64_t r = atomicCAS((unsigned long long*)&t.slots[idx], (unsigned long long)expect,
-                                 (unsigned long long)make_slot(k, 1u));
+                                 (unsigned long long)make_slot(k, inc));
     if (r == expect) {
       ++added;
       record(idx, 0u);
@@ -168,19 +173,40 @@ struct BlTicket {
   __device__ __forceinline__ void end() {}  // the size counts values (phase 3)
 };
 
+// n_dev non-NULL: the element count is *n_dev (runs counted on the device).
 template <int G, int W>
 __global__ __launch_bounds__(BLOCK) void k_bl_ticket(TableView t, WorkCtl ctl, BucketView b,
-                                                     const uint32_t* __restrict__ keys, uint64_t n,
+                                                     const uint32_t* __restrict__ keys,
+                                                     const uint32_t* __restrict__ incr, uint64_t n,
+                                                     const uint64_t* __restrict__ n_dev,
                                                      uint64_t* __restrict__ pos, uint32_t* __restrict__ ticket,
                                                      uint8_t* __restrict__ st) {
   BlTicket<G, W> op;
   op.t = t;
   op.b = b;
   op.keys = keys;
+  op.incr = incr;
   op.pos = pos;
   op.ticket = ticket;
   op.st = st;
-  drive<G>(n, ctl, op);
+  drive<G>(n_dev != nullptr ? *n_dev : n, ctl, op);
+}
+
+// Pair j of a sorted batch takes the ticket of its run plus its rank in the run.
+// scan: exclusive scan of the run-start flags (scan[j + 1] - 1 = run of j).
+__global__ __launch_bounds__(256) void k_bl_expand(const uint64_t* __restrict__ scan,
+                                                   const uint64_t* __restrict__ starts, uint64_t n,
+                                                   const uint64_t* __restrict__ rpos,
+                                                   const uint32_t* __restrict__ rticket,
+                                                   const uint8_t* __restrict__ rst, uint64_t* __restrict__ pos,
+                                                   uint32_t* __restrict__ ticket, uint8_t* __restrict__ st) {
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  for (uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += stride) {
+    const uint64_t r = scan[j + 1] - 1;
+    st[j] = rst[r];
+    pos[j] = rpos[r];
+    ticket[j] = rticket[r] + (uint32_t)(j - starts[r]);
+  }
 }
 
 // ---- phase 2: buckets per touched key -------------------------------------------------
@@ -441,17 +467,39 @@ hc_err launch_bl_insert(const TableView& t, const BucketView& b, uint32_t G, uin
   uint64_t* pos = (uint64_t*)p; p += align256(8 * n);
   uint32_t* ticket = (uint32_t*)p; p += align256(4 * n);
   uint8_t* st = (uint8_t*)p;
-  hc_err r = dispatch_gw(G, W, [&](auto g, auto w) -> hc_err {
+  hc_err r = launch_bl_tickets(t, b, G, W, keys, nullptr, n, nullptr, pos, ticket, st, s);
+  if (r != HC_OK) return r;
+  return launch_bl_finish(t, b, values, n, pos, ticket, st, status, s);
+}
+
+hc_err launch_bl_tickets(const TableView& t, const BucketView& b, uint32_t G, uint32_t W, const uint32_t* keys,
+                         const uint32_t* incr, uint64_t n, const uint64_t* n_dev, uint64_t* pos, uint32_t* ticket,
+                         uint8_t* st, hipStream_t s) {
+  return dispatch_gw(G, W, [&](auto g, auto w) -> hc_err {
     constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
     auto k = k_bl_ticket<GG, WW>;
     const unsigned grid = grid_for(k, n, GG);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid), b, keys, n, pos, ticket, st);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n_dev ? n / 8 : n, GG, grid), b, keys, incr,
+                       n, n_dev, pos, ticket, st);
     return check_launch("bucket list tickets");
   });
-  if (r != HC_OK) return r;
+}
+
+hc_err launch_bl_expand(const uint64_t* scan, const uint64_t* starts, uint64_t n, const uint64_t* rpos,
+                        const uint32_t* rticket, const uint8_t* rst, uint64_t* pos, uint32_t* ticket, uint8_t* st,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_bl_expand, dim3(stream_grid(n)), dim3(256), 0, s, scan, starts, n, rpos, rticket, rst, pos,
+                     ticket, st);
+  return check_launch("bucket list tickets of pairs");
+}
+
+hc_err launch_bl_finish(const TableView& t, const BucketView& b, const uint32_t* values, uint64_t n,
+                        const uint64_t* pos, const uint32_t* ticket, const uint8_t* st, uint8_t* status,
+                        hipStream_t s) {
   hipLaunchKernelGGL(k_bl_alloc, dim3(stream_grid(n)), dim3(256), 0, s, t, b);
-  if ((r = check_launch("bucket list allocation")) != HC_OK) return r;
-  hipLaunchKernelGGL(k_bl_place, dim3(stream_grid(n)), dim3(256), 0, s, t, b, values, n, pos, ticket, st, status);
+  if (hc_err r = check_launch("bucket list allocation"); r != HC_OK) return r;
+  hipLaunchKernelGGL(k_bl_place, dim3(stream_grid(n)), dim3(256), 0, s, t, b, values, n, pos, ticket,
+                     const_cast<uint8_t*>(st), status);
   return check_launch("bucket list values");
 }
 

@@ -40,6 +40,18 @@ bool bucket_ramp(uint32_t s0, double growth, uint32_t smax, uint64_t* cum, uint3
 uint64_t bl_insert_workspace(uint64_t n);
 hc_err launch_bl_insert(const TableView& t, const BucketView& b, uint32_t G, uint32_t W, const uint32_t* keys,
                         const uint32_t* values, uint64_t n, uint8_t* status, void* ws, hipStream_t s);
+// The phases separately (grouped insert): tickets of n elements (n_dev non-NULL: *n_dev
+// elements, n an upper bound) with incr[i] values each (NULL: 1); tickets of the pairs of a
+// sorted batch from those of its runs; allocation and placement.
+hc_err launch_bl_tickets(const TableView& t, const BucketView& b, uint32_t G, uint32_t W, const uint32_t* keys,
+                         const uint32_t* incr, uint64_t n, const uint64_t* n_dev, uint64_t* pos, uint32_t* ticket,
+                         uint8_t* st, hipStream_t s);
+hc_err launch_bl_expand(const uint64_t* scan, const uint64_t* starts, uint64_t n, const uint64_t* rpos,
+                        const uint32_t* rticket, const uint8_t* rst, uint64_t* pos, uint32_t* ticket, uint8_t* st,
+                        hipStream_t s);
+hc_err launch_bl_finish(const TableView& t, const BucketView& b, const uint32_t* values, uint64_t n,
+                        const uint64_t* pos, const uint32_t* ticket, const uint8_t* st, uint8_t* status,
+                        hipStream_t s);
 // Counts of keys (into offsets[i], and counts[i] when given), before the scan.
 hc_err launch_bl_count(const TableView& t, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n, uint32_t* counts,
                        uint64_t* offsets, hipStream_t s);

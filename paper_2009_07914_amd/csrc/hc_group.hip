@@ -31,6 +31,7 @@
 //     key that makes up a large part of a batch costs one atomic, not millions on
 //     the same slot.
 #include "hc_group.hpp"
+#include "hc_bucket.hpp"
 #include "hc_kernels.hpp"
 #include "hc_launch.hpp"
 #include "hc_sort.hpp"
@@ -973,6 +974,52 @@ hc_err launch_grouped_insert(const TableView& t, int kind, uint32_t G, uint32_t 
     hipLaunchKernelGGL(kc2, dim3(cgrid), dim3(GB), 0, s, t, ctl, kc, vc, starts, wk);
     return check_launch("walk claim");
   });
+}
+
+// Bucket list table, grouped: sort, one ticket per run (the run's length added to the
+// key's count with one atomic), pair tickets by rank in the run, then the bucket
+// allocation and placement of a plain bulk insert.
+uint64_t bl_grouped_workspace_bytes(uint64_t n) {
+  return 4 * align256(4 * n) + align256(8 * sort_pairs_workspace(n)) +
+         align256(8 * scan_tiles_needed(sort_pairs_workspace(n) > n + 1 ? sort_pairs_workspace(n) : n + 1)) +
+         align256(8 * (n + 1)) + align256(8 * (n + 2)) + 256 + 2 * (align256(8 * n) + align256(4 * n) + align256(n));
+}
+
+hc_err launch_bl_grouped(const TableView& t, const BucketView& b, uint32_t G, uint32_t W, const uint32_t* keys,
+                         const uint32_t* values, uint64_t n, void* work, hipStream_t s) {
+  if (n == 0) return HC_OK;
+  char* p = (char*)work;
+  uint32_t* kc = (uint32_t*)p; p += align256(4 * n);
+  uint32_t* vc = (uint32_t*)p; p += align256(4 * n);
+  uint32_t* kt = (uint32_t*)p; p += align256(4 * n);
+  uint32_t* vt = (uint32_t*)p; p += align256(4 * n);
+  const uint64_t hist_n = sort_pairs_workspace(n);
+  uint64_t* hist = (uint64_t*)p; p += align256(8 * hist_n);
+  uint64_t* tiles = (uint64_t*)p; p += align256(8 * scan_tiles_needed(hist_n > n + 1 ? hist_n : n + 1));
+  uint64_t* flags = (uint64_t*)p; p += align256(8 * (n + 1));
+  uint64_t* starts = (uint64_t*)p; p += align256(8 * (n + 2));
+  unsigned long long* nlists = (unsigned long long*)p; p += 256;
+  uint64_t* rpos = (uint64_t*)p; p += align256(8 * n);
+  uint32_t* rticket = (uint32_t*)p; p += align256(4 * n);
+  uint8_t* rst = (uint8_t*)p; p += align256(n);
+  uint64_t* pos = (uint64_t*)p; p += align256(8 * n);
+  uint32_t* ticket = (uint32_t*)p; p += align256(4 * n);
+  uint8_t* st = (uint8_t*)p;
+  hipError_t e = hipMemcpyAsync(kc, keys, 4 * n, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(vc, values, 4 * n, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return fail(HC_E_DEVICE, "grouped insert copy: %s", hipGetErrorString(e));
+  if (hc_err r = sort_pairs(kc, vc, kt, vt, n, hist, tiles, s); r != HC_OK) return r;
+  const unsigned g256 = (unsigned)((n + 256) / 256);
+  hipLaunchKernelGGL(k_run_flags, dim3(g256), dim3(256), 0, s, kc, n, flags, nlists);
+  if (hc_err r = check_launch("run flags"); r != HC_OK) return r;
+  if (hc_err r = exclusive_scan_inplace(flags, n, tiles, s); r != HC_OK) return r;
+  hipLaunchKernelGGL(k_run_starts, dim3(g256), dim3(256), 0, s, flags, n, starts);
+  if (hc_err r = check_launch("run starts"); r != HC_OK) return r;
+  hipLaunchKernelGGL(k_run_lengths, dim3(g256), dim3(256), 0, s, kc, starts, flags + n, n, kt, vt);
+  if (hc_err r = check_launch("run lengths"); r != HC_OK) return r;
+  if (hc_err r = launch_bl_tickets(t, b, G, W, kt, vt, n, flags + n, rpos, rticket, rst, s); r != HC_OK) return r;
+  if (hc_err r = launch_bl_expand(flags, starts, n, rpos, rticket, rst, pos, ticket, st, s); r != HC_OK) return r;
+  return launch_bl_finish(t, b, vc, n, pos, ticket, st, nullptr, s);
 }
 
 hc_err launch_zero_u64(unsigned long long* p, uint32_t count, hipStream_t s) {

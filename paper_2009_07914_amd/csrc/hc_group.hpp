@@ -18,6 +18,12 @@ hc_err launch_grouped_insert(const TableView& t, int kind, uint32_t G, uint32_t 
                              const uint32_t* values, uint64_t n, void* ws, hipStream_t s);
 hc_err launch_zero_u64(unsigned long long* p, uint32_t count, hipStream_t s);
 
+struct BucketView;
+// Grouped insert into a bucket list table (one ticket per run of equal keys).
+uint64_t bl_grouped_workspace_bytes(uint64_t n);
+hc_err launch_bl_grouped(const TableView& t, const BucketView& b, uint32_t G, uint32_t W, const uint32_t* keys,
+                         const uint32_t* values, uint64_t n, void* work, hipStream_t s);
+
 // Queries handed over by the count (mode 0) or write (mode 1) pass after `budget`
 // windows, and the state of the rounds that finish them, all in one workspace.
 struct LongState {

@@ -206,6 +206,16 @@ static BucketView bview_of(const hc_table_s* t) {
   return b;
 }
 
+// A new insert batch of a bucket list table: next batch number, no touched keys yet.
+static hc_err next_bucket_batch(hc_table_s* t, hipStream_t s) {
+  if (t->epoch == 0xFFFFFFFEu) {  // batch numbers run out: restart them on fresh stamps
+    if (hc_err r = launch_bl_reset(bview_of(t), t->C, s); r != HC_OK) return r;
+    t->epoch = 0;
+  }
+  ++t->epoch;
+  return launch_zero_u64(t->d_size + 2, 1, s);
+}
+
 static TableView view_of(const hc_table_s* t) {
   TableView v;
   v.slots = t->slots;
@@ -633,13 +643,8 @@ hc_err hc_insert(hc_table t, const uint32_t* d_keys, const uint32_t* d_values, u
   if ((r = set_device(t)) != HC_OK) return r;
   if (t->kind == HC_BUCKET_LIST) {
     hipStream_t s = (hipStream_t)stream;
-    if (t->epoch == 0xFFFFFFFEu) {  // batch numbers run out: restart them on fresh stamps
-      if ((r = launch_bl_reset(bview_of(t), t->C, s)) != HC_OK) return r;
-      t->epoch = 0;
-    }
-    ++t->epoch;
+    if ((r = next_bucket_batch(t, s)) != HC_OK) return r;
     if ((r = ensure_ws(t, bl_insert_workspace(n))) != HC_OK) return r;
-    if ((r = launch_zero_u64(t->d_size + 2, 1, s)) != HC_OK) return r;  // touched keys of this batch
     return launch_bl_insert(view_of(t), bview_of(t), g, t->window, d_keys, d_values, n, d_status, t->d_ws, s);
   }
   return launch_insert(view_of(t), (int)t->kind, g, t->window, d_keys, d_values, n, d_status, (hipStream_t)stream);
@@ -752,8 +757,8 @@ hc_err hc_retrieve_all(hc_table t, const uint32_t* d_keys, uint64_t n, const uin
 hc_err hc_insert_grouped(hc_table t, const uint32_t* d_keys, const uint32_t* d_values, uint64_t n, void* stream) {
   hc_err r = check_table(t);
   if (r != HC_OK) return r;
-  if (t->kind == HC_SINGLE_VALUE || t->kind == HC_BUCKET_LIST)
-    return fail(HC_E_KIND, "grouped insert needs a multi-value or counting table");
+  if (t->kind == HC_SINGLE_VALUE)
+    return fail(HC_E_KIND, "grouped insert needs a multi-value, counting or bucket list table");
   if (n == 0) return HC_OK;
   if (d_keys == nullptr) return fail(HC_E_ARG, "keys is NULL");
   if (t->kind == HC_COUNTING) {
@@ -763,6 +768,12 @@ hc_err hc_insert_grouped(hc_table t, const uint32_t* d_keys, const uint32_t* d_v
   }
   if (n > 0xFFFFFFFFull) return fail(HC_E_ARG, "grouped insert takes at most 2^32-1 pairs");
   if ((r = set_device(t)) != HC_OK) return r;
+  if (t->kind == HC_BUCKET_LIST) {
+    hipStream_t s = (hipStream_t)stream;
+    if ((r = next_bucket_batch(t, s)) != HC_OK) return r;
+    if ((r = ensure_ws(t, bl_grouped_workspace_bytes(n))) != HC_OK) return r;
+    return launch_bl_grouped(view_of(t), bview_of(t), t->group, t->window, d_keys, d_values, n, t->d_ws, s);
+  }
   if ((r = ensure_ws(t, grouped_workspace_bytes(n))) != HC_OK) return r;
   return launch_grouped_insert(view_of(t), (int)t->kind, t->group, t->window, d_keys, d_values, n, t->d_ws,
                                (hipStream_t)stream);

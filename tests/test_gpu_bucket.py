@@ -152,12 +152,32 @@ def test_bucket_list_reserved_keys_and_full(hc):
     assert int((st2 == hc.S_OK).sum()) == t2.capacity and t2.size() == t2.capacity
 
 
+@pytest.mark.parametrize("window,group", [(16, 4), (8, 1), (64, 16)])
+def test_bucket_list_grouped_insert(hc, window, group):
+    """Grouped batches (one ticket per run) mixed with per-pair batches: same lists, same multiset."""
+    w = gen.multi_value_zipf_workload(1 << 17, 1 << 10, 1.1, 101 + window)
+    t = hc.Table("bucket", 1 << 11, scheme="double", window=window, group=group,
+                 bucket=dict(s0=2, growth=1.5, smax=4096, pool_values=1 << 19))
+    orc = oracle.OracleTable(oracle.MULTI, 1 << 20)
+    parts = np.array_split(np.arange(w["keys"].size), 3)
+    hc.hc_insert_grouped(t.handle, d(w["keys"][parts[0]]), d(w["values"][parts[0]]))
+    orc.insert(w["keys"][parts[0]], w["values"][parts[0]])
+    assert np.all(h(t.insert(d(w["keys"][parts[1]]), d(w["values"][parts[1]]), status=True)) == hc.S_OK)
+    orc.insert(w["keys"][parts[1]], w["values"][parts[1]])
+    hc.hc_insert_grouped(t.handle, d(w["keys"][parts[2]]), d(w["values"][parts[2]]))
+    orc.insert(w["keys"][parts[2]], w["values"][parts[2]])
+    assert t.size() == w["keys"].size
+    _parity(t, orc, w["queries"])
+    _check_lists(t, orc, w["keys"])
+    # reserved keys in a grouped batch are skipped
+    k = np.array([0, 0xFFFFFFFF, 0, 7], np.uint32)
+    hc.hc_insert_grouped(t.handle, d(k), d(k))
+    assert t.size() == w["keys"].size + 1
+
+
 def test_bucket_list_rejects_other_calls(hc):
     t = hc.Table("bucket", 1024)
     k = d(np.arange(1, 10, dtype=np.uint32))
-    with pytest.raises(hc.HcError) as e:
-        hc.hc_insert_grouped(t.handle, k, k)
-    assert e.value.code == hc.E_KIND
     with pytest.raises(hc.HcError) as e:
         t.insert(k, None)
     assert e.value.code == hc.E_ARG
