@@ -38,10 +38,11 @@ KERNEL_NAMES = {"insert": "k_insert_unique", "retrieve": "k_retrieve"}
 def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="single", choices=["single", "batched", "serving", "multi", "sweep"],
+    ap.add_argument("--workload", default="single", choices=["single", "batched", "serving", "multi", "sweep", "bucket"],
                     help="single: the 2^28-slot table (default); batched: 256 tables in one launch; "
                          "serving: Poisson request stream on 16 resident tables; multi: counting and "
-                         "multi-value tables; sweep: load x scheme x group size on the 2^28-slot table")
+                         "multi-value tables; sweep: load x scheme x group size on the 2^28-slot table; "
+                         "bucket: bucket list tables on the multi-value workloads")
     ap.add_argument("--loads", default="0.5,0.8,0.9,0.95,0.99", help="sweep: load factors")
     ap.add_argument("--requests", type=int, default=1500)
     ap.add_argument("--max-log2-request", type=int, default=24)
@@ -121,6 +122,8 @@ def main():
         return bench_serving(args)
     if args.workload == "sweep":
         return bench_sweep(args)
+    if args.workload == "bucket":
+        return bench_bucket(args)
     if args.workload == "multi":
         return bench_multi(args)
     import numpy as np
@@ -497,6 +500,104 @@ def bench_multi(args):
                                "multi-value: keys uniform on 1..2^26/r, queries 1..2^26; "
                                "skewed multi-value: Zipf(1.1) over 2^22 keys, grouped insert",
                    "capacity": cap, "pairs": n},
+        "modes": res,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_bucket(args):
+    """Bucket list tables (s0 = 1, growth 2) on the multi-value workloads: 2^26 pairs with keys uniform on
+    1..2^26/r, and 2^26 pairs Zipf(1.1) over 2^22 keys.  Insert (per pair and grouped), count + prefix sum,
+    retrieve-all of every key; storage density = 4 bytes per distinct key and per value over the table's key slots,
+    last-bucket offsets and used pool words (a multi-value table of 2^27 slots holding the same pairs has
+    4 (keys + 2^26) / 2^30)."""
+    import numpy as np
+    import torch
+
+    lib = os.path.join(ROOT, "paper_2009_07914_amd", "libhc.so")
+    if not os.path.exists(lib):
+        import __graft_entry__
+        __graft_entry__.build()
+    import gen
+    import paper_2009_07914_amd as hc
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    s = torch.cuda.current_stream()
+    n = 1 << 26
+    reps = args.warmup + args.steps
+
+    def ev_time(fn, count):
+        ms = []
+        for _ in range(count):
+            if fn[0]:
+                fn[0]()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            fn[1]()
+            b.record(s)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        return ms
+
+    def check(w, q, offs, out):
+        off = offs.cpu().numpy().astype(np.int64)
+        assert int(off[-1]) == n, "sum of counts must equal the number of stored pairs"
+        order = np.lexsort((w["values"], w["keys"]))
+        sk, sv = w["keys"][order], w["values"][order]
+        o = out.cpu().numpy()
+        qh = q.cpu().numpy()
+        heavy = np.argsort(np.diff(off))[-4:]
+        for qi in np.concatenate([heavy, np.linspace(0, qh.size - 1, 1000).astype(np.int64)]):
+            lo, hi = np.searchsorted(sk, qh[qi], "left"), np.searchsorted(sk, qh[qi], "right")
+            assert np.array_equal(np.sort(o[off[qi]:off[qi + 1]]), sv[lo:hi]), "segment disagrees"
+
+    res = {}
+    cases = [(f"uniform_r{r}", gen.multi_value_uniform_r_workload(n, r, gen.SEED_BASE + 20 + r), n // r)
+             for r in (1, 4, 16, 64)]
+    cases.append(("zipf", gen.multi_value_zipf_workload(n, 1 << 22, 1.1, gen.SEED_BASE + 3), 1 << 22))
+    for name, w, distinct in cases:
+        keys = torch.from_numpy(w["keys"]).to(dev)
+        vals = torch.from_numpy(w["values"]).to(dev)
+        q = torch.from_numpy(w["queries"]).to(dev)
+        cap = int(distinct / 0.8)
+        t = hc.Table("bucket", cap, scheme="double", window=16, group=4, device=dev,
+                     bucket=dict(s0=1, growth=2.0, smax=1 << 16, pool_values=3 * n))
+        row = {}
+        if name != "zipf":  # per pair: the Zipf batch's hottest key would take 8 M atomics on one slot
+            ins = ev_time((t.clear, lambda: hc.hc_insert(t.handle, keys, vals, None, 4, s)), reps)[args.warmup:]
+            row["insert_ms"] = round(statistics.mean(ins), 4)
+        gins = ev_time((t.clear, lambda: hc.hc_insert_grouped(t.handle, keys, vals, s)), reps)[args.warmup:]
+        row["insert_grouped_ms"] = round(statistics.mean(gins), 4)
+        assert t.size() == n
+        offs = torch.empty(q.numel() + 1, dtype=torch.uint64, device=dev)
+        out = torch.empty(n, dtype=torch.uint32, device=dev)
+        cnt = ev_time((None, lambda: hc.hc_count_values(t.handle, q, offs, None, False, 4, s)), reps)[args.warmup:]
+        wr = ev_time((None, lambda: hc.hc_retrieve_all(t.handle, q, offs, out, 4, s)), reps)[args.warmup:]
+        check(w, q, offs, out)
+        u = t.bucket_usage()
+        st = t.stats()
+        # stored information (each distinct key once, each value once, 32 bits each) over the table's key slots,
+        # last-bucket offsets and used pool words
+        density = (4.0 * (int(st["live"]) + n)) / (8.0 * t.capacity + 4.0 * t.capacity + 4.0 * u["pool_used"])
+        best_ins = min(row.get("insert_ms", 1e9), row["insert_grouped_ms"])
+        row.update({"count_scan_ms": round(statistics.mean(cnt), 4), "write_ms": round(statistics.mean(wr), 4),
+                    "insert_gops": round(n / best_ins / 1e6, 4),
+                    "retrieve_all_gops": round(n / (statistics.mean(cnt) + statistics.mean(wr)) / 1e6, 4),
+                    "keys": int(st["live"]), "pool_used_words": int(u["pool_used"]),
+                    "storage_density": round(density, 4)})
+        res[name] = row
+        print("# " + json.dumps({name: row}), flush=True)
+        del t, keys, vals, q, offs, out, w
+        torch.cuda.empty_cache()
+    out = {
+        "metric": "G pairs/s of bucket list tables (insert; count / prefix sum / retrieve-all) and storage density",
+        "value": res["zipf"]["retrieve_all_gops"], "unit": "G ops/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "bucket list tables (s0 1, growth 2, cap 2^16) for 2^26 uint32 pairs: keys uniform on "
+                               "1..2^26/r, and Zipf(1.1) over 2^22 keys; key table at load 0.8 of the distinct keys",
+                   "pairs": n},
         "modes": res,
     }
     print(json.dumps(out), flush=True)

@@ -15,12 +15,12 @@
 //      else adding 1 to the count with one 64-bit atomic): the count before the
 //      add is the pair's ticket, its rank among all values of the key.  The first
 //      ticket of each key in the batch is recorded with an atomic minimum on a
-//      per-slot stamp tagged with the batch number, whose first writer also lists
-//      the key as touched;
-//   2. for every touched key one thread takes the buckets its new tickets need
-//      from the pool in one allocation, links them (previous-bucket offsets) and
-//      moves `last`; if the pool is exhausted the count is cut back to what the
-//      existing buckets hold (a key left with none becomes a tombstone);
+//      per-slot stamp tagged with the batch number;
+//   2. the pair holding that first ticket takes the buckets the key's new tickets
+//      need from the pool in one allocation (one pool atomic per wavefront),
+//      links them (previous-bucket offsets) and moves `last`; if the pool is
+//      exhausted the count is cut back to what the existing buckets hold (a key
+//      left with none becomes a tombstone);
 //   3. every pair writes its value where its ticket falls: ticket t lies in the
 //      bucket i with S(i) <= t < S(i+1), S(i) = s_0 + ... + s_{i-1}.
 // Values of a key therefore appear in its list in ticket order.
@@ -101,9 +101,7 @@ struct BlTicket {
     pos[i] = idx;
     ticket[i] = tk;
     st[i] = ST_OK;
-    const unsigned long long mark = ((unsigned long long)(~b.epoch) << 32) | tk;
-    const unsigned long long old = atomicMin(b.stamp + idx, mark);
-    if ((uint32_t)(old >> 32) != ~b.epoch) b.touched[atomicAdd(b.touched_n, 1ull)] = idx;  // first of this batch
+    atomicMin(b.stamp + idx, ((unsigned long long)(~b.epoch) << 32) | tk);  // older batches compare larger
   }
   __device__ __forceinline__ void add_one(uint64_t idx) {  // `inc` more values (tickets old .. old + inc - 1)
     const uint64_t old = atomicAdd((unsigned long long*)&t.slots[idx], (unsigned long long)inc << 32);
@@ -209,39 +207,65 @@ __global__ __launch_bounds__(256) void k_bl_expand(const uint64_t* __restrict__ 
   }
 }
 
-// ---- phase 2: buckets per touched key -------------------------------------------------
+// ---- phase 2: buckets per key -----------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_bl_alloc(TableView t, BucketView b) {
-  const uint64_t T = *b.touched_n;
+// Run by every pair; the pair whose ticket is its key's first of the batch
+// allocates.  Pool words are taken with one atomic per wavefront.
+__global__ __launch_bounds__(256) void k_bl_alloc(TableView t, BucketView b, uint64_t n,
+                                                  const uint64_t* __restrict__ pos,
+                                                  const uint32_t* __restrict__ ticket,
+                                                  const uint8_t* __restrict__ st) {
   const uint64_t stride = (uint64_t)gridDim.x * 256;
-  for (uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x; e < T; e += stride) {
-    const uint64_t p = b.touched[e];
-    const uint64_t c0 = (uint32_t)b.stamp[p];  // first ticket of this batch = count before it
-    const uint64_t word = t.slots[p];
-    const uint64_t c1 = slot_value(word);     // count after phase 1
-    const uint64_t b0 = bl_buckets(b, c0), b1 = bl_buckets(b, c1);
-    const uint32_t old_last = b.last[p];
-    uint32_t first_new = 0xFFFFFFFFu;
-    if (b1 > b0) {
-      const uint64_t words = bl_words(b, b0, b1);
-      const unsigned long long base = atomicAdd(b.pool_next, (unsigned long long)words);
-      if (base + words > b.pool_cap || base + words > 0xFFFFFFFFull) {
-        // pool exhausted: keep what the existing buckets hold; a key left with no value leaves the table
-        const uint64_t keep = bl_S(b, b0);
-        atomicExch((unsigned long long*)&t.slots[p],
-                   (unsigned long long)(keep ? make_slot(slot_key(word), (uint32_t)keep) : WORD_TOMB));
-      } else {
-        uint64_t o = base, prev = old_last;
-        for (uint64_t i = b0; i < b1; ++i) {
-          if (i >= 1) b.pool[o] = (uint32_t)prev;
-          prev = o;
-          o += bl_S(b, i + 1) - bl_S(b, i) + (i >= 1 ? 1 : 0);
-        }
-        b.last[p] = (uint32_t)prev;
-        first_new = (uint32_t)base;
+  const uint32_t lane = __lane_id();
+  for (uint64_t i0 = (uint64_t)blockIdx.x * 256 + (threadIdx.x & ~63u); i0 < n; i0 += stride) {
+    const uint64_t i = i0 + lane;
+    uint64_t p = 0, word = 0, b0 = 0, b1 = 0, words = 0;
+    bool mine = false;
+    if (i < n && st[i] == ST_OK) {
+      p = pos[i];
+      const uint64_t c0 = (uint32_t)b.stamp[p];  // first ticket of this batch = count before it
+      mine = ticket[i] == c0;
+      if (mine) {
+        word = t.slots[p];
+        b0 = bl_buckets(b, c0);
+        b1 = bl_buckets(b, slot_value(word));  // count after phase 1
+        words = bl_words(b, b0, b1);
       }
     }
-    b.batch[p] = (uint64_t)old_last | ((uint64_t)first_new << 32);
+    // wavefront-wide exclusive scan of the words, one pool atomic
+    uint64_t incl = words;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t lo = __shfl_up((uint32_t)incl, d, 64), hi = __shfl_up((uint32_t)(incl >> 32), d, 64);
+      if (lane >= (uint32_t)d) incl += (uint64_t)lo | ((uint64_t)hi << 32);
+    }
+    const uint64_t total = ((uint64_t)__shfl((uint32_t)(incl >> 32), 63, 64) << 32) | __shfl((uint32_t)incl, 63, 64);
+    unsigned long long wbase = 0;
+    if (lane == 63 && total) wbase = atomicAdd(b.pool_next, (unsigned long long)total);
+    wbase = ((uint64_t)__shfl((uint32_t)(wbase >> 32), 63, 64) << 32) | __shfl((uint32_t)wbase, 63, 64);
+    if (mine) {
+      const uint32_t old_last = b.last[p];
+      uint32_t first_new = 0xFFFFFFFFu;
+      if (b1 > b0) {
+        const uint64_t base = wbase + incl - words;
+        if (base + words > b.pool_cap || base + words > 0xFFFFFFFFull) {
+          // pool exhausted: keep what the existing buckets hold; a key left with no value leaves the table
+          const uint64_t keep = bl_S(b, b0);
+          atomicExch((unsigned long long*)&t.slots[p],
+                     (unsigned long long)(keep ? make_slot(slot_key(word), (uint32_t)keep) : WORD_TOMB));
+        } else {
+          uint64_t o = base, prev = old_last;
+          for (uint64_t j = b0; j < b1; ++j) {
+            if (j >= 1) b.pool[o] = (uint32_t)prev;
+            prev = o;
+            o += bl_S(b, j + 1) - bl_S(b, j) + (j >= 1 ? 1 : 0);
+          }
+          b.last[p] = (uint32_t)prev;
+          first_new = (uint32_t)base;
+        }
+      }
+      b.batch[p] = (uint64_t)old_last | ((uint64_t)first_new << 32);
+    }
   }
 }
 
@@ -290,6 +314,8 @@ struct BlProbe {
   uint32_t* __restrict__ counts;
   uint64_t* __restrict__ offsets;
   uint32_t* __restrict__ out;
+  unsigned long long* long_n = nullptr;  // lists longer than BL_LONG_LIST values: (query, slot, count)
+  uint64_t* long_list = nullptr;
   uint64_t i = 0, base_nx = 0, end_nx = 0, base = 0, limit = 0;
   uint32_t k = 0, lbase = 0, k_nx = 0;
   Seq s{};
@@ -316,6 +342,15 @@ struct BlProbe {
       }
     } else {
       if (c == 0 || limit == 0) return true;
+      if (c > BL_LONG_LIST) {  // copied by a whole block
+        if (ln.g.glane == 0) {
+          const unsigned long long e = atomicAdd(long_n, 1ull);
+          long_list[3 * e] = i;
+          long_list[3 * e + 1] = p;
+          long_list[3 * e + 2] = c;
+        }
+        return true;
+      }
       uint64_t bi = bl_bucket_of(b, c - 1);
       uint64_t o = b.last[p];
       for (;;) {
@@ -356,7 +391,8 @@ template <int G, int W, bool WRITE>
 __global__ __launch_bounds__(BLOCK) void k_bl_probe(TableView t, WorkCtl ctl, BucketView b,
                                                     const uint32_t* __restrict__ keys, uint64_t n,
                                                     uint32_t* __restrict__ counts, uint64_t* __restrict__ offsets,
-                                                    uint32_t* __restrict__ out) {
+                                                    uint32_t* __restrict__ out, unsigned long long* long_n,
+                                                    uint64_t* long_list) {
   BlProbe<G, W, WRITE> op;
   op.t = t;
   op.b = b;
@@ -364,7 +400,45 @@ __global__ __launch_bounds__(BLOCK) void k_bl_probe(TableView t, WorkCtl ctl, Bu
   op.counts = counts;
   op.offsets = offsets;
   op.out = out;
+  op.long_n = long_n;
+  op.long_list = long_list;
   drive<G>(n, ctl, op);
+}
+
+// Long lists: one block per list walks it back from the last bucket, all its
+// threads copying each bucket's values.
+__global__ __launch_bounds__(1024) void k_bl_write_long(BucketView b, const uint64_t* __restrict__ offsets,
+                                                        uint32_t* __restrict__ out, WorkCtl ctl,
+                                                        const unsigned long long* __restrict__ long_n,
+                                                        const uint64_t* __restrict__ long_list) {
+  __shared__ unsigned long long s_item;
+  const uint64_t L = *long_n;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(ctl.counters, 1ull);
+    __syncthreads();
+    const uint64_t e = s_item;
+    __syncthreads();
+    if (e >= L) break;
+    const uint64_t i = long_list[3 * e], p = long_list[3 * e + 1], c = long_list[3 * e + 2];
+    const uint64_t base = offsets[i], limit = offsets[i + 1] - base;
+    uint64_t bi = bl_bucket_of(b, c - 1);
+    uint64_t o = b.last[p];
+    for (;;) {
+      const uint64_t lo = bl_S(b, bi), hi = bl_S(b, bi + 1) < c ? bl_S(b, bi + 1) : c;
+      const uint64_t v0 = o + (bi >= 1 ? 1 : 0);
+      for (uint64_t j = threadIdx.x; j < hi - lo; j += 1024)
+        if (lo + j < limit) out[base + lo + j] = b.pool[v0 + j];  // never leave the segment
+      if (bi == 0) break;
+      o = b.pool[o];
+      --bi;
+    }
+  }
+  if (threadIdx.x == 0) {
+    if (atomicAdd(ctl.counters + 1, 1ull) == (unsigned long long)gridDim.x - 1) {
+      atomicExch(ctl.counters, 0ull);
+      atomicExch(ctl.counters + 1, 0ull);
+    }
+  }
 }
 
 // ---- erase: the key's slot becomes a tombstone, its values leave the count ------------
@@ -426,6 +500,10 @@ __global__ __launch_bounds__(BLOCK) void k_bl_erase(TableView t, WorkCtl ctl, co
   op.keys = keys;
   op.status = status;
   drive<G>(n, ctl, op);
+}
+
+__global__ __launch_bounds__(64) void k_bl_zero1(unsigned long long* p) {
+  if (threadIdx.x == 0) *p = 0ull;
 }
 
 __global__ __launch_bounds__(256) void k_bl_reset(unsigned long long* stamp, uint64_t C) {
@@ -496,7 +574,7 @@ hc_err launch_bl_expand(const uint64_t* scan, const uint64_t* starts, uint64_t n
 hc_err launch_bl_finish(const TableView& t, const BucketView& b, const uint32_t* values, uint64_t n,
                         const uint64_t* pos, const uint32_t* ticket, const uint8_t* st, uint8_t* status,
                         hipStream_t s) {
-  hipLaunchKernelGGL(k_bl_alloc, dim3(stream_grid(n)), dim3(256), 0, s, t, b);
+  hipLaunchKernelGGL(k_bl_alloc, dim3(stream_grid(n)), dim3(256), 0, s, t, b, n, pos, ticket, st);
   if (hc_err r = check_launch("bucket list allocation"); r != HC_OK) return r;
   hipLaunchKernelGGL(k_bl_place, dim3(stream_grid(n)), dim3(256), 0, s, t, b, values, n, pos, ticket,
                      const_cast<uint8_t*>(st), status);
@@ -510,21 +588,35 @@ hc_err launch_bl_count(const TableView& t, uint32_t G, uint32_t W, const uint32_
     auto k = k_bl_probe<GG, WW, false>;
     const unsigned grid = grid_for(k, n, GG);
     hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid), BucketView{}, keys, n, counts,
-                       offsets, nullptr);
+                       offsets, nullptr, nullptr, nullptr);
     return check_launch("bucket list count");
   });
 }
 
+uint64_t bl_write_workspace(uint64_t n) { return 256 + 24 * n; }
+
 hc_err launch_bl_write(const TableView& t, const BucketView& b, uint32_t G, uint32_t W, const uint32_t* keys,
-                       uint64_t n, const uint64_t* offsets, uint32_t* out, hipStream_t s) {
-  return dispatch_gw(G, W, [&](auto g, auto w) -> hc_err {
+                       uint64_t n, const uint64_t* offsets, uint32_t* out, void* ws, hipStream_t s) {
+  unsigned long long* long_n = (unsigned long long*)ws;
+  uint64_t* long_list = (uint64_t*)((char*)ws + 256);
+  hipLaunchKernelGGL(k_bl_zero1, dim3(1), dim3(64), 0, s, long_n);
+  hc_err r = check_launch("bucket list write");
+  if (r != HC_OK) return r;
+  r = dispatch_gw(G, W, [&](auto g, auto w) -> hc_err {
     constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
     auto k = k_bl_probe<GG, WW, true>;
     const unsigned grid = grid_for(k, n, GG);
     hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid), b, keys, n, nullptr,
-                       const_cast<uint64_t*>(offsets), out);  // the write pass only reads offsets
+                       const_cast<uint64_t*>(offsets), out, long_n, long_list);  // the write pass only reads offsets
     return check_launch("bucket list write");
   });
+  if (r != HC_OK) return r;
+  const uint64_t cap = (uint64_t)device_cu_count() * (uint64_t)blocks_per_cu_threads(
+                           reinterpret_cast<const void*>(k_bl_write_long), 1024);
+  const unsigned grid = (unsigned)(cap < n ? cap : (n ? n : 1));
+  hipLaunchKernelGGL(k_bl_write_long, dim3(grid), dim3(1024), 0, s, b, offsets, out, work_for(0, 64, grid * 4), long_n,
+                     long_list);
+  return check_launch("bucket list long write");
 }
 
 hc_err launch_bl_erase(const TableView& t, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n, uint8_t* status,

@@ -25,8 +25,6 @@ struct BucketView {
   uint32_t* last;                  // per key slot: pool offset of the key's last bucket
   unsigned long long* stamp;       // per key slot: (~batch << 32) | first ticket of the key in that batch
   uint64_t* batch;                 // per key slot: old last bucket (low 32) | first new bucket (high 32)
-  unsigned long long* touched_n;   // keys touched by the current batch
-  uint64_t* touched;               // their slot indices
   uint32_t epoch;                  // batch number (1 ..)
 };
 
@@ -55,9 +53,12 @@ hc_err launch_bl_finish(const TableView& t, const BucketView& b, const uint32_t*
 // Counts of keys (into offsets[i], and counts[i] when given), before the scan.
 hc_err launch_bl_count(const TableView& t, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n, uint32_t* counts,
                        uint64_t* offsets, hipStream_t s);
-// Values of keys into out[offsets[i] .. offsets[i+1]).
+// Values of keys into out[offsets[i] .. offsets[i+1]); lists longer than BL_LONG_LIST
+// values are copied by whole blocks.  Workspace: bl_write_workspace(n) bytes.
+constexpr uint64_t BL_LONG_LIST = 1024;
+uint64_t bl_write_workspace(uint64_t n);
 hc_err launch_bl_write(const TableView& t, const BucketView& b, uint32_t G, uint32_t W, const uint32_t* keys,
-                       uint64_t n, const uint64_t* offsets, uint32_t* out, hipStream_t s);
+                       uint64_t n, const uint64_t* offsets, uint32_t* out, void* ws, hipStream_t s);
 hc_err launch_bl_erase(const TableView& t, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n, uint8_t* status,
                        hipStream_t s);
 // stamp[0..C) = ~0 (a fill kernel).

@@ -50,7 +50,6 @@ struct hc_table_s {
   uint32_t* d_last = nullptr;
   unsigned long long* d_stamp = nullptr;
   uint64_t* d_batch = nullptr;
-  uint64_t* d_touched = nullptr;
   uint32_t epoch = 0;
 };
 
@@ -196,24 +195,22 @@ static BucketView bview_of(const hc_table_s* t) {
   b.smax = t->bl_smax;
   b.pool = t->d_pool;
   b.pool_cap = t->pool_cap;
-  b.pool_next = t->d_size + 1;  // size counter, pool counter, touched-key counter share one allocation
+  b.pool_next = t->d_size + 1;  // the size counter and the pool counter share one allocation
   b.last = t->d_last;
   b.stamp = t->d_stamp;
   b.batch = t->d_batch;
-  b.touched_n = t->d_size + 2;
-  b.touched = t->d_touched;
   b.epoch = t->epoch;
   return b;
 }
 
-// A new insert batch of a bucket list table: next batch number, no touched keys yet.
+// A new insert batch of a bucket list table: the next batch number.
 static hc_err next_bucket_batch(hc_table_s* t, hipStream_t s) {
   if (t->epoch == 0xFFFFFFFEu) {  // batch numbers run out: restart them on fresh stamps
     if (hc_err r = launch_bl_reset(bview_of(t), t->C, s); r != HC_OK) return r;
     t->epoch = 0;
   }
   ++t->epoch;
-  return launch_zero_u64(t->d_size + 2, 1, s);
+  return HC_OK;
 }
 
 static TableView view_of(const hc_table_s* t) {
@@ -520,7 +517,6 @@ hc_err hc_create_bucket_list(hc_table* out, uint64_t key_capacity, const hc_para
   if (e == hipSuccess) e = hipMalloc((void**)&t->d_last, t->C * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMalloc((void**)&t->d_stamp, t->C * sizeof(unsigned long long));
   if (e == hipSuccess) e = hipMalloc((void**)&t->d_batch, t->C * sizeof(uint64_t));
-  if (e == hipSuccess) e = hipMalloc((void**)&t->d_touched, t->C * sizeof(uint64_t));
   if (e != hipSuccess) {
     (void)hipGetLastError();
     hc_destroy(t);
@@ -599,8 +595,7 @@ hc_err hc_destroy(hc_table t) {
   if (t->d_size) (void)hipFree(t->d_size);
   if (t->d_tiles) (void)hipFree(t->d_tiles);
   if (t->d_ws) (void)hipFree(t->d_ws);
-  for (void* q : {(void*)t->d_cum, (void*)t->d_pool, (void*)t->d_last, (void*)t->d_stamp, (void*)t->d_batch,
-                  (void*)t->d_touched})
+  for (void* q : {(void*)t->d_cum, (void*)t->d_pool, (void*)t->d_last, (void*)t->d_stamp, (void*)t->d_batch})
     if (q) (void)hipFree(q);
   delete t;
   if (e != hipSuccess) return hip_fail(e, "hc_destroy: synchronise");
@@ -620,7 +615,7 @@ hc_err hc_clear(hc_table t, void* stream) {
                      reinterpret_cast<ulonglong2*>(t->slots), pairs, t->d_size);
   if ((r = check_launch("clear")) != HC_OK) return r;
   if (t->kind == HC_BUCKET_LIST && t->d_stamp != nullptr) {  // empty pool, fresh batch stamps (once allocated)
-    if ((r = launch_zero_u64(t->d_size + 1, 2, (hipStream_t)stream)) != HC_OK) return r;
+    if ((r = launch_zero_u64(t->d_size + 1, 1, (hipStream_t)stream)) != HC_OK) return r;
     if ((r = launch_bl_reset(bview_of(t), t->C, (hipStream_t)stream)) != HC_OK) return r;
     t->epoch = 0;
   }
@@ -741,8 +736,10 @@ hc_err hc_retrieve_all(hc_table t, const uint32_t* d_keys, uint64_t n, const uin
   if (d_keys == nullptr || d_offsets == nullptr) return fail(HC_E_ARG, "keys or offsets is NULL");
   if ((r = set_device(t)) != HC_OK) return r;
   hipStream_t s = (hipStream_t)stream;
-  if (t->kind == HC_BUCKET_LIST)
-    return launch_bl_write(view_of(t), bview_of(t), g, t->window, d_keys, n, d_offsets, d_values_out, s);
+  if (t->kind == HC_BUCKET_LIST) {
+    if ((r = ensure_ws(t, bl_write_workspace(n))) != HC_OK) return r;
+    return launch_bl_write(view_of(t), bview_of(t), g, t->window, d_keys, n, d_offsets, d_values_out, t->d_ws, s);
+  }
   if ((r = ensure_ws(t, long_workspace_bytes(n, 1))) != HC_OK) return r;
   const LongState ls = long_layout(t->d_ws, n, 1);
   if ((r = launch_zero_u64((unsigned long long*)ls.nlong, 1, s)) != HC_OK) return r;
