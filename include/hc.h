@@ -253,6 +253,12 @@ typedef struct {
 /* Synchronises the stream.  Errors: HC_E_ARG (NULL output), HC_E_NOMEM. */
 hc_err hc_stats(hc_table table, hc_table_stats* h_out, void* stream);
 
+/* The table's device view for user kernels (the device-side API in
+ * paper_2009_07914_amd/csrc/hc_device_api.hpp: hc::dev::insert / retrieve / erase / for_all,
+ * called by groups of G lanes from any kernel).  h_view receives a hc::TableView (defined in
+ * hc_device.hpp) by value; bytes must be its size.  The view stays valid until hc_destroy. */
+hc_err hc_device_view(hc_table table, void* h_view, uint64_t bytes);
+
 /* Copy the C slot words into caller memory d_dst (C uint64, device), on the stream. */
 hc_err hc_dump_slots(hc_table table, uint64_t* d_dst, void* stream);
 

@@ -17,7 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhc.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2009_07914_amd.build`")
+    raise ImportError(f"{LIB_PATH} is not built; run `python paper_2009_07914_amd/build.py` "
+                      "or `__graft_entry__.build()`")
 
 _lib = ctypes.CDLL(LIB_PATH)
 
@@ -98,6 +99,7 @@ _SIGS = {
                               ctypes.c_int),
     "hc_bucket_usage": ([_p, ctypes.POINTER(HcBucketUsage), _p], ctypes.c_int),
     "hc_dump_buckets": ([_p, _p, _p, _p], ctypes.c_int),
+    "hc_device_view": ([_p, _p, _u64], ctypes.c_int),
     "hc_destroy": ([_p], ctypes.c_int),
     "hc_clear": ([_p, _p], ctypes.c_int),
     "hc_insert": ([_p, _p, _p, _u64, _p, _u32, _p], ctypes.c_int),
@@ -234,6 +236,13 @@ def hc_bucket_usage(h: int, stream=None) -> HcBucketUsage:
 
 def hc_dump_buckets(h: int, pool, last, stream=None):
     _check(_lib.hc_dump_buckets(h, _u32t(pool, "pool"), _u32t(last, "last"), _stream(stream)), "hc_dump_buckets")
+
+
+def hc_device_view(h: int, nbytes: int) -> ctypes.Array:
+    """The table's device view (a hc::TableView, nbytes long) for kernels on the device-side API."""
+    buf = (ctypes.c_ubyte * nbytes)()
+    _check(_lib.hc_device_view(h, buf, nbytes), "hc_device_view")
+    return buf
 
 
 def hc_destroy(h: int):

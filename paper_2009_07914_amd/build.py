@@ -1,8 +1,9 @@
 """Build libhc.so (the HIP kernels and the C ABI) in-tree for gfx950.
 
 Each ``csrc/*.hip`` translation unit is compiled to an object in parallel, then
-linked into ``libhc.so`` next to this file.  Run as ``python -m
-paper_2009_07914_amd.build`` or through ``__graft_entry__.build()``.
+linked into ``libhc.so`` next to this file.  Run as ``python
+paper_2009_07914_amd/build.py`` or through ``__graft_entry__.build()`` (not through the
+package, whose import loads the library).
 """
 from __future__ import annotations
 

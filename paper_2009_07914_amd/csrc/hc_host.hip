@@ -845,6 +845,17 @@ hc_err hc_stats(hc_table t, hc_table_stats* h_out, void* stream) {
   return HC_OK;
 }
 
+hc_err hc_device_view(hc_table t, void* h_view, uint64_t bytes) {
+  hc_err r = check_table(t);
+  if (r != HC_OK) return r;
+  if (h_view == nullptr) return fail(HC_E_ARG, "view is NULL");
+  if (bytes != sizeof(TableView)) return fail(HC_E_ARG, "view takes %zu bytes, not %llu", sizeof(TableView),
+                                              (unsigned long long)bytes);
+  const TableView v = view_of(t);
+  std::memcpy(h_view, &v, sizeof v);
+  return HC_OK;
+}
+
 hc_err hc_dump_slots(hc_table t, uint64_t* d_dst, void* stream) {
   hc_err r = check_table(t);
   if (r != HC_OK) return r;

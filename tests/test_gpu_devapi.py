@@ -1,0 +1,96 @@
+"""The device-side API (hc_device_api.hpp) called from user kernels, against the oracle and numpy.
+
+The kernels live in tests/devapi/devapi_kernels.hip (built by __graft_entry__.build()): a fused
+k-mer counter that turns a DNA read into 2-bit k-mer codes and counts them in a counting table
+from inside one kernel, group lookups, group inserts and a for_all export.
+"""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from tests.gpu_util import check_layout, d, h
+
+pytestmark = pytest.mark.gpu
+
+LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "devapi", "libhc_devapi.so")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not os.path.exists(LIB):
+        raise RuntimeError("tests/devapi/libhc_devapi.so is not built: run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB)
+    lib.devapi_view_bytes.restype = ctypes.c_uint64
+    P = ctypes.c_void_p
+    lib.devapi_count_kmers.argtypes = [P, ctypes.c_uint32, P, ctypes.c_uint64, ctypes.c_uint32, P]
+    lib.devapi_lookup.argtypes = [P, ctypes.c_uint32, P, ctypes.c_uint64, P, P, P]
+    lib.devapi_insert.argtypes = [P, ctypes.c_uint32, P, P, ctypes.c_uint64, P, P]
+    lib.devapi_export.argtypes = [P, ctypes.c_uint32, P, P, P, P]
+    return lib
+
+
+def _view(hc, dev, t):
+    return hc.hc_device_view(t.handle, int(dev.devapi_view_bytes()))
+
+
+@pytest.mark.parametrize("k", [5, 12, 15])
+def test_fused_kmer_counting(hc, dev, k):
+    n = 200000
+    seq = (gen.values(300 + k, n) & 3).astype(np.uint8)  # a random read, bases 0..3
+    t = hc.Table("counting", 1 << 18, scheme="double", window=16, group=4)
+    s = torch.cuda.current_stream()
+    dseq = d(seq)
+    assert dev.devapi_count_kmers(_view(hc, dev, t), 16, dseq.data_ptr(), n, k, ctypes.c_void_p(s.cuda_stream)) == 0
+    torch.cuda.synchronize()
+    # numpy: codes of every window of the read, then counts per distinct code
+    w = np.lib.stride_tricks.sliding_window_view(seq.astype(np.uint64), k)
+    codes = (w * (4 ** np.arange(k - 1, -1, -1, dtype=np.uint64))).sum(axis=1).astype(np.uint64)
+    u, c = np.unique(codes + 1, return_counts=True)
+    assert t.size() == u.size
+    v, f = t.retrieve(d(u.astype(np.uint32)))
+    assert np.all(h(f) == 1) and np.array_equal(h(v), c.astype(np.uint32))
+    check_layout(t, oracle.COUNT)
+
+
+def test_device_insert_lookup_export(hc, dev):
+    w = gen.single_value_workload(1 << 16, 0.85, 17)
+    t = hc.Table("single", 1 << 16, scheme="quadratic", window=16, group=4)
+    orc = oracle.OracleTable(oracle.SINGLE, t.capacity)
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    keys = np.concatenate([w["keys"], w["keys"][:1000], np.array([0, 0xFFFFFFFF], np.uint32)])
+    vals = np.concatenate([w["values"], w["values"][:1000], np.array([1, 2], np.uint32)])
+    dk, dv = d(keys), d(vals)
+    st = torch.empty(keys.size, dtype=torch.uint8, device="cuda")
+    assert dev.devapi_insert(_view(hc, dev, t), 16, dk.data_ptr(), dv.data_ptr(), keys.size, st.data_ptr(), s) == 0
+    torch.cuda.synchronize()
+    # one copy of a repeated key reports OK, the other DUPLICATE; which one is unspecified within a launch
+    st, st_o = h(st), orc.insert(keys, vals)
+    order = np.lexsort((st, keys))
+    order_o = np.lexsort((st_o, keys))
+    assert np.array_equal(st[order], st_o[order_o])
+    assert t.size() == orc.size()
+    q = w["queries"]
+    out = torch.empty(q.size, dtype=torch.uint32, device="cuda")
+    fnd = torch.empty(q.size, dtype=torch.uint8, device="cuda")
+    dq = d(q)
+    assert dev.devapi_lookup(_view(hc, dev, t), 16, dq.data_ptr(), q.size, out.data_ptr(), fnd.data_ptr(), s) == 0
+    torch.cuda.synchronize()
+    vo, fo = orc.retrieve(q)
+    assert np.array_equal(h(out), vo) and np.array_equal(h(fnd), fo)
+    ek = torch.empty(t.capacity, dtype=torch.uint32, device="cuda")
+    ev = torch.empty(t.capacity, dtype=torch.uint32, device="cuda")
+    en = torch.zeros(1, dtype=torch.uint64, device="cuda")
+    assert dev.devapi_export(_view(hc, dev, t), 16, ek.data_ptr(), ev.data_ptr(), en.data_ptr(), s) == 0
+    torch.cuda.synchronize()
+    m = int(en.item())
+    assert m == orc.size()
+    ek, ev = h(ek)[:m], h(ev)[:m]
+    order = np.argsort(ek)
+    vo2, fo2 = orc.retrieve(ek[order])
+    assert np.all(fo2 == 1) and np.array_equal(vo2, ev[order])
+    check_layout(t, oracle.SINGLE)
