@@ -83,6 +83,20 @@ def _load():
         lib.orc_model_insert.argtypes = [p, u64, u32, i, u64, p, p, u64, p]
         lib.orc_model_insert.restype = u64
         lib.orc_model_lookup_windows.argtypes = [p, u64, u32, i, u64, p, u64, p]
+        lib.orc64_create.argtypes = [u64]
+        lib.orc64_create.restype = p
+        lib.orc64_destroy.argtypes = [p]
+        lib.orc64_size.argtypes = [p]
+        lib.orc64_size.restype = u64
+        lib.orc64_insert.argtypes = [p, p, p, u64, p]
+        lib.orc64_retrieve.argtypes = [p, p, u64, p, p]
+        lib.orc64_erase.argtypes = [p, p, u64, p]
+        lib.orc_fmix64.argtypes = [u64]
+        lib.orc_fmix64.restype = u64
+        lib.orc64_window_at.argtypes = [u64, u64, u64, i, u64]
+        lib.orc64_window_at.restype = u64
+        lib.orc64_check_layout.argtypes = [p, u64, u32, i, u64, p]
+        lib.orc64_check_layout.restype = i
         _lib = lib
     return _lib
 
@@ -212,3 +226,62 @@ def model_lookup_windows(slots: np.ndarray, P: int, W: int, scheme: int, seed: i
     _load().orc_model_lookup_windows(_ptr(slots), P, W, scheme, seed & (2**64 - 1), _ptr(keys), keys.size,
                                      _ptr(win))
     return win
+
+
+# ---- single-value table with 64-bit keys and values ----------------------------
+
+class OracleTable64:
+    """Bounded map uint64 -> uint64 with the single-value table's observable semantics."""
+
+    def __init__(self, capacity: int):
+        self._lib = _load()
+        self.capacity = int(capacity)
+        self._h = self._lib.orc64_create(self.capacity)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.orc64_destroy(h)
+            self._h = None
+
+    def size(self) -> int:
+        return int(self._lib.orc64_size(self._h))
+
+    def insert(self, keys, values) -> np.ndarray:
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        vals = np.ascontiguousarray(values, dtype=np.uint64)
+        status = np.empty(keys.size, dtype=np.uint8)
+        self._lib.orc64_insert(self._h, _ptr(keys), _ptr(vals), keys.size, _ptr(status))
+        return status
+
+    def retrieve(self, keys):
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        out = np.empty(keys.size, dtype=np.uint64)
+        found = np.empty(keys.size, dtype=np.uint8)
+        self._lib.orc64_retrieve(self._h, _ptr(keys), keys.size, _ptr(out), _ptr(found))
+        return out, found
+
+    def erase(self, keys) -> np.ndarray:
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        status = np.empty(keys.size, dtype=np.uint8)
+        self._lib.orc64_erase(self._h, _ptr(keys), keys.size, _ptr(status))
+        return status
+
+
+def fmix64(x: int) -> int:
+    return int(_load().orc_fmix64(x & (2**64 - 1)))
+
+
+def window_at64(key: int, l: int, P: int, scheme: int, seed: int) -> int:
+    return int(_load().orc64_window_at(key & (2**64 - 1), l, P, scheme, seed & (2**64 - 1)))
+
+
+def check_layout64(slots: np.ndarray, P: int, W: int, scheme: int, seed: int):
+    """slots: 2 * P * W uint64 words (key, value per slot).  Returns (error_code, stats dict)."""
+    slots = np.ascontiguousarray(slots, dtype=np.uint64)
+    assert slots.size == 2 * P * W
+    st = np.zeros(5, dtype=np.uint64)
+    rc = _load().orc64_check_layout(_ptr(slots), P, W, scheme, seed & (2**64 - 1), _ptr(st))
+    return int(rc), {"live": int(st[0]), "tombstones": int(st[1]), "max_windows": int(st[2]),
+                     "sum_windows": int(st[3]), "first_bad_slot": int(st[4])}
+

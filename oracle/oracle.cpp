@@ -420,4 +420,142 @@ void orc_model_lookup_windows(const uint64_t* slots, uint64_t P, uint32_t W, int
   }
 }
 
+/* ------------------------------------------------------------------------- *
+ * Single-value table with 64-bit keys and 64-bit values (the wider types the
+ * paper's tables are generic over, Sec. IV-B1 packed and AoS layouts).  Same
+ * semantics as the 32-bit single-value table; reserved keys 0 (empty) and
+ * 2^64 - 1 (tombstone).
+ * ------------------------------------------------------------------------- */
+
+struct Table64 {
+  uint64_t capacity;
+  std::unordered_map<uint64_t, uint64_t> map;
+};
+
+static bool reserved64(uint64_t k) { return k == 0 || k == ~0ull; }
+
+void* orc64_create(uint64_t capacity) {
+  Table64* t = new Table64();
+  t->capacity = capacity;
+  return t;
+}
+
+void orc64_destroy(void* h) { delete static_cast<Table64*>(h); }
+
+uint64_t orc64_size(void* h) { return static_cast<Table64*>(h)->map.size(); }
+
+void orc64_insert(void* h, const uint64_t* keys, const uint64_t* values, uint64_t n, uint8_t* status) {
+  Table64* t = static_cast<Table64*>(h);
+  for (uint64_t i = 0; i < n; ++i) {
+    const uint64_t k = keys[i];
+    uint8_t st;
+    if (reserved64(k)) {
+      st = ST_INVALID_KEY;
+    } else {
+      auto it = t->map.find(k);
+      if (it != t->map.end()) { it->second = values[i]; st = ST_DUPLICATE; }
+      else if (t->map.size() < t->capacity) { t->map.emplace(k, values[i]); st = ST_OK; }
+      else st = ST_FULL;
+    }
+    if (status) status[i] = st;
+  }
+}
+
+void orc64_retrieve(void* h, const uint64_t* keys, uint64_t n, uint64_t* values_out, uint8_t* found_out) {
+  Table64* t = static_cast<Table64*>(h);
+  for (uint64_t i = 0; i < n; ++i) {
+    uint64_t v = 0;
+    uint8_t f = 0;
+    if (!reserved64(keys[i])) {
+      auto it = t->map.find(keys[i]);
+      if (it != t->map.end()) { v = it->second; f = 1; }
+    }
+    values_out[i] = v;
+    found_out[i] = f;
+  }
+}
+
+void orc64_erase(void* h, const uint64_t* keys, uint64_t n, uint8_t* status) {
+  Table64* t = static_cast<Table64*>(h);
+  for (uint64_t i = 0; i < n; ++i) {
+    uint8_t st;
+    if (reserved64(keys[i])) st = ST_INVALID_KEY;
+    else st = t->map.erase(keys[i]) ? ST_OK : ST_NOT_FOUND;
+    if (status) status[i] = st;
+  }
+}
+
+/* MurmurHash3's 64-bit finaliser (Appleby, public domain). */
+uint64_t orc_fmix64(uint64_t x) {
+  x ^= x >> 33;
+  x *= 0xff51afd7ed558ccdull;
+  x ^= x >> 33;
+  x *= 0xc4ceb9fe1a85ec53ull;
+  x ^= x >> 33;
+  return x;
+}
+
+/* Window of sequence step l for a 64-bit key: h1 and h2 are the low and high
+ * halves of fmix64(k ^ seed); otherwise as orc_window_at. */
+uint64_t orc64_window_at(uint64_t k, uint64_t l, uint64_t P, int scheme, uint64_t seed) {
+  const uint64_t x = orc_fmix64(k ^ seed);
+  const uint64_t w0 = reduce((uint32_t)x, P);
+  if (scheme == SCHEME_LINEAR) return (w0 + l) % P;
+  if (scheme == SCHEME_QUADRATIC) {
+    unsigned __int128 tri = (unsigned __int128)l * (l + 1) / 2;
+    return (uint64_t)((w0 + tri) % P);
+  }
+  const uint32_t h2 = (uint32_t)(x >> 32);
+  uint64_t step;
+  if (is_pow2(P)) step = (h2 & (P - 1)) | 1u;
+  else step = 1 + (((uint64_t)h2 * (P - 1)) >> 32);
+  unsigned __int128 s = (unsigned __int128)l * step;
+  return (uint64_t)((w0 + s) % P);
+}
+
+/* Layout check of a dumped 64-bit table: P * W slots of two words (key, value).
+ * Codes as orc_check_layout: 1 bad encoding (empty or tombstone slot with a
+ * nonzero value word), 2 a key behind an empty slot of its sequence, 3 a key
+ * stored twice, 4 a key where its sequence never reaches.  stats as there. */
+int orc64_check_layout(const uint64_t* slots, uint64_t P, uint32_t W, int scheme, uint64_t seed, uint64_t* stats) {
+  uint64_t bad = ~0ull;
+  int code = 0;
+  auto note = [&](uint64_t i, int c) {
+    if (i < bad || (i == bad && c < code)) { bad = i; code = c; }
+  };
+  uint64_t live_n = 0, tombs = 0, maxw = 0, sumw = 0;
+  std::unordered_map<uint64_t, uint64_t> where;
+  const uint64_t C = P * W;
+  for (uint64_t i = 0; i < C; ++i) {
+    const uint64_t k = slots[2 * i], v = slots[2 * i + 1];
+    if (k == 0) { if (v != 0) note(i, 1); continue; }
+    if (k == ~0ull) { if (v != 0) note(i, 1); ++tombs; continue; }
+    ++live_n;
+    if (!where.emplace(k, i).second) { note(i, 3); continue; }
+  }
+  for (auto& kv : where) {
+    const uint64_t k = kv.first, i = kv.second, tw = i / W;
+    bool reached = false, empty_before = false;
+    for (uint64_t l = 0; l < P; ++l) {
+      const uint64_t w = orc64_window_at(k, l, P, scheme, seed);
+      const uint64_t jmax = (w == tw) ? i - w * W : W;
+      for (uint64_t j = 0; j < jmax && !empty_before; ++j) empty_before = slots[2 * (w * W + j)] == 0;
+      if (w == tw) {
+        if (empty_before) note(i, 2);
+        maxw = std::max<uint64_t>(maxw, l + 1);
+        sumw += l + 1;
+        reached = true;
+        break;
+      }
+    }
+    if (!reached) note(i, 4);
+  }
+  stats[0] = live_n;
+  stats[1] = tombs;
+  stats[2] = maxw;
+  stats[3] = sumw;
+  stats[4] = bad;
+  return code;
+}
+
 }  // extern "C"
