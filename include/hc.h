@@ -51,7 +51,7 @@ typedef struct hc_table_s* hc_table;
 
 /* Table kinds (Sec. IV: SingleValueHashTable, MultiValueHashTable, CountingHashTable,
  * BucketListHashTable; the last is made by hc_create_bucket_list). */
-enum { HC_SINGLE_VALUE = 0, HC_MULTI_VALUE = 1, HC_COUNTING = 2, HC_BUCKET_LIST = 3 };
+enum { HC_SINGLE_VALUE = 0, HC_MULTI_VALUE = 1, HC_COUNTING = 2, HC_BUCKET_LIST = 3, HC_SINGLE_VALUE_64 = 4 };
 
 /* Outer probing schemes over windows (Sec. II):
  *   linear     w_l = (h + l) mod P
@@ -118,6 +118,22 @@ hc_err hc_table_bytes(uint64_t capacity, const hc_params* params, uint64_t* h_ou
  * too small array. */
 hc_err hc_create_in(hc_table* out, uint32_t kind, void* d_slots, uint64_t slot_bytes, uint64_t capacity,
                     const hc_params* params);
+
+/* ---- single-value tables with 64-bit keys and values (Sec. IV-B1 wider types) ------
+ * Kind HC_SINGLE_VALUE_64 (hc_create): slots of 16 bytes (key word, then value word), so a
+ * window of W = 8 slots is one 128-byte line; group sizes g <= W.  Keys 0 and 2^64-1 are
+ * reserved.  A claim is a 64-bit CAS of the key word followed by an atomic exchange of the
+ * value word; a present key's value is replaced by an exchange (status DUPLICATE).  Results,
+ * statuses and errors as hc_insert / hc_retrieve / hc_erase with uint64 keys and values.
+ * hc_size, hc_load_factor, hc_capacity, hc_info, hc_clear, hc_destroy apply; hc_dump_slots
+ * copies 2*C uint64 words; hc_create_in needs 16 bytes per slot (hc_table_bytes counts 8).
+ * The 32-bit entry points, hc_stats, hc_device_view, batches and the server return HC_E_KIND. */
+hc_err hc_insert64(hc_table table, const uint64_t* d_keys, const uint64_t* d_values, uint64_t n, uint8_t* d_status,
+                   uint32_t group, void* stream);
+hc_err hc_retrieve64(hc_table table, const uint64_t* d_keys, uint64_t n, uint64_t* d_values_out,
+                     uint8_t* d_found_out, uint32_t group, void* stream);
+hc_err hc_erase64(hc_table table, const uint64_t* d_keys, uint64_t n, uint8_t* d_status, uint32_t group,
+                  void* stream);
 
 /* ---- bucket list tables (Sec. IV-C) ------------------------------------------------
  * A multi-value table that stores each distinct key once: the key's slot in a

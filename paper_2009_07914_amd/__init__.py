@@ -30,8 +30,9 @@ E_OK, E_ARG, E_NOMEM, E_KIND, E_DEVICE = 0, 1, 2, 3, 4
 OP_INSERT, OP_RETRIEVE, OP_ERASE = 0, 1, 2
 
 SCHEMES = {"linear": LINEAR, "quadratic": QUADRATIC, "double": DOUBLE}
-BUCKET_LIST = 3
-KINDS = {"single": SINGLE_VALUE, "multi": MULTI_VALUE, "counting": COUNTING, "bucket": BUCKET_LIST}
+BUCKET_LIST, SINGLE_VALUE_64 = 3, 4
+KINDS = {"single": SINGLE_VALUE, "multi": MULTI_VALUE, "counting": COUNTING, "bucket": BUCKET_LIST,
+         "single64": SINGLE_VALUE_64}
 
 
 class HcParams(ctypes.Structure):
@@ -100,6 +101,9 @@ _SIGS = {
     "hc_bucket_usage": ([_p, ctypes.POINTER(HcBucketUsage), _p], ctypes.c_int),
     "hc_dump_buckets": ([_p, _p, _p, _p], ctypes.c_int),
     "hc_device_view": ([_p, _p, _u64], ctypes.c_int),
+    "hc_insert64": ([_p, _p, _p, _u64, _p, _u32, _p], ctypes.c_int),
+    "hc_retrieve64": ([_p, _p, _u64, _p, _p, _u32, _p], ctypes.c_int),
+    "hc_erase64": ([_p, _p, _u64, _p, _u32, _p], ctypes.c_int),
     "hc_destroy": ([_p], ctypes.c_int),
     "hc_clear": ([_p, _p], ctypes.c_int),
     "hc_insert": ([_p, _p, _p, _u64, _p, _u32, _p], ctypes.c_int),
@@ -243,6 +247,30 @@ def hc_device_view(h: int, nbytes: int) -> ctypes.Array:
     buf = (ctypes.c_ubyte * nbytes)()
     _check(_lib.hc_device_view(h, buf, nbytes), "hc_device_view")
     return buf
+
+
+def _u64t(t, what, n=None):
+    if t is not None and t.dtype == torch.int64:
+        t = t.view(torch.uint64)
+    return _dptr(t, torch.uint64, what, n)
+
+
+def hc_insert64(h: int, keys, values, status=None, group: int = 0, stream=None):
+    n = keys.numel()
+    _check(_lib.hc_insert64(h, _u64t(keys, "keys"), _u64t(values, "values", n), n,
+                            _dptr(status, torch.uint8, "status", n), group, _stream(stream)), "hc_insert64")
+
+
+def hc_retrieve64(h: int, keys, values_out, found_out=None, group: int = 0, stream=None):
+    n = keys.numel()
+    _check(_lib.hc_retrieve64(h, _u64t(keys, "keys"), n, _u64t(values_out, "values_out", n),
+                              _dptr(found_out, torch.uint8, "found_out", n), group, _stream(stream)), "hc_retrieve64")
+
+
+def hc_erase64(h: int, keys, status=None, group: int = 0, stream=None):
+    n = keys.numel()
+    _check(_lib.hc_erase64(h, _u64t(keys, "keys"), n, _dptr(status, torch.uint8, "status", n), group,
+                           _stream(stream)), "hc_erase64")
 
 
 def hc_destroy(h: int):
@@ -570,18 +598,22 @@ class Table:
 
     def insert(self, keys, values=None, status=False, group=0, stream=None):
         st = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device) if status else None
-        hc_insert(self.handle, keys, values, st, group, stream)
+        if self.kind == SINGLE_VALUE_64:
+            hc_insert64(self.handle, keys, values, st, group, stream)
+        else:
+            hc_insert(self.handle, keys, values, st, group, stream)
         return st
 
     def retrieve(self, keys, group=0, stream=None):
-        vals = torch.empty(keys.numel(), dtype=torch.uint32, device=keys.device)
+        wide = self.kind == SINGLE_VALUE_64
+        vals = torch.empty(keys.numel(), dtype=torch.uint64 if wide else torch.uint32, device=keys.device)
         found = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
-        hc_retrieve(self.handle, keys, vals, found, group, stream)
+        (hc_retrieve64 if wide else hc_retrieve)(self.handle, keys, vals, found, group, stream)
         return vals, found
 
     def erase(self, keys, status=False, group=0, stream=None):
         st = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device) if status else None
-        hc_erase(self.handle, keys, st, group, stream)
+        (hc_erase64 if self.kind == SINGLE_VALUE_64 else hc_erase)(self.handle, keys, st, group, stream)
         return st
 
     def count_values(self, keys, group=0, stream=None):
@@ -620,6 +652,7 @@ class Table:
                 "probe_sum": st.probe_sum, "probe_hist": list(st.probe_hist)}
 
     def dump_slots(self, stream=None):
-        out = torch.empty(self.capacity, dtype=torch.uint64, device=self.device)
+        words = self.capacity * (2 if self.kind == SINGLE_VALUE_64 else 1)
+        out = torch.empty(words, dtype=torch.uint64, device=self.device)
         hc_dump_slots(self.handle, out, stream)
         return out

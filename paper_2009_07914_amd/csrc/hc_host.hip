@@ -17,6 +17,7 @@
 #include "hc.h"
 #include "hc_batch.hpp"
 #include "hc_bucket.hpp"
+#include "hc_wide.hpp"
 #include "hc_device.hpp"
 #include "hc_group.hpp"
 #include "hc_stats.hpp"
@@ -188,6 +189,8 @@ static hc_err ensure_ws(hc_table_s* t, uint64_t bytes) {
   return HC_OK;
 }
 
+static uint64_t slot_bytes(uint32_t kind) { return kind == HC_SINGLE_VALUE_64 ? 16 : 8; }
+
 static BucketView bview_of(const hc_table_s* t) {
   BucketView b{};
   b.cum = t->d_cum;
@@ -210,6 +213,13 @@ static hc_err next_bucket_batch(hc_table_s* t, hipStream_t s) {
     t->epoch = 0;
   }
   ++t->epoch;
+  return HC_OK;
+}
+
+// 32-bit entry points on a 64-bit table.
+static hc_err not_wide(hc_table t, const char* what) {
+  if (t != nullptr && t->kind == HC_SINGLE_VALUE_64)
+    return fail(HC_E_KIND, "%s: 64-bit tables take hc_insert64 / hc_retrieve64 / hc_erase64", what);
   return HC_OK;
 }
 
@@ -282,7 +292,7 @@ hc_err build_plan(const hc_batch_op* ops, uint32_t count, int dev, PlanHost* out
     const hc_batch_op& o = ops[j];
     if (o.table == nullptr) return fail(HC_E_ARG, "op %u: table is NULL", j);
     const hc_table_s* t = o.table;
-    if (t->kind == HC_MULTI_VALUE || t->kind == HC_BUCKET_LIST)
+    if (t->kind == HC_MULTI_VALUE || t->kind == HC_BUCKET_LIST || t->kind == HC_SINGLE_VALUE_64)
       return fail(HC_E_KIND, "op %u: batched operations take single-value or counting tables", j);
     if (t->device != dev) return fail(HC_E_ARG, "op %u: table lives on device %d, current device is %d", j, t->device, dev);
     if (o.op > HC_OP_ERASE) return fail(HC_E_ARG, "op %u: unknown operation %u", j, o.op);
@@ -412,15 +422,17 @@ static hc_err create_table(hc_table* out, uint32_t kind, uint64_t capacity, cons
                            void* ext_slots, uint64_t ext_bytes) {
   if (out == nullptr) return fail(HC_E_ARG, "out is NULL");
   *out = nullptr;
-  if (kind > 3) return fail(HC_E_ARG, "unknown table kind %u", kind);
+  if (kind > 4) return fail(HC_E_ARG, "unknown table kind %u", kind);
   hc_params p;
   uint64_t P = 0;
   if (hc_err r = table_geometry(capacity, params, &p, &P); r != HC_OK) return r;
+  if (kind == HC_SINGLE_VALUE_64 && p.group > p.window)
+    return fail(HC_E_ARG, "64-bit tables need group <= window (group %u, window %u)", p.group, p.window);
   if (ext_slots != nullptr) {
     if ((reinterpret_cast<uintptr_t>(ext_slots) & 255) != 0) return fail(HC_E_ARG, "slot array is not 256-byte aligned");
-    if (ext_bytes < P * p.window * sizeof(uint64_t))
+    if (ext_bytes < P * p.window * slot_bytes(kind))
       return fail(HC_E_ARG, "slot array holds %llu bytes, the table needs %llu", (unsigned long long)ext_bytes,
-                  (unsigned long long)(P * p.window * sizeof(uint64_t)));
+                  (unsigned long long)(P * p.window * slot_bytes(kind)));
   }
   hc_table_s* t = new (std::nothrow) hc_table_s();
   if (!t) return fail(HC_E_NOMEM, "host allocation failed");
@@ -443,7 +455,7 @@ static hc_err create_table(hc_table* out, uint32_t kind, uint64_t capacity, cons
   if (ext_slots != nullptr) {
     t->slots = static_cast<uint64_t*>(ext_slots);
   } else {
-    hipError_t e = hipMalloc((void**)&t->slots, t->C * sizeof(uint64_t));
+    hipError_t e = hipMalloc((void**)&t->slots, t->C * slot_bytes(kind));
     if (e != hipSuccess) {
       (void)hipGetLastError();
       delete t;
@@ -606,7 +618,7 @@ hc_err hc_clear(hc_table t, void* stream) {
   hc_err r = check_table(t);
   if (r != HC_OK) return r;
   if ((r = set_device(t)) != HC_OK) return r;
-  const uint64_t pairs = t->C / 2;  // C = P * W with W >= 8: even
+  const uint64_t pairs = t->C * slot_bytes(t->kind) / 16;  // 16-byte stores; C = P * W with W >= 8: even
   uint64_t blocks = (pairs + BLOCK - 1) / BLOCK;
   const uint64_t cap = (uint64_t)device_cu_count() * 16;
   if (blocks > cap) blocks = cap;
@@ -626,6 +638,7 @@ hc_err hc_insert(hc_table t, const uint32_t* d_keys, const uint32_t* d_values, u
                  uint32_t group, void* stream) {
   hc_err r = check_table(t);
   if (r != HC_OK) return r;
+  if ((r = not_wide(t, "hc_insert")) != HC_OK) return r;
   uint32_t g;
   if ((r = resolve_group(t, group, &g)) != HC_OK) return r;
   if (n == 0) return HC_OK;
@@ -649,6 +662,7 @@ hc_err hc_retrieve(hc_table t, const uint32_t* d_keys, uint64_t n, uint32_t* d_v
                    uint32_t group, void* stream) {
   hc_err r = check_table(t);
   if (r != HC_OK) return r;
+  if ((r = not_wide(t, "hc_retrieve")) != HC_OK) return r;
   uint32_t g;
   if ((r = resolve_group(t, group, &g)) != HC_OK) return r;
   if (n == 0) return HC_OK;
@@ -663,6 +677,7 @@ hc_err hc_retrieve(hc_table t, const uint32_t* d_keys, uint64_t n, uint32_t* d_v
 hc_err hc_erase(hc_table t, const uint32_t* d_keys, uint64_t n, uint8_t* d_status, uint32_t group, void* stream) {
   hc_err r = check_table(t);
   if (r != HC_OK) return r;
+  if ((r = not_wide(t, "hc_erase")) != HC_OK) return r;
   uint32_t g;
   if ((r = resolve_group(t, group, &g)) != HC_OK) return r;
   if (n == 0) return HC_OK;
@@ -676,6 +691,7 @@ hc_err hc_count_values(hc_table t, const uint32_t* d_keys, uint64_t n, uint32_t*
                        uint64_t* h_total, uint32_t group, void* stream) {
   hc_err r = check_table(t);
   if (r != HC_OK) return r;
+  if ((r = not_wide(t, "hc_count_values")) != HC_OK) return r;
   if (t->kind != HC_MULTI_VALUE && t->kind != HC_BUCKET_LIST)
     return fail(HC_E_KIND, "count_values needs a multi-value or bucket list table");
   uint32_t g;
@@ -728,6 +744,7 @@ hc_err hc_retrieve_all(hc_table t, const uint32_t* d_keys, uint64_t n, const uin
                        uint32_t* d_values_out, uint32_t group, void* stream) {
   hc_err r = check_table(t);
   if (r != HC_OK) return r;
+  if ((r = not_wide(t, "hc_retrieve_all")) != HC_OK) return r;
   if (t->kind != HC_MULTI_VALUE && t->kind != HC_BUCKET_LIST)
     return fail(HC_E_KIND, "retrieve_all needs a multi-value or bucket list table");
   uint32_t g;
@@ -754,6 +771,7 @@ hc_err hc_retrieve_all(hc_table t, const uint32_t* d_keys, uint64_t n, const uin
 hc_err hc_insert_grouped(hc_table t, const uint32_t* d_keys, const uint32_t* d_values, uint64_t n, void* stream) {
   hc_err r = check_table(t);
   if (r != HC_OK) return r;
+  if ((r = not_wide(t, "hc_insert_grouped")) != HC_OK) return r;
   if (t->kind == HC_SINGLE_VALUE)
     return fail(HC_E_KIND, "grouped insert needs a multi-value, counting or bucket list table");
   if (n == 0) return HC_OK;
@@ -774,6 +792,34 @@ hc_err hc_insert_grouped(hc_table t, const uint32_t* d_keys, const uint32_t* d_v
   if ((r = ensure_ws(t, grouped_workspace_bytes(n))) != HC_OK) return r;
   return launch_grouped_insert(view_of(t), (int)t->kind, t->group, t->window, d_keys, d_values, n, t->d_ws,
                                (hipStream_t)stream);
+}
+
+static hc_err wide_call(hc_table t, int op, const uint64_t* keys, const uint64_t* values, uint64_t n,
+                        uint64_t* values_out, uint8_t* flags, uint32_t group, void* stream) {
+  hc_err r = check_table(t);
+  if (r != HC_OK) return r;
+  if (t->kind != HC_SINGLE_VALUE_64) return fail(HC_E_KIND, "64-bit entry points need a 64-bit table");
+  uint32_t g;
+  if ((r = resolve_group(t, group, &g)) != HC_OK) return r;
+  if (n == 0) return HC_OK;
+  if (keys == nullptr) return fail(HC_E_ARG, "keys is NULL");
+  if (op == WIDE_INSERT && values == nullptr) return fail(HC_E_ARG, "values is NULL");
+  if ((r = set_device(t)) != HC_OK) return r;
+  return launch_wide(op, view_of(t), g, t->window, keys, values, n, values_out, flags, (hipStream_t)stream);
+}
+
+hc_err hc_insert64(hc_table t, const uint64_t* d_keys, const uint64_t* d_values, uint64_t n, uint8_t* d_status,
+                   uint32_t group, void* stream) {
+  return wide_call(t, WIDE_INSERT, d_keys, d_values, n, nullptr, d_status, group, stream);
+}
+
+hc_err hc_retrieve64(hc_table t, const uint64_t* d_keys, uint64_t n, uint64_t* d_values_out, uint8_t* d_found_out,
+                     uint32_t group, void* stream) {
+  return wide_call(t, WIDE_RETRIEVE, d_keys, nullptr, n, d_values_out, d_found_out, group, stream);
+}
+
+hc_err hc_erase64(hc_table t, const uint64_t* d_keys, uint64_t n, uint8_t* d_status, uint32_t group, void* stream) {
+  return wide_call(t, WIDE_ERASE, d_keys, nullptr, n, nullptr, d_status, group, stream);
 }
 
 hc_err hc_size(hc_table t, uint64_t* h_out, void* stream) {
@@ -824,6 +870,7 @@ hc_err hc_info(hc_table t, hc_table_info* h_out) {
 hc_err hc_stats(hc_table t, hc_table_stats* h_out, void* stream) {
   hc_err r = check_table(t);
   if (r != HC_OK) return r;
+  if ((r = not_wide(t, "hc_stats")) != HC_OK) return r;
   if (h_out == nullptr) return fail(HC_E_ARG, "out is NULL");
   static_assert(HC_PROBE_BUCKETS == STATS_BUCKETS, "histogram width");
   static_assert(sizeof(hc_table_stats) == (5 + STATS_BUCKETS) * sizeof(uint64_t), "stats layout");
@@ -848,6 +895,7 @@ hc_err hc_stats(hc_table t, hc_table_stats* h_out, void* stream) {
 hc_err hc_device_view(hc_table t, void* h_view, uint64_t bytes) {
   hc_err r = check_table(t);
   if (r != HC_OK) return r;
+  if ((r = not_wide(t, "hc_device_view")) != HC_OK) return r;
   if (h_view == nullptr) return fail(HC_E_ARG, "view is NULL");
   if (bytes != sizeof(TableView)) return fail(HC_E_ARG, "view takes %zu bytes, not %llu", sizeof(TableView),
                                               (unsigned long long)bytes);
@@ -861,7 +909,8 @@ hc_err hc_dump_slots(hc_table t, uint64_t* d_dst, void* stream) {
   if (r != HC_OK) return r;
   if (d_dst == nullptr) return fail(HC_E_ARG, "destination is NULL");
   if ((r = set_device(t)) != HC_OK) return r;
-  hipError_t e = hipMemcpyAsync(d_dst, t->slots, t->C * sizeof(uint64_t), hipMemcpyDeviceToDevice, (hipStream_t)stream);
+  hipError_t e = hipMemcpyAsync(d_dst, t->slots, t->C * slot_bytes(t->kind), hipMemcpyDeviceToDevice,
+                                (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "hc_dump_slots");
   return HC_OK;
 }
