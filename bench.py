@@ -38,11 +38,11 @@ KERNEL_NAMES = {"insert": "k_insert_unique", "retrieve": "k_retrieve"}
 def _parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="single", choices=["single", "batched", "serving", "multi", "sweep", "bucket"],
+    ap.add_argument("--workload", default="single", choices=["single", "batched", "serving", "multi", "sweep", "bucket", "wide"],
                     help="single: the 2^28-slot table (default); batched: 256 tables in one launch; "
                          "serving: Poisson request stream on 16 resident tables; multi: counting and "
                          "multi-value tables; sweep: load x scheme x group size on the 2^28-slot table; "
-                         "bucket: bucket list tables on the multi-value workloads")
+                         "bucket: bucket list tables on the multi-value workloads; wide: 64-bit keys and values")
     ap.add_argument("--loads", default="0.5,0.8,0.9,0.95,0.99", help="sweep: load factors")
     ap.add_argument("--requests", type=int, default=1500)
     ap.add_argument("--max-log2-request", type=int, default=24)
@@ -124,6 +124,8 @@ def main():
         return bench_sweep(args)
     if args.workload == "bucket":
         return bench_bucket(args)
+    if args.workload == "wide":
+        return bench_wide(args)
     if args.workload == "multi":
         return bench_multi(args)
     import numpy as np
@@ -603,6 +605,68 @@ def bench_bucket(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_wide(args):
+    """Single-value table with 64-bit keys and values: 2^27 slots of 16 bytes (2 GiB, the memory of the
+    2^28-slot 32-bit table), load 0.9, W = 8 (one 128-byte line), double hashing, g = 4: insert all, then
+    retrieve 50% present / 50% absent; every retrieved value checked against the inserted ones."""
+    import numpy as np
+    import torch
+
+    lib = os.path.join(ROOT, "paper_2009_07914_amd", "libhc.so")
+    if not os.path.exists(lib):
+        import __graft_entry__
+        __graft_entry__.build()
+    import gen
+    import paper_2009_07914_amd as hc
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    s = torch.cuda.current_stream()
+    cap = 1 << 27
+    t = hc.Table("single64", cap, scheme="double", window=8, group=4, device=dev)
+    n = int(0.9 * t.capacity)
+    low = gen.keys(gen.derive_seed(gen.SEED_BASE, 41), 1, 2 * n).astype(np.uint64)
+    high = gen.values(gen.derive_seed(gen.SEED_BASE, 42), 2 * n).astype(np.uint64)
+    allk = (high << np.uint64(32)) | low
+    vals = (gen.values(gen.derive_seed(gen.SEED_BASE, 43), n).astype(np.uint64) << np.uint64(32)) | low[:n]
+    src = gen.permutation(gen.derive_seed(gen.SEED_BASE, 44), 2 * n).astype(np.int64)
+    keys = torch.from_numpy(allk[:n]).to(dev)
+    dvals = torch.from_numpy(vals).to(dev)
+    q = torch.from_numpy(allk[src]).to(dev)
+    out = torch.empty(2 * n, dtype=torch.uint64, device=dev)
+    fnd = torch.empty(2 * n, dtype=torch.uint8, device=dev)
+    ins, ret = [], []
+    for rep in range(args.warmup + args.steps):
+        t.clear()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record(s)
+        hc.hc_insert64(t.handle, keys, dvals, None, 4, s)
+        e[1].record(s)
+        hc.hc_retrieve64(t.handle, q, out, fnd, 4, s)
+        e[2].record(s)
+        torch.cuda.synchronize()
+        if rep >= args.warmup:
+            ins.append(e[0].elapsed_time(e[1]))
+            ret.append(e[1].elapsed_time(e[2]))
+    assert t.size() == n
+    f = fnd.cpu().numpy()
+    o = out.cpu().numpy()
+    present = src < n
+    assert np.array_equal(f, present.astype(np.uint8)), "found flags"
+    assert np.array_equal(o[present], vals[src[present]]), "values"
+    ti, tr = statistics.mean(ins), statistics.mean(ret)
+    res = {"metric": "G inserts/s and G retrievals/s, 64-bit keys and values at load 0.9", "value": round(
+        (n + 2 * n) / (ti + tr) / 1e6, 4), "unit": "G ops/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ti + tr, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "single-value table, 64-bit keys and values, 2^27 slots of 16 bytes, load 0.9, "
+                               "W 8, double hashing, g 4; retrieve 50% present / 50% absent",
+                   "capacity": t.capacity, "n_insert": n, "n_retrieve": 2 * n},
+        "insert_ms": round(ti, 4), "retrieve_ms": round(tr, 4), "insert_gops": round(n / ti / 1e6, 4),
+        "retrieve_gops": round(2 * n / tr / 1e6, 4)}
+    print(json.dumps(res), flush=True)
+
+
 def bench_sweep(args):
     """Single-value table of 2^log2 slots at each load: insert all keys, then retrieve them plus as many absent
     ones (50/50), for every probing scheme and group size at W = 16, and W = 32 / 64 for groups of 32 and 64.
@@ -715,7 +779,7 @@ def bench_serving(args):
     uni = [gen.keys(gen.derive_seed(seed, 10 + j), 1, int(0.9 * c)) for j, c in enumerate(caps)]
     pre = [u.size // 2 for u in uni]
     rng = np.random.default_rng(seed & 0xFFFFFFFF)
-    zipf_pmf = None
+    zipf_cdf = {}
     reqs = []
     nxt_ins, nxt_er = list(pre), [0] * len(caps)
     for r in range(args.requests):
@@ -732,9 +796,12 @@ def bench_serving(args):
             nxt_er[t] += n
             reqs.append((t, hc.OP_ERASE, keys, None))
             continue
-        if args.zipf:
-            ranks = gen.zipf_ranks(gen.derive_seed(seed, 200000 + r), uni[t].size, 1.1, n)
-            keys = uni[t][ranks.astype(np.int64) - 1]
+        if args.zipf:  # Zipf(1.1) over the table's first min(|U|, 2^22) keys, one inverse CDF per table
+            if t not in zipf_cdf:
+                zipf_cdf[t] = np.cumsum(gen.zipf_pmf(min(uni[t].size, 1 << 22), 1.1))
+            u = gen.values(gen.derive_seed(seed, 200000 + r), n).astype(np.float64) / 2.0**32
+            ranks = np.minimum(np.searchsorted(zipf_cdf[t], u * zipf_cdf[t][-1], side="right"), zipf_cdf[t].size - 1)
+            keys = uni[t][ranks.astype(np.int64)]
         else:
             keys = uni[t][rng.integers(0, uni[t].size, n)]
         m = n // 10
@@ -817,7 +884,8 @@ def bench_serving(args):
         "config": {"workload": "16 resident single-value tables (2^20..2^28 slots), prefilled to 45% of capacity; "
                                f"{len(host)} requests of log-uniform size in [1, 2^{args.max_log2_request}], "
                                "30% insert / 60% retrieve (10% absent keys) / 10% erase, "
-                               + ("Zipf(1.1)" if args.zipf else "uniform") + " retrieve keys; Poisson arrivals",
+                               + ("Zipf(1.1) (over each table's first 2^22 keys)" if args.zipf else "uniform")
+                               + " retrieve keys; Poisson arrivals",
                    "requests": len(host), "ops": total_ops, "host_buffers": "pinned"},
         "modes": {k: fmt(v) for k, v in res.items()},
         "serial_rate_req_per_s": round(base_rate, 2),
