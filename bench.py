@@ -779,7 +779,7 @@ def bench_serving(args):
     uni = [gen.keys(gen.derive_seed(seed, 10 + j), 1, int(0.9 * c)) for j, c in enumerate(caps)]
     pre = [u.size // 2 for u in uni]
     rng = np.random.default_rng(seed & 0xFFFFFFFF)
-    zipf_cdf = {}
+    zipf_pool = {}
     reqs = []
     nxt_ins, nxt_er = list(pre), [0] * len(caps)
     for r in range(args.requests):
@@ -796,12 +796,14 @@ def bench_serving(args):
             nxt_er[t] += n
             reqs.append((t, hc.OP_ERASE, keys, None))
             continue
-        if args.zipf:  # Zipf(1.1) over the table's first min(|U|, 2^22) keys, one inverse CDF per table
-            if t not in zipf_cdf:
-                zipf_cdf[t] = np.cumsum(gen.zipf_pmf(min(uni[t].size, 1 << 22), 1.1))
-            u = gen.values(gen.derive_seed(seed, 200000 + r), n).astype(np.float64) / 2.0**32
-            ranks = np.minimum(np.searchsorted(zipf_cdf[t], u * zipf_cdf[t][-1], side="right"), zipf_cdf[t].size - 1)
-            keys = uni[t][ranks.astype(np.int64)]
+        if args.zipf:  # Zipf(1.1) over the table's first min(|U|, 2^22) keys: a pool of 2^21 draws per
+            if t not in zipf_pool:  # table (inverse CDF), from which each request takes a wrapped slice
+                cdf = np.cumsum(gen.zipf_pmf(min(uni[t].size, 1 << 22), 1.1))
+                u = gen.values(gen.derive_seed(seed, 200000 + t), 1 << 21).astype(np.float64) / 2.0**32
+                zipf_pool[t] = np.minimum(np.searchsorted(cdf, u * cdf[-1], side="right"), cdf.size - 1)
+            pool = zipf_pool[t]
+            start = int(rng.integers(pool.size))
+            keys = uni[t][pool[(start + np.arange(n)) % pool.size]]
         else:
             keys = uni[t][rng.integers(0, uni[t].size, n)]
         m = n // 10
