@@ -7,6 +7,13 @@ retrievals of many same-sized tables for every candidate (scheme, W, g) at a gri
 of capacities and loads, and keeps the fastest insert and query configuration per
 grid point; ``choose()`` returns the entry of the nearest grid point.  The
 measured table ships with the package as ``tuning.json``.
+
+Each grid point is measured on enough elements (``elements``, spread over up to
+``max_tables`` tables) that the launches run at steady throughput: with a few
+million elements a launch is dominated by its start and its slowest groups, and
+the winners there lose in large mixed batches.  Every (g, W) pair the tuner may
+pick belongs to the batched launcher's mixed-launch set, so tables tuned to
+different pairs still share one launch per phase and operation kind.
 """
 from __future__ import annotations
 
@@ -41,7 +48,7 @@ def choose(capacity: int, load: float) -> dict:
 
 
 def tune(log2_capacities=(10, 13, 16, 19, 22, 24), loads=(0.6, 0.8, 0.95), schemes=("linear", "double"),
-         windows=(8, 16, 32), groups=(1, 2, 4, 8, 16), elements=1 << 22, max_tables=256, reps=3,
+         windows=(8, 16, 32), groups=(1, 2, 4, 8, 16), elements=1 << 25, max_tables=1024, reps=3,
          out_path=TUNING_PATH, log=print):
     """Measure every candidate on the current GPU and write the winners to `out_path`."""
     import torch
@@ -68,7 +75,7 @@ def tune(log2_capacities=(10, 13, 16, 19, 22, 24), loads=(0.6, 0.8, 0.95), schem
                     tabs = [Table("single", cap, scheme=scheme, window=W, group=4) for _ in range(m)]
                     rec = per_layout.setdefault((scheme, W), [(math.inf, 0), (math.inf, 0)])
                     for G in groups:
-                        if W // G > 8:  # at most 8 slots per lane
+                        if W // G > 8 or G > W:  # 1 to 8 slots per lane
                             continue
                         ins = Batch([(hc_batch_op(t, OP_INSERT, k, v, group=G), [k, v])
                                      for t, (k, v, _) in zip(tabs, dev)])

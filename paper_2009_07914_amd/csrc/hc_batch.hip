@@ -46,14 +46,14 @@ __device__ __forceinline__ void run_chunk(const BatchDesc& d, uint64_t begin, ui
   }
 }
 
-// One kernel per (operation kind, group size, window): every descriptor of a
-// launch has them, so the kernel keeps the register budget of a single-table
-// kernel.  chunk_start[d] = first global chunk of descriptor d;
-// chunk_start[ndesc] = total chunks.
-template <uint32_t OP, int G, int W>
-__global__ __launch_bounds__(BLOCK) void k_batch(const BatchDesc* __restrict__ descs,
-                                                 const uint64_t* __restrict__ chunk_start, uint32_t ndesc,
-                                                 WorkCtl ctl) {
+// Every wavefront takes (descriptor, chunk) items from the launch's counter until
+// none is left and runs body(descriptor, first element, end) on each; the last
+// wavefront to leave resets the counters for the launch slot's next use.
+// chunk_start[d] = first global chunk of descriptor d; chunk_start[ndesc] = total.
+template <typename Body>
+__device__ __forceinline__ void take_chunks(const BatchDesc* __restrict__ descs,
+                                            const uint64_t* __restrict__ chunk_start, uint32_t ndesc, WorkCtl ctl,
+                                            Body&& body) {
   const uint32_t lane = __lane_id();
   const uint64_t total = chunk_start[ndesc];
   for (;;) {
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const BatchDesc* __restrict__ d
     const BatchDesc d = descs[lo];
     const uint64_t begin = (c - chunk_start[lo]) * d.chunk;
     const uint64_t end = begin + d.chunk < d.n ? begin + d.chunk : d.n;
-    run_chunk<OP, G, W>(d, begin, end);
+    body(d, begin, end);
   }
   if (lane == 0) {
     const unsigned long long waves = (unsigned long long)gridDim.x * (BLOCK / 64);
@@ -83,18 +83,69 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const BatchDesc* __restrict__ d
   }
 }
 
+// One kernel per (operation kind, group size, window): every descriptor of a
+// launch has them, so the kernel keeps the register budget of a single-table
+// kernel.
+template <uint32_t OP, int G, int W>
+__global__ __launch_bounds__(BLOCK) void k_batch(const BatchDesc* __restrict__ descs,
+                                                 const uint64_t* __restrict__ chunk_start, uint32_t ndesc,
+                                                 WorkCtl ctl) {
+  take_chunks(descs, chunk_start, ndesc, ctl,
+              [](const BatchDesc& d, uint64_t begin, uint64_t end) { run_chunk<OP, G, W>(d, begin, end); });
+}
+
+// Mixed launch: each chunk runs with its descriptor's (G, W) pair, so tables
+// tuned to different pairs still share one launch per operation kind (the
+// descriptor is wavefront-uniform, so is the branch).  The register budget is
+// that of the largest pair of the set.
+template <uint32_t OP>
+__global__ __launch_bounds__(BLOCK) void k_batch_mixed(const BatchDesc* __restrict__ descs,
+                                                       const uint64_t* __restrict__ chunk_start, uint32_t ndesc,
+                                                       WorkCtl ctl) {
+  take_chunks(descs, chunk_start, ndesc, ctl, [](const BatchDesc& d, uint64_t begin, uint64_t end) {
+    switch (d.variant) {
+      case 0: run_chunk<OP, 1, 8>(d, begin, end); break;
+      case 1: run_chunk<OP, 2, 8>(d, begin, end); break;
+      case 2: run_chunk<OP, 4, 8>(d, begin, end); break;
+      case 3: run_chunk<OP, 8, 8>(d, begin, end); break;
+      case 4: run_chunk<OP, 2, 16>(d, begin, end); break;
+      case 5: run_chunk<OP, 4, 16>(d, begin, end); break;
+      case 6: run_chunk<OP, 8, 16>(d, begin, end); break;
+      case 7: run_chunk<OP, 16, 16>(d, begin, end); break;
+      case 8: run_chunk<OP, 4, 32>(d, begin, end); break;
+      case 9: run_chunk<OP, 8, 32>(d, begin, end); break;
+      case 10: run_chunk<OP, 16, 32>(d, begin, end); break;
+      default: break;  // the planner puts no other pair into a mixed launch
+    }
+  });
+}
+
+uint32_t mixed_variant(uint32_t G, uint32_t W) {
+  switch (W) {
+    case 8: return G == 1 ? 0 : G == 2 ? 1 : G == 4 ? 2 : G == 8 ? 3 : MIXED_NONE;
+    case 16: return G == 2 ? 4 : G == 4 ? 5 : G == 8 ? 6 : G == 16 ? 7 : MIXED_NONE;
+    case 32: return G == 4 ? 8 : G == 8 ? 9 : G == 16 ? 10 : MIXED_NONE;
+    default: return MIXED_NONE;
+  }
+}
+
+template <typename K>
+static hc_err launch_persistent(K k, const BatchDesc* d_descs, const uint64_t* d_chunk_start, uint32_t ndesc,
+                                uint64_t total_chunks, hipStream_t stream) {
+  const uint64_t cap = (uint64_t)device_cu_count() * (uint64_t)blocks_per_cu(reinterpret_cast<const void*>(k));
+  const uint64_t need = (total_chunks + (BLOCK / 64) - 1) / (BLOCK / 64);
+  const unsigned grid = (unsigned)(need < cap ? need : cap);
+  WorkCtl ctl = work_for(0, 64, grid);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, d_descs, d_chunk_start, ndesc, ctl);
+  return check_launch("batch");
+}
+
 template <uint32_t OP>
 static hc_err launch_batch_op(uint32_t G, uint32_t W, const BatchDesc* d_descs, const uint64_t* d_chunk_start,
                               uint32_t ndesc, uint64_t total_chunks, hipStream_t stream) {
   return dispatch_gw(G, W, [&](auto g, auto w) -> hc_err {
     constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
-    auto k = k_batch<OP, GG, WW>;
-    const uint64_t cap = (uint64_t)device_cu_count() * (uint64_t)blocks_per_cu(reinterpret_cast<const void*>(k));
-    const uint64_t need = (total_chunks + (BLOCK / 64) - 1) / (BLOCK / 64);
-    const unsigned grid = (unsigned)(need < cap ? need : cap);
-    WorkCtl ctl = work_for(0, 64, grid);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, d_descs, d_chunk_start, ndesc, ctl);
-    return check_launch("batch");
+    return launch_persistent(k_batch<OP, GG, WW>, d_descs, d_chunk_start, ndesc, total_chunks, stream);
   });
 }
 
@@ -110,6 +161,22 @@ hc_err launch_batch(uint32_t op, uint32_t G, uint32_t W, const BatchDesc* d_desc
       return launch_batch_op<BATCH_RETRIEVE>(G, W, d_descs, d_chunk_start, ndesc, total_chunks, stream);
     case BATCH_ERASE:
       return launch_batch_op<BATCH_ERASE>(G, W, d_descs, d_chunk_start, ndesc, total_chunks, stream);
+  }
+  return fail(HC_E_ARG, "unknown batched operation %u", op);
+}
+
+hc_err launch_batch_mixed(uint32_t op, const BatchDesc* d_descs, const uint64_t* d_chunk_start, uint32_t ndesc,
+                          uint64_t total_chunks, hipStream_t stream) {
+  if (ndesc == 0 || total_chunks == 0) return HC_OK;
+  switch (op) {
+    case BATCH_INSERT:
+      return launch_persistent(k_batch_mixed<BATCH_INSERT>, d_descs, d_chunk_start, ndesc, total_chunks, stream);
+    case BATCH_COUNT:
+      return launch_persistent(k_batch_mixed<BATCH_COUNT>, d_descs, d_chunk_start, ndesc, total_chunks, stream);
+    case BATCH_RETRIEVE:
+      return launch_persistent(k_batch_mixed<BATCH_RETRIEVE>, d_descs, d_chunk_start, ndesc, total_chunks, stream);
+    case BATCH_ERASE:
+      return launch_persistent(k_batch_mixed<BATCH_ERASE>, d_descs, d_chunk_start, ndesc, total_chunks, stream);
   }
   return fail(HC_E_ARG, "unknown batched operation %u", op);
 }

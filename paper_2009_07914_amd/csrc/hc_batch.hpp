@@ -20,15 +20,27 @@ struct BatchDesc {
   uint64_t n;
   uint32_t chunk;           // elements per chunk
   uint32_t op;              // BATCH_*
+  uint32_t variant;         // index of (G, W) in the mixed-launch set, or MIXED_NONE
+  uint32_t reserved;
 };
+
+// (group size, window) pairs that one mixed launch can run side by side: the
+// windows 8, 16 and 32 with at most 8 slots per lane (a wavefront takes each
+// chunk with the chunk's own pair).  Pairs outside it get launches of their own.
+constexpr uint32_t MIXED_NONE = 0xFFFFFFFFu;
+constexpr uint32_t MIXED_COUNT = 11;
+uint32_t mixed_variant(uint32_t G, uint32_t W);
 
 // One persistent launch over descs[0..ndesc) (device arrays, all of operation
 // kind `op`, group size G and window W) on `stream`.
 hc_err launch_batch(uint32_t op, uint32_t G, uint32_t W, const BatchDesc* d_descs, const uint64_t* d_chunk_start,
                     uint32_t ndesc, uint64_t total_chunks, hipStream_t stream);
+// The same over descriptors of several (G, W) pairs of the mixed-launch set.
+hc_err launch_batch_mixed(uint32_t op, const BatchDesc* d_descs, const uint64_t* d_chunk_start, uint32_t ndesc,
+                          uint64_t total_chunks, hipStream_t stream);
 
 struct PlanLaunch {
-  uint32_t op, G, W;
+  uint32_t op, G, W;           // G = W = 0: a mixed launch (each descriptor's own pair)
   uint32_t first_desc, ndesc;  // descriptors [first_desc, first_desc + ndesc)
   uint64_t cs_offset;          // this launch's chunk starts
   uint64_t total_chunks;

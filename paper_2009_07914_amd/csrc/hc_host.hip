@@ -315,38 +315,66 @@ hc_err build_plan(const hc_batch_op* ops, uint32_t count, int dev, PlanHost* out
     if (phase + 1 > phases) phases = phase + 1;
     if (o.n > 0) items.push_back({phase, bop, g, t->window, j});
   }
-  // launches: (phase, kind, G, W) groups, list order kept inside each group
+  // Launches: one per (phase, kind, G, W) group, list order kept inside each group.
+  // Where a (phase, kind) has several pairs, those of the mixed-launch set share one
+  // mixed launch (G = W = 0 below); pairs outside the set keep launches of their own.
+  auto pair_key = [](const Item& x) { return (x.G << 8) | x.W; };
   std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
     if (a.phase != b.phase) return a.phase < b.phase;
-    if (a.op != b.op) return a.op < b.op;
-    if (a.G != b.G) return a.G < b.G;
-    return a.W < b.W;
+    return a.op < b.op;
   });
-  out->phases = phases;
+  std::vector<uint8_t> mixed(items.size(), 0);
   for (size_t a = 0; a < items.size();) {
     size_t e = a;
-    while (e < items.size() && items[e].phase == items[a].phase && items[e].op == items[a].op &&
-           items[e].G == items[a].G && items[e].W == items[a].W)
+    bool several = false;
+    while (e < items.size() && items[e].phase == items[a].phase && items[e].op == items[a].op) {
+      several |= pair_key(items[e]) != pair_key(items[a]);
       ++e;
+    }
+    if (several)
+      for (size_t q = a; q < e; ++q) mixed[q] = mixed_variant(items[q].G, items[q].W) != MIXED_NONE;
+    a = e;
+  }
+  std::vector<size_t> order(items.size());
+  for (size_t q = 0; q < order.size(); ++q) order[q] = q;
+  std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+    const Item &a = items[x], &b = items[y];
+    if (a.phase != b.phase) return a.phase < b.phase;
+    if (a.op != b.op) return a.op < b.op;
+    if (mixed[x] != mixed[y]) return mixed[x] > mixed[y];
+    return mixed[x] ? false : pair_key(a) < pair_key(b);
+  });
+  const uint64_t waves = (uint64_t)device_cu_count() * 32;
+  out->phases = phases;
+  for (size_t a = 0; a < order.size();) {
+    const Item& f = items[order[a]];
+    const bool mix = mixed[order[a]] != 0;
+    size_t e = a;
+    while (e < order.size()) {
+      const Item& x = items[order[e]];
+      if (x.phase != f.phase || x.op != f.op || (mixed[order[e]] != 0) != mix) break;
+      if (!mix && pair_key(x) != pair_key(f)) break;
+      ++e;
+    }
     PlanLaunch L;
-    L.op = items[a].op;
-    L.G = items[a].G;
-    L.W = items[a].W;
+    L.op = f.op;
+    L.G = mix ? 0 : f.G;
+    L.W = mix ? 0 : f.W;
     L.first_desc = (uint32_t)out->descs.size();
     L.ndesc = (uint32_t)(e - a);
     L.cs_offset = out->cs.size();
     // chunk size: about two chunks per resident wavefront over the whole launch, between
-    // one element per group and 64 elements per group of a wavefront
+    // one element per group and 64 elements per group of a wavefront (per descriptor's G)
     uint64_t total = 0;
-    for (size_t q = a; q < e; ++q) total += ops[items[q].index].n;
-    const uint64_t gpw = 64 / L.G;
-    const uint64_t waves = (uint64_t)device_cu_count() * 32;
-    uint64_t ch = (total + 2 * waves - 1) / (2 * waves);
-    if (ch < gpw) ch = gpw;
-    if (ch > 64 * gpw) ch = 64 * gpw;
+    for (size_t q = a; q < e; ++q) total += ops[items[order[q]].index].n;
+    const uint64_t per_wave = (total + 2 * waves - 1) / (2 * waves);
     uint64_t chunks = 0;
     for (size_t q = a; q < e; ++q) {
-      const hc_batch_op& o = ops[items[q].index];
+      const Item& x = items[order[q]];
+      const hc_batch_op& o = ops[x.index];
+      const uint64_t gpw = 64 / x.G;
+      uint64_t ch = per_wave < gpw ? gpw : per_wave;
+      if (ch > 64 * gpw) ch = 64 * gpw;
       BatchDesc d;
       d.t = view_of(o.table);
       d.keys = o.d_keys;
@@ -356,6 +384,8 @@ hc_err build_plan(const hc_batch_op* ops, uint32_t count, int dev, PlanHost* out
       d.n = o.n;
       d.chunk = (uint32_t)(o.n < ch ? o.n : ch);
       d.op = L.op;
+      d.variant = mix ? mixed_variant(x.G, x.W) : MIXED_NONE;
+      d.reserved = 0;
       out->descs.push_back(d);
       out->cs.push_back(chunks);
       chunks += (o.n + d.chunk - 1) / d.chunk;
@@ -371,8 +401,10 @@ hc_err build_plan(const hc_batch_op* ops, uint32_t count, int dev, PlanHost* out
 hc_err launch_plan(const std::vector<PlanLaunch>& launches, const BatchDesc* d_descs, const uint64_t* d_cs,
                    hipStream_t stream) {
   for (const auto& L : launches) {
-    hc_err r = launch_batch(L.op, L.G, L.W, d_descs + L.first_desc, d_cs + L.cs_offset, L.ndesc, L.total_chunks,
-                            stream);
+    hc_err r = L.G == 0 ? launch_batch_mixed(L.op, d_descs + L.first_desc, d_cs + L.cs_offset, L.ndesc,
+                                             L.total_chunks, stream)
+                        : launch_batch(L.op, L.G, L.W, d_descs + L.first_desc, d_cs + L.cs_offset, L.ndesc,
+                                       L.total_chunks, stream);
     if (r != HC_OK) return r;
   }
   return HC_OK;

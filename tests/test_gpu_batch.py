@@ -27,6 +27,23 @@ def _tables(hc, n_tables, log2_lo, log2_hi, seed, kind="single"):
     return out
 
 
+# (group size, window) pairs that share one mixed launch when a phase's operations of one
+# kind use several pairs; other pairs get launches of their own
+MIXED = {(1, 8), (2, 8), (4, 8), (8, 8), (2, 16), (4, 16), (8, 16), (16, 16), (4, 32), (8, 32), (16, 32)}
+
+
+def _expected_launches(groups):
+    """groups: per (phase, kind), the list of (G, W) pairs of its non-empty operations."""
+    n = 0
+    for pairs in groups:
+        p = set(pairs)
+        if len(p) == 1:
+            n += 1
+        else:
+            n += int(any(x in MIXED for x in p)) + sum(x not in MIXED for x in p)
+    return n
+
+
 def test_many_tables_build_then_query(hc):
     tabs = _tables(hc, 40, 10, 16, 123)
     ins, ret, keep = [], [], []
@@ -41,6 +58,9 @@ def test_many_tables_build_then_query(hc):
         outs.append((st, vo, fo))
     b = hc.Batch(ins + ret)
     assert b.phases == 2
+    gi = [([1, 2, 4, 8, 16][(j + 1) % 5], t.window) for j, (t, _) in enumerate(tabs)]
+    gr = [(t.group, t.window) for t, _ in tabs]
+    assert b.launches == _expected_launches([gi, gr])
     b.launch()
     torch.cuda.synchronize()
     for (t, w), (st, vo, fo) in zip(tabs, outs):
