@@ -50,8 +50,16 @@ extern "C" {
 typedef struct hc_table_s* hc_table;
 
 /* Table kinds (Sec. IV: SingleValueHashTable, MultiValueHashTable, CountingHashTable,
- * BucketListHashTable; the last is made by hc_create_bucket_list). */
-enum { HC_SINGLE_VALUE = 0, HC_MULTI_VALUE = 1, HC_COUNTING = 2, HC_BUCKET_LIST = 3, HC_SINGLE_VALUE_64 = 4 };
+ * BucketListHashTable, made by hc_create_bucket_list; single-value tables of 64-bit keys and
+ * values; HashSet). */
+enum {
+  HC_SINGLE_VALUE = 0,
+  HC_MULTI_VALUE = 1,
+  HC_COUNTING = 2,
+  HC_BUCKET_LIST = 3,
+  HC_SINGLE_VALUE_64 = 4,
+  HC_HASH_SET = 5
+};
 
 /* Outer probing schemes over windows (Sec. II):
  *   linear     w_l = (h + l) mod P
@@ -134,6 +142,65 @@ hc_err hc_retrieve64(hc_table table, const uint64_t* d_keys, uint64_t n, uint64_
                      uint8_t* d_found_out, uint32_t group, void* stream);
 hc_err hc_erase64(hc_table table, const uint64_t* d_keys, uint64_t n, uint8_t* d_status, uint32_t group,
                   void* stream);
+
+/* ---- HashSet (Sec. IV: a set of keys, each stored once) -----------------------------
+ * Kind HC_HASH_SET (hc_create): slots of 4 bytes holding only the key, so a window of
+ * W = 16 slots is one 64-byte line; group sizes g <= W.  Keys 0 and 0xFFFFFFFF are reserved.
+ * The window sequence and hash are those of the 32-bit tables, so a key lands in the window a
+ * single-value table of the same geometry would give it.  Entry points:
+ *   hc_insert(set, keys, NULL, n, status, ...)      status OK (new key), DUPLICATE, FULL,
+ *                                                   INVALID_KEY; d_values must be NULL
+ *   hc_retrieve(set, keys, n, NULL, found, ...)     found[i] = 1 if keys[i] is in the set;
+ *                                                   d_values_out must be NULL, d_found_out not
+ *   hc_erase(set, keys, n, status, ...)             as for single-value tables
+ * hc_size, hc_load_factor, hc_capacity, hc_info, hc_clear, hc_destroy apply; hc_dump_slots
+ * copies C uint32 keys (C * 4 bytes); hc_create_in needs 4 bytes per slot.  hc_count_values,
+ * hc_retrieve_all, hc_insert_grouped, hc_stats, hc_device_view, the 64-bit entry points,
+ * batches and the server return HC_E_KIND. */
+
+/* ---- Bloom filter (Sec. IV: answers set membership queries) ------------------------
+ * The paper lists a BloomFilter without a design; this one is a split-block filter: the bit
+ * array is B blocks of block_words 32-bit words (8, 16 or 32: 32, 64 or 128 bytes), and key x
+ * sets one bit in every word of block reduce(h1(x), B): bit fmix32(h2(x) + i * 0x9E3779B9) >> 27
+ * of word i, so k = block_words bits per key.  h1, h2 and reduce are the tables' (fmix32 of the
+ * key with the seed's low / high half; mask for a power-of-two B, multiply-high otherwise).
+ * Every 32-bit key is valid.  No false negatives; the false-positive rate with n keys is
+ * sum_j Binomial(j; n, 1/B) (1 - (31/32)^j)^block_words.  A group of g lanes (power of two,
+ * g <= block_words) takes one key; group is a tuning knob and never changes results. */
+typedef struct hc_bloom_s* hc_bloom;
+
+typedef struct {
+  uint32_t block_words; /* 8, 16 or 32 (bits per key) */
+  uint32_t group;       /* default group size g */
+  uint64_t seed;
+} hc_bloom_params;
+
+typedef struct {
+  uint64_t blocks;      /* B */
+  uint32_t block_words;
+  uint32_t group;
+  uint64_t seed;
+  uint32_t* d_bits;     /* B * block_words uint32 words, block j at words [j * block_words, ...) */
+} hc_bloom_info_t;
+
+/* Defaults: 16 words (one 64-byte block, 16 bits per key), g = 4, a fixed seed. */
+void hc_default_bloom_params(hc_bloom_params* params);
+/* A cleared filter of at least `bits` bits (B = ceil(bits / (32 * block_words)) blocks,
+ * B <= 2^32) on the current device; params may be NULL (defaults).  The call synchronises.
+ * Errors: HC_E_ARG (bits 0, bad params), HC_E_NOMEM. */
+hc_err hc_bloom_create(hc_bloom* out, uint64_t bits, const hc_bloom_params* params);
+hc_err hc_bloom_destroy(hc_bloom filter);
+/* Clear every bit (a fill kernel on the stream). */
+hc_err hc_bloom_clear(hc_bloom filter, void* stream);
+/* Add n keys (device array).  group 0 = the filter's default.  Concurrent inserts and
+ * inserts racing with queries are allowed; a query sees a key inserted by an earlier launch. */
+hc_err hc_bloom_insert(hc_bloom filter, const uint32_t* d_keys, uint64_t n, uint32_t group, void* stream);
+/* d_found_out[i] = 1 if every bit of keys[i] is set, else 0. */
+hc_err hc_bloom_contains(hc_bloom filter, const uint32_t* d_keys, uint64_t n, uint8_t* d_found_out, uint32_t group,
+                         void* stream);
+hc_err hc_bloom_info(hc_bloom filter, hc_bloom_info_t* h_out);
+/* Copy the B * block_words words of the bit array into d_dst (device), on the stream. */
+hc_err hc_bloom_dump(hc_bloom filter, uint32_t* d_dst, void* stream);
 
 /* ---- bucket list tables (Sec. IV-C) ------------------------------------------------
  * A multi-value table that stores each distinct key once: the key's slot in a

@@ -96,6 +96,14 @@ def _load():
         lib.orc64_window_at.argtypes = [u64, u64, u64, i, u64]
         lib.orc64_window_at.restype = u64
         lib.orc64_check_layout.argtypes = [p, u64, u32, i, u64, p]
+        lib.orc_bloom_insert.argtypes = [p, u64, u32, u64, p, u64]
+        lib.orc_bloom_insert.restype = None
+        lib.orc_bloom_query.argtypes = [p, u64, u32, u64, p, u64, p]
+        lib.orc_bloom_query.restype = None
+        lib.orc_bloom_positions.argtypes = [u32, u64, u32, u64, p, p]
+        lib.orc_bloom_blocks.argtypes = [p, u64, u64, u64, p]
+        lib.orc_bloom_blocks.restype = None
+        lib.orc_bloom_positions.restype = None
         lib.orc64_check_layout.restype = i
         _lib = lib
     return _lib
@@ -285,3 +293,40 @@ def check_layout64(slots: np.ndarray, P: int, W: int, scheme: int, seed: int):
     return int(rc), {"live": int(st[0]), "tombstones": int(st[1]), "max_windows": int(st[2]),
                      "sum_windows": int(st[3]), "first_bad_slot": int(st[4])}
 
+
+
+# ---- Bloom filter (blocked) --------------------------------------------------
+
+class OracleBloom:
+    """Split-block Bloom filter: ``blocks`` blocks of ``words`` 32-bit words; each key sets one bit
+    in every word of one block (k = words).  ``bits`` is the word array (blocks * words uint32)."""
+
+    def __init__(self, blocks: int, words: int, seed: int):
+        assert words in (8, 16, 32) and blocks >= 1
+        self.blocks, self.words, self.seed = blocks, words, seed & (2**64 - 1)
+        self.bits = np.zeros(blocks * words, dtype=np.uint32)
+
+    def insert(self, keys):
+        keys = _u32(keys)
+        _load().orc_bloom_insert(_ptr(self.bits), self.blocks, self.words, self.seed, _ptr(keys), keys.size)
+
+    def query(self, keys) -> np.ndarray:
+        keys = _u32(keys)
+        out = np.empty(keys.size, dtype=np.uint8)
+        _load().orc_bloom_query(_ptr(self.bits), self.blocks, self.words, self.seed, _ptr(keys), keys.size,
+                                _ptr(out))
+        return out
+
+    def blocks_of(self, keys) -> np.ndarray:
+        """Block index of every key."""
+        keys = _u32(keys)
+        out = np.empty(keys.size, dtype=np.uint64)
+        _load().orc_bloom_blocks(_ptr(keys), keys.size, self.blocks, self.seed, _ptr(out))
+        return out
+
+    def positions(self, key: int):
+        """(block, bit of each word) of one key."""
+        blk = np.zeros(1, dtype=np.uint64)
+        bit = np.zeros(self.words, dtype=np.uint32)
+        _load().orc_bloom_positions(key & 0xFFFFFFFF, self.blocks, self.words, self.seed, _ptr(blk), _ptr(bit))
+        return int(blk[0]), bit

@@ -40,6 +40,14 @@
  *      layouts for the checker's own tests and to measure windows per
  *      operation on actual key sets.
  *
+ *  (4) The Bloom filter (Sec. IV lists a BloomFilter answering set membership
+ *      queries; the paper gives no design), in the blocked form read for it:
+ *      the bit array is B blocks of `words` 32-bit words; key x picks block
+ *      reduce(h1(x), B) and sets one bit in every word of it, bit
+ *      fmix32(h2(x) + i * 0x9E3779B9) >> 27 of word i (a split-block filter:
+ *      k = words bits per key, one per word).  A query answers yes iff all
+ *      of them are set.
+ *
  * Where the paper is silent the readings are: hash h1(k) = fmix32(k ^ seed_lo),
  * h2(k) = fmix32((k ^ seed_hi) + 0x9E3779B9) (MurmurHash3's finaliser,
  * Appleby, public domain); window index reduction by mask (power-of-two P)
@@ -556,6 +564,48 @@ int orc64_check_layout(const uint64_t* slots, uint64_t P, uint32_t W, int scheme
   stats[3] = sumw;
   stats[4] = bad;
   return code;
+}
+
+/* ------------------------------------------------------------------------- *
+ * Bloom filter (split-block; the rule is stated in the header comment).
+ * bits: B * words uint32 words, block j at words [j * words, (j + 1) * words).
+ * ------------------------------------------------------------------------- */
+
+static uint64_t bloom_block(uint32_t key, uint64_t B, uint64_t seed) {
+  return reduce(orc_fmix32(key ^ (uint32_t)seed), B);
+}
+
+static uint32_t bloom_bit(uint32_t key, uint32_t i, uint64_t seed) {
+  const uint32_t h2 = orc_fmix32((key ^ (uint32_t)(seed >> 32)) + 0x9E3779B9u);
+  return orc_fmix32(h2 + i * 0x9E3779B9u) >> 27;
+}
+
+void orc_bloom_insert(uint32_t* bits, uint64_t B, uint32_t words, uint64_t seed, const uint32_t* keys, uint64_t n) {
+  for (uint64_t x = 0; x < n; ++x) {
+    const uint64_t blk = bloom_block(keys[x], B, seed);
+    for (uint32_t i = 0; i < words; ++i) bits[blk * words + i] |= 1u << bloom_bit(keys[x], i, seed);
+  }
+}
+
+void orc_bloom_query(const uint32_t* bits, uint64_t B, uint32_t words, uint64_t seed, const uint32_t* keys,
+                     uint64_t n, uint8_t* out) {
+  for (uint64_t x = 0; x < n; ++x) {
+    const uint64_t blk = bloom_block(keys[x], B, seed);
+    bool all = true;
+    for (uint32_t i = 0; i < words; ++i) all = all && ((bits[blk * words + i] >> bloom_bit(keys[x], i, seed)) & 1u);
+    out[x] = all ? 1 : 0;
+  }
+}
+
+/* Block index of each key (to sample the blocks of a large filter). */
+void orc_bloom_blocks(const uint32_t* keys, uint64_t n, uint64_t B, uint64_t seed, uint64_t* out) {
+  for (uint64_t x = 0; x < n; ++x) out[x] = bloom_block(keys[x], B, seed);
+}
+
+/* Block index and the bit of every word of one key (for the oracle's own tests). */
+void orc_bloom_positions(uint32_t key, uint64_t B, uint32_t words, uint64_t seed, uint64_t* block, uint32_t* bit) {
+  *block = bloom_block(key, B, seed);
+  for (uint32_t i = 0; i < words; ++i) bit[i] = bloom_bit(key, i, seed);
 }
 
 }  // extern "C"

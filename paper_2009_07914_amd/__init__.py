@@ -30,9 +30,9 @@ E_OK, E_ARG, E_NOMEM, E_KIND, E_DEVICE = 0, 1, 2, 3, 4
 OP_INSERT, OP_RETRIEVE, OP_ERASE = 0, 1, 2
 
 SCHEMES = {"linear": LINEAR, "quadratic": QUADRATIC, "double": DOUBLE}
-BUCKET_LIST, SINGLE_VALUE_64 = 3, 4
+BUCKET_LIST, SINGLE_VALUE_64, HASH_SET = 3, 4, 5
 KINDS = {"single": SINGLE_VALUE, "multi": MULTI_VALUE, "counting": COUNTING, "bucket": BUCKET_LIST,
-         "single64": SINGLE_VALUE_64}
+         "single64": SINGLE_VALUE_64, "set": HASH_SET}
 
 
 class HcParams(ctypes.Structure):
@@ -57,6 +57,15 @@ class HcBucketParams(ctypes.Structure):
 class HcBucketUsage(ctypes.Structure):
     _fields_ = [("values", ctypes.c_uint64), ("pool_used", ctypes.c_uint64), ("pool_words", ctypes.c_uint64),
                 ("smax", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class HcBloomParams(ctypes.Structure):
+    _fields_ = [("block_words", ctypes.c_uint32), ("group", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+
+
+class HcBloomInfo(ctypes.Structure):
+    _fields_ = [("blocks", ctypes.c_uint64), ("block_words", ctypes.c_uint32), ("group", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64), ("d_bits", ctypes.c_void_p)]
 
 
 class HcTableStats(ctypes.Structure):
@@ -104,6 +113,14 @@ _SIGS = {
     "hc_insert64": ([_p, _p, _p, _u64, _p, _u32, _p], ctypes.c_int),
     "hc_retrieve64": ([_p, _p, _u64, _p, _p, _u32, _p], ctypes.c_int),
     "hc_erase64": ([_p, _p, _u64, _p, _u32, _p], ctypes.c_int),
+    "hc_default_bloom_params": ([ctypes.POINTER(HcBloomParams)], None),
+    "hc_bloom_create": ([ctypes.POINTER(_p), _u64, ctypes.POINTER(HcBloomParams)], ctypes.c_int),
+    "hc_bloom_destroy": ([_p], ctypes.c_int),
+    "hc_bloom_clear": ([_p, _p], ctypes.c_int),
+    "hc_bloom_insert": ([_p, _p, _u64, _u32, _p], ctypes.c_int),
+    "hc_bloom_contains": ([_p, _p, _u64, _p, _u32, _p], ctypes.c_int),
+    "hc_bloom_info": ([_p, ctypes.POINTER(HcBloomInfo)], ctypes.c_int),
+    "hc_bloom_dump": ([_p, _p, _p], ctypes.c_int),
     "hc_destroy": ([_p], ctypes.c_int),
     "hc_clear": ([_p, _p], ctypes.c_int),
     "hc_insert": ([_p, _p, _p, _u64, _p, _u32, _p], ctypes.c_int),
@@ -348,8 +365,14 @@ def hc_info(h: int) -> HcTableInfo:
     return out
 
 
+def slot_words(h: int) -> int:
+    """uint64 words of a table's slot array: C, 2C for 64-bit tables, C/2 for sets."""
+    info = hc_info(h)
+    return {SINGLE_VALUE_64: 2 * info.capacity, HASH_SET: info.capacity // 2}.get(info.kind, info.capacity)
+
+
 def hc_dump_slots(h: int, dst, stream=None):
-    _check(_lib.hc_dump_slots(h, _dptr(dst, torch.uint64, "dst", hc_capacity(h)), _stream(stream)),
+    _check(_lib.hc_dump_slots(h, _dptr(dst, torch.uint64, "dst", slot_words(h)), _stream(stream)),
            "hc_dump_slots")
 
 
@@ -605,6 +628,11 @@ class Table:
         return st
 
     def retrieve(self, keys, group=0, stream=None):
+        """(values, found); a set returns (None, found)."""
+        if self.kind == HASH_SET:
+            found = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
+            hc_retrieve(self.handle, keys, None, found, group, stream)
+            return None, found
         wide = self.kind == SINGLE_VALUE_64
         vals = torch.empty(keys.numel(), dtype=torch.uint64 if wide else torch.uint32, device=keys.device)
         found = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
@@ -652,7 +680,95 @@ class Table:
                 "probe_sum": st.probe_sum, "probe_hist": list(st.probe_hist)}
 
     def dump_slots(self, stream=None):
-        words = self.capacity * (2 if self.kind == SINGLE_VALUE_64 else 1)
-        out = torch.empty(words, dtype=torch.uint64, device=self.device)
+        """The slot array: C uint64 words (2C for 64-bit tables); a set's C uint32 keys."""
+        out = torch.empty(slot_words(self.handle), dtype=torch.uint64, device=self.device)
         hc_dump_slots(self.handle, out, stream)
+        return out.view(torch.uint32) if self.kind == HASH_SET else out
+
+
+# ---- Bloom filter ------------------------------------------------------------
+
+def hc_default_bloom_params() -> HcBloomParams:
+    p = HcBloomParams()
+    _lib.hc_default_bloom_params(ctypes.byref(p))
+    return p
+
+
+def hc_bloom_create(bits: int, params: HcBloomParams | None = None) -> int:
+    h = ctypes.c_void_p()
+    _check(_lib.hc_bloom_create(ctypes.byref(h), bits, ctypes.byref(params) if params else None), "hc_bloom_create")
+    return h.value
+
+
+def hc_bloom_destroy(h: int):
+    _check(_lib.hc_bloom_destroy(h), "hc_bloom_destroy")
+
+
+def hc_bloom_clear(h: int, stream=None):
+    _check(_lib.hc_bloom_clear(h, _stream(stream)), "hc_bloom_clear")
+
+
+def hc_bloom_insert(h: int, keys, group: int = 0, stream=None):
+    _check(_lib.hc_bloom_insert(h, _u32t(keys, "keys"), keys.numel(), group, _stream(stream)), "hc_bloom_insert")
+
+
+def hc_bloom_contains(h: int, keys, found_out, group: int = 0, stream=None):
+    n = keys.numel()
+    _check(_lib.hc_bloom_contains(h, _u32t(keys, "keys"), n, _dptr(found_out, torch.uint8, "found_out", n), group,
+                                  _stream(stream)), "hc_bloom_contains")
+
+
+def hc_bloom_info(h: int) -> HcBloomInfo:
+    out = HcBloomInfo()
+    _check(_lib.hc_bloom_info(h, ctypes.byref(out)), "hc_bloom_info")
+    return out
+
+
+def hc_bloom_dump(h: int, dst, stream=None):
+    info = hc_bloom_info(h)
+    _check(_lib.hc_bloom_dump(h, _dptr(dst, torch.uint32, "dst", info.blocks * info.block_words), _stream(stream)),
+           "hc_bloom_dump")
+
+
+class Bloom:
+    """Blocked Bloom filter handle (see ``hc_bloom_create``)."""
+
+    def __init__(self, bits, block_words=16, group=4, seed=None, device=None):
+        p = hc_default_bloom_params()
+        p.block_words, p.group = block_words, group
+        if seed is not None:
+            p.seed = seed & (2**64 - 1)
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        with torch.cuda.device(self.device):
+            self.handle = hc_bloom_create(bits, p)
+        info = hc_bloom_info(self.handle)
+        self.blocks, self.block_words, self.group, self.seed = (
+            int(info.blocks), int(info.block_words), int(info.group), int(info.seed))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            with torch.cuda.device(self.device):
+                hc_bloom_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def clear(self, stream=None):
+        hc_bloom_clear(self.handle, stream)
+
+    def insert(self, keys, group=0, stream=None):
+        hc_bloom_insert(self.handle, keys, group, stream)
+
+    def contains(self, keys, group=0, stream=None):
+        found = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
+        hc_bloom_contains(self.handle, keys, found, group, stream)
+        return found
+
+    def dump(self, stream=None):
+        out = torch.empty(self.blocks * self.block_words, dtype=torch.uint32, device=self.device)
+        hc_bloom_dump(self.handle, out, stream)
         return out

@@ -17,6 +17,7 @@
 #include "hc.h"
 #include "hc_batch.hpp"
 #include "hc_bucket.hpp"
+#include "hc_set.hpp"
 #include "hc_wide.hpp"
 #include "hc_device.hpp"
 #include "hc_group.hpp"
@@ -189,7 +190,7 @@ static hc_err ensure_ws(hc_table_s* t, uint64_t bytes) {
   return HC_OK;
 }
 
-static uint64_t slot_bytes(uint32_t kind) { return kind == HC_SINGLE_VALUE_64 ? 16 : 8; }
+static uint64_t slot_bytes(uint32_t kind) { return kind == HC_SINGLE_VALUE_64 ? 16 : kind == HC_HASH_SET ? 4 : 8; }
 
 static BucketView bview_of(const hc_table_s* t) {
   BucketView b{};
@@ -220,6 +221,13 @@ static hc_err next_bucket_batch(hc_table_s* t, hipStream_t s) {
 static hc_err not_wide(hc_table t, const char* what) {
   if (t != nullptr && t->kind == HC_SINGLE_VALUE_64)
     return fail(HC_E_KIND, "%s: 64-bit tables take hc_insert64 / hc_retrieve64 / hc_erase64", what);
+  return HC_OK;
+}
+
+// Table-only entry points on a set.
+static hc_err not_set(hc_table t, const char* what) {
+  if (t != nullptr && t->kind == HC_HASH_SET)
+    return fail(HC_E_KIND, "%s: sets take hc_insert / hc_retrieve / hc_erase", what);
   return HC_OK;
 }
 
@@ -292,7 +300,8 @@ hc_err build_plan(const hc_batch_op* ops, uint32_t count, int dev, PlanHost* out
     const hc_batch_op& o = ops[j];
     if (o.table == nullptr) return fail(HC_E_ARG, "op %u: table is NULL", j);
     const hc_table_s* t = o.table;
-    if (t->kind == HC_MULTI_VALUE || t->kind == HC_BUCKET_LIST || t->kind == HC_SINGLE_VALUE_64)
+    if (t->kind == HC_MULTI_VALUE || t->kind == HC_BUCKET_LIST || t->kind == HC_SINGLE_VALUE_64 ||
+        t->kind == HC_HASH_SET)
       return fail(HC_E_KIND, "op %u: batched operations take single-value or counting tables", j);
     if (t->device != dev) return fail(HC_E_ARG, "op %u: table lives on device %d, current device is %d", j, t->device, dev);
     if (o.op > HC_OP_ERASE) return fail(HC_E_ARG, "op %u: unknown operation %u", j, o.op);
@@ -454,12 +463,14 @@ static hc_err create_table(hc_table* out, uint32_t kind, uint64_t capacity, cons
                            void* ext_slots, uint64_t ext_bytes) {
   if (out == nullptr) return fail(HC_E_ARG, "out is NULL");
   *out = nullptr;
-  if (kind > 4) return fail(HC_E_ARG, "unknown table kind %u", kind);
+  if (kind > HC_HASH_SET) return fail(HC_E_ARG, "unknown table kind %u", kind);
   hc_params p;
   uint64_t P = 0;
   if (hc_err r = table_geometry(capacity, params, &p, &P); r != HC_OK) return r;
   if (kind == HC_SINGLE_VALUE_64 && p.group > p.window)
     return fail(HC_E_ARG, "64-bit tables need group <= window (group %u, window %u)", p.group, p.window);
+  if (kind == HC_HASH_SET && p.group > p.window)
+    return fail(HC_E_ARG, "sets need group <= window (group %u, window %u)", p.group, p.window);
   if (ext_slots != nullptr) {
     if ((reinterpret_cast<uintptr_t>(ext_slots) & 255) != 0) return fail(HC_E_ARG, "slot array is not 256-byte aligned");
     if (ext_bytes < P * p.window * slot_bytes(kind))
@@ -675,6 +686,11 @@ hc_err hc_insert(hc_table t, const uint32_t* d_keys, const uint32_t* d_values, u
   if ((r = resolve_group(t, group, &g)) != HC_OK) return r;
   if (n == 0) return HC_OK;
   if (d_keys == nullptr) return fail(HC_E_ARG, "keys is NULL");
+  if (t->kind == HC_HASH_SET) {
+    if (d_values != nullptr) return fail(HC_E_ARG, "sets take no values");
+    if ((r = set_device(t)) != HC_OK) return r;
+    return launch_set(SET_INSERT, view_of(t), g, t->window, d_keys, n, d_status, (hipStream_t)stream);
+  }
   if (t->kind == HC_COUNTING) {
     if (d_values != nullptr) return fail(HC_E_ARG, "counting tables take no values");
   } else if (d_values == nullptr) {
@@ -699,7 +715,13 @@ hc_err hc_retrieve(hc_table t, const uint32_t* d_keys, uint64_t n, uint32_t* d_v
   if ((r = resolve_group(t, group, &g)) != HC_OK) return r;
   if (n == 0) return HC_OK;
   if (d_keys == nullptr) return fail(HC_E_ARG, "keys is NULL");
+  if (t->kind == HC_HASH_SET) {
+    if (d_values_out != nullptr) return fail(HC_E_ARG, "sets return no values");
+    if (d_found_out == nullptr) return fail(HC_E_ARG, "found is NULL");
+  }
   if ((r = set_device(t)) != HC_OK) return r;
+  if (t->kind == HC_HASH_SET)
+    return launch_set(SET_CONTAINS, view_of(t), g, t->window, d_keys, n, d_found_out, (hipStream_t)stream);
   if (t->kind == HC_MULTI_VALUE)
     return launch_count_multi(view_of(t), g, t->window, d_keys, n, d_values_out, nullptr, d_found_out, 0xFFFFFFFFu,
                               nullptr, nullptr, (hipStream_t)stream);
@@ -716,6 +738,8 @@ hc_err hc_erase(hc_table t, const uint32_t* d_keys, uint64_t n, uint8_t* d_statu
   if (d_keys == nullptr) return fail(HC_E_ARG, "keys is NULL");
   if ((r = set_device(t)) != HC_OK) return r;
   if (t->kind == HC_BUCKET_LIST) return launch_bl_erase(view_of(t), g, t->window, d_keys, n, d_status, (hipStream_t)stream);
+  if (t->kind == HC_HASH_SET)
+    return launch_set(SET_ERASE, view_of(t), g, t->window, d_keys, n, d_status, (hipStream_t)stream);
   return launch_erase(view_of(t), (int)t->kind, g, t->window, d_keys, n, d_status, (hipStream_t)stream);
 }
 
@@ -724,6 +748,7 @@ hc_err hc_count_values(hc_table t, const uint32_t* d_keys, uint64_t n, uint32_t*
   hc_err r = check_table(t);
   if (r != HC_OK) return r;
   if ((r = not_wide(t, "hc_count_values")) != HC_OK) return r;
+  if ((r = not_set(t, "hc_count_values")) != HC_OK) return r;
   if (t->kind != HC_MULTI_VALUE && t->kind != HC_BUCKET_LIST)
     return fail(HC_E_KIND, "count_values needs a multi-value or bucket list table");
   uint32_t g;
@@ -777,6 +802,7 @@ hc_err hc_retrieve_all(hc_table t, const uint32_t* d_keys, uint64_t n, const uin
   hc_err r = check_table(t);
   if (r != HC_OK) return r;
   if ((r = not_wide(t, "hc_retrieve_all")) != HC_OK) return r;
+  if ((r = not_set(t, "hc_retrieve_all")) != HC_OK) return r;
   if (t->kind != HC_MULTI_VALUE && t->kind != HC_BUCKET_LIST)
     return fail(HC_E_KIND, "retrieve_all needs a multi-value or bucket list table");
   uint32_t g;
@@ -804,6 +830,7 @@ hc_err hc_insert_grouped(hc_table t, const uint32_t* d_keys, const uint32_t* d_v
   hc_err r = check_table(t);
   if (r != HC_OK) return r;
   if ((r = not_wide(t, "hc_insert_grouped")) != HC_OK) return r;
+  if ((r = not_set(t, "hc_insert_grouped")) != HC_OK) return r;
   if (t->kind == HC_SINGLE_VALUE)
     return fail(HC_E_KIND, "grouped insert needs a multi-value, counting or bucket list table");
   if (n == 0) return HC_OK;
@@ -903,6 +930,7 @@ hc_err hc_stats(hc_table t, hc_table_stats* h_out, void* stream) {
   hc_err r = check_table(t);
   if (r != HC_OK) return r;
   if ((r = not_wide(t, "hc_stats")) != HC_OK) return r;
+  if ((r = not_set(t, "hc_stats")) != HC_OK) return r;
   if (h_out == nullptr) return fail(HC_E_ARG, "out is NULL");
   static_assert(HC_PROBE_BUCKETS == STATS_BUCKETS, "histogram width");
   static_assert(sizeof(hc_table_stats) == (5 + STATS_BUCKETS) * sizeof(uint64_t), "stats layout");
@@ -928,6 +956,7 @@ hc_err hc_device_view(hc_table t, void* h_view, uint64_t bytes) {
   hc_err r = check_table(t);
   if (r != HC_OK) return r;
   if ((r = not_wide(t, "hc_device_view")) != HC_OK) return r;
+  if ((r = not_set(t, "hc_device_view")) != HC_OK) return r;
   if (h_view == nullptr) return fail(HC_E_ARG, "view is NULL");
   if (bytes != sizeof(TableView)) return fail(HC_E_ARG, "view takes %zu bytes, not %llu", sizeof(TableView),
                                               (unsigned long long)bytes);
