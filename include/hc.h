@@ -51,14 +51,15 @@ typedef struct hc_table_s* hc_table;
 
 /* Table kinds (Sec. IV: SingleValueHashTable, MultiValueHashTable, CountingHashTable,
  * BucketListHashTable, made by hc_create_bucket_list; single-value tables of 64-bit keys and
- * values; HashSet). */
+ * values in the array-of-structures and structure-of-arrays layouts of Sec. IV-B1; HashSet). */
 enum {
   HC_SINGLE_VALUE = 0,
   HC_MULTI_VALUE = 1,
   HC_COUNTING = 2,
   HC_BUCKET_LIST = 3,
   HC_SINGLE_VALUE_64 = 4,
-  HC_HASH_SET = 5
+  HC_HASH_SET = 5,
+  HC_SINGLE_VALUE_64_SOA = 6
 };
 
 /* Outer probing schemes over windows (Sec. II):
@@ -135,7 +136,14 @@ hc_err hc_create_in(hc_table* out, uint32_t kind, void* d_slots, uint64_t slot_b
  * statuses and errors as hc_insert / hc_retrieve / hc_erase with uint64 keys and values.
  * hc_size, hc_load_factor, hc_capacity, hc_info, hc_clear, hc_destroy apply; hc_dump_slots
  * copies 2*C uint64 words; hc_create_in needs 16 bytes per slot (hc_table_bytes counts 8).
- * The 32-bit entry points, hc_stats, hc_device_view, batches and the server return HC_E_KIND. */
+ * The 32-bit entry points, hc_stats, hc_device_view, batches and the server return HC_E_KIND.
+ *
+ * Kind HC_SINGLE_VALUE_64_SOA: the same table in the structure-of-arrays layout: C key words,
+ * then C value words, in one allocation of 16 * C bytes (hc_dump_slots copies the C keys, then
+ * the C values).  Probing reads only key words (W = 16 keys: one 128-byte line) and a hit reads
+ * one value word; the value is written after the key's CAS with a relaxed atomic store.  A
+ * reader in the same launch as an insert may see the key before its value (the torn read of a
+ * key-only CAS); a later launch sees whole pairs.  Same entry points, statuses and errors. */
 hc_err hc_insert64(hc_table table, const uint64_t* d_keys, const uint64_t* d_values, uint64_t n, uint8_t* d_status,
                    uint32_t group, void* stream);
 hc_err hc_retrieve64(hc_table table, const uint64_t* d_keys, uint64_t n, uint64_t* d_values_out,

@@ -30,9 +30,10 @@ E_OK, E_ARG, E_NOMEM, E_KIND, E_DEVICE = 0, 1, 2, 3, 4
 OP_INSERT, OP_RETRIEVE, OP_ERASE = 0, 1, 2
 
 SCHEMES = {"linear": LINEAR, "quadratic": QUADRATIC, "double": DOUBLE}
-BUCKET_LIST, SINGLE_VALUE_64, HASH_SET = 3, 4, 5
+BUCKET_LIST, SINGLE_VALUE_64, HASH_SET, SINGLE_VALUE_64_SOA = 3, 4, 5, 6
 KINDS = {"single": SINGLE_VALUE, "multi": MULTI_VALUE, "counting": COUNTING, "bucket": BUCKET_LIST,
-         "single64": SINGLE_VALUE_64, "set": HASH_SET}
+         "single64": SINGLE_VALUE_64, "set": HASH_SET, "single64_soa": SINGLE_VALUE_64_SOA}
+WIDE_KINDS = (SINGLE_VALUE_64, SINGLE_VALUE_64_SOA)
 
 
 class HcParams(ctypes.Structure):
@@ -368,7 +369,8 @@ def hc_info(h: int) -> HcTableInfo:
 def slot_words(h: int) -> int:
     """uint64 words of a table's slot array: C, 2C for 64-bit tables, C/2 for sets."""
     info = hc_info(h)
-    return {SINGLE_VALUE_64: 2 * info.capacity, HASH_SET: info.capacity // 2}.get(info.kind, info.capacity)
+    return {SINGLE_VALUE_64: 2 * info.capacity, SINGLE_VALUE_64_SOA: 2 * info.capacity,
+            HASH_SET: info.capacity // 2}.get(info.kind, info.capacity)
 
 
 def hc_dump_slots(h: int, dst, stream=None):
@@ -621,7 +623,7 @@ class Table:
 
     def insert(self, keys, values=None, status=False, group=0, stream=None):
         st = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device) if status else None
-        if self.kind == SINGLE_VALUE_64:
+        if self.kind in WIDE_KINDS:
             hc_insert64(self.handle, keys, values, st, group, stream)
         else:
             hc_insert(self.handle, keys, values, st, group, stream)
@@ -633,7 +635,7 @@ class Table:
             found = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
             hc_retrieve(self.handle, keys, None, found, group, stream)
             return None, found
-        wide = self.kind == SINGLE_VALUE_64
+        wide = self.kind in WIDE_KINDS
         vals = torch.empty(keys.numel(), dtype=torch.uint64 if wide else torch.uint32, device=keys.device)
         found = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
         (hc_retrieve64 if wide else hc_retrieve)(self.handle, keys, vals, found, group, stream)
@@ -641,7 +643,7 @@ class Table:
 
     def erase(self, keys, status=False, group=0, stream=None):
         st = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device) if status else None
-        (hc_erase64 if self.kind == SINGLE_VALUE_64 else hc_erase)(self.handle, keys, st, group, stream)
+        (hc_erase64 if self.kind in WIDE_KINDS else hc_erase)(self.handle, keys, st, group, stream)
         return st
 
     def count_values(self, keys, group=0, stream=None):
@@ -680,7 +682,8 @@ class Table:
                 "probe_sum": st.probe_sum, "probe_hist": list(st.probe_hist)}
 
     def dump_slots(self, stream=None):
-        """The slot array: C uint64 words (2C for 64-bit tables); a set's C uint32 keys."""
+        """The slot array: C uint64 words (2C for 64-bit tables: pairs, or C keys then C values in the
+        structure-of-arrays layout); a set's C uint32 keys."""
         out = torch.empty(slot_words(self.handle), dtype=torch.uint64, device=self.device)
         hc_dump_slots(self.handle, out, stream)
         return out.view(torch.uint32) if self.kind == HASH_SET else out

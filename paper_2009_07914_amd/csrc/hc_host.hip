@@ -190,7 +190,9 @@ static hc_err ensure_ws(hc_table_s* t, uint64_t bytes) {
   return HC_OK;
 }
 
-static uint64_t slot_bytes(uint32_t kind) { return kind == HC_SINGLE_VALUE_64 ? 16 : kind == HC_HASH_SET ? 4 : 8; }
+static bool is_wide(uint32_t kind) { return kind == HC_SINGLE_VALUE_64 || kind == HC_SINGLE_VALUE_64_SOA; }
+
+static uint64_t slot_bytes(uint32_t kind) { return is_wide(kind) ? 16 : kind == HC_HASH_SET ? 4 : 8; }
 
 static BucketView bview_of(const hc_table_s* t) {
   BucketView b{};
@@ -219,7 +221,7 @@ static hc_err next_bucket_batch(hc_table_s* t, hipStream_t s) {
 
 // 32-bit entry points on a 64-bit table.
 static hc_err not_wide(hc_table t, const char* what) {
-  if (t != nullptr && t->kind == HC_SINGLE_VALUE_64)
+  if (t != nullptr && is_wide(t->kind))
     return fail(HC_E_KIND, "%s: 64-bit tables take hc_insert64 / hc_retrieve64 / hc_erase64", what);
   return HC_OK;
 }
@@ -300,8 +302,7 @@ hc_err build_plan(const hc_batch_op* ops, uint32_t count, int dev, PlanHost* out
     const hc_batch_op& o = ops[j];
     if (o.table == nullptr) return fail(HC_E_ARG, "op %u: table is NULL", j);
     const hc_table_s* t = o.table;
-    if (t->kind == HC_MULTI_VALUE || t->kind == HC_BUCKET_LIST || t->kind == HC_SINGLE_VALUE_64 ||
-        t->kind == HC_HASH_SET)
+    if (t->kind == HC_MULTI_VALUE || t->kind == HC_BUCKET_LIST || is_wide(t->kind) || t->kind == HC_HASH_SET)
       return fail(HC_E_KIND, "op %u: batched operations take single-value or counting tables", j);
     if (t->device != dev) return fail(HC_E_ARG, "op %u: table lives on device %d, current device is %d", j, t->device, dev);
     if (o.op > HC_OP_ERASE) return fail(HC_E_ARG, "op %u: unknown operation %u", j, o.op);
@@ -463,11 +464,11 @@ static hc_err create_table(hc_table* out, uint32_t kind, uint64_t capacity, cons
                            void* ext_slots, uint64_t ext_bytes) {
   if (out == nullptr) return fail(HC_E_ARG, "out is NULL");
   *out = nullptr;
-  if (kind > HC_HASH_SET) return fail(HC_E_ARG, "unknown table kind %u", kind);
+  if (kind > HC_SINGLE_VALUE_64_SOA) return fail(HC_E_ARG, "unknown table kind %u", kind);
   hc_params p;
   uint64_t P = 0;
   if (hc_err r = table_geometry(capacity, params, &p, &P); r != HC_OK) return r;
-  if (kind == HC_SINGLE_VALUE_64 && p.group > p.window)
+  if (is_wide(kind) && p.group > p.window)
     return fail(HC_E_ARG, "64-bit tables need group <= window (group %u, window %u)", p.group, p.window);
   if (kind == HC_HASH_SET && p.group > p.window)
     return fail(HC_E_ARG, "sets need group <= window (group %u, window %u)", p.group, p.window);
@@ -857,14 +858,15 @@ static hc_err wide_call(hc_table t, int op, const uint64_t* keys, const uint64_t
                         uint64_t* values_out, uint8_t* flags, uint32_t group, void* stream) {
   hc_err r = check_table(t);
   if (r != HC_OK) return r;
-  if (t->kind != HC_SINGLE_VALUE_64) return fail(HC_E_KIND, "64-bit entry points need a 64-bit table");
+  if (!is_wide(t->kind)) return fail(HC_E_KIND, "64-bit entry points need a 64-bit table");
   uint32_t g;
   if ((r = resolve_group(t, group, &g)) != HC_OK) return r;
   if (n == 0) return HC_OK;
   if (keys == nullptr) return fail(HC_E_ARG, "keys is NULL");
   if (op == WIDE_INSERT && values == nullptr) return fail(HC_E_ARG, "values is NULL");
   if ((r = set_device(t)) != HC_OK) return r;
-  return launch_wide(op, view_of(t), g, t->window, keys, values, n, values_out, flags, (hipStream_t)stream);
+  return launch_wide(op, t->kind == HC_SINGLE_VALUE_64_SOA, view_of(t), g, t->window, keys, values, n, values_out,
+                     flags, (hipStream_t)stream);
 }
 
 hc_err hc_insert64(hc_table t, const uint64_t* d_keys, const uint64_t* d_values, uint64_t n, uint8_t* d_status,

@@ -355,7 +355,7 @@ hc_err hc_server_submit(hc_server s, const hc_request* req, uint64_t* h_ticket) 
   hc_table_info info;
   if (hc_err e = hc_info(r.table, &info); e != HC_OK) return e;
   if (info.kind == HC_MULTI_VALUE || info.kind == HC_BUCKET_LIST || info.kind == HC_SINGLE_VALUE_64 ||
-      info.kind == HC_HASH_SET)
+      info.kind == HC_SINGLE_VALUE_64_SOA || info.kind == HC_HASH_SET)
     return fail(HC_E_KIND, "requests take single-value or counting tables");
   if (r.group != 0 && (r.group > 64 || (r.group & (r.group - 1)) != 0))
     return fail(HC_E_ARG, "group size %u is not a power of two in [1, 64]", r.group);

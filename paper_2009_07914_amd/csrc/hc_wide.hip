@@ -1,15 +1,22 @@
 // Single-value table with 64-bit keys and 64-bit values (the wider types of
-// Sec. IV-B1, array-of-structures layout): a slot is 16 bytes, key word then
-// value word; the empty key is 0 and the tombstone key 2^64 - 1 (value 0).
-// A window of W = 8 slots is one 128-byte line.
+// Sec. IV-B1), in either layout the paper names:
+//  * array of structures (AoS): a slot is 16 bytes, key word then value word;
+//    a window of W = 8 slots is one 128-byte line;
+//  * structure of arrays (SoA): C key words, then C value words, in one
+//    allocation; a window's keys (W = 16: one 128-byte line) are probed without
+//    touching values, and a hit reads one value word.
+// The empty key is 0 and the tombstone key 2^64 - 1 (value 0).
 //
 // The probe is the cooperative scheme of the 32-bit tables (Sec. IV-B2): a group
 // of G <= W lanes loads a whole window (W/G slots per lane, 16-byte loads),
 // votes with a ballot and claims the first reusable slot once the window shows
 // the key absent up to an empty slot.  A claim is a 64-bit CAS of the key word
-// only; the value word is then written with an atomic exchange, so a reader in
-// a later launch sees a whole pair.  Within one launch an update of a present
-// key is an exchange of its value word (which of a repeated key's values
+// only; the value word is then written (AoS: atomic exchange; SoA: a relaxed
+// atomic store), so a reader in a later launch sees a whole pair.  Within one
+// launch a reader may find a freshly claimed key before its value store lands
+// (the torn-read hazard of a key-only CAS): inserts and queries of one table
+// belong in different launches, as for every table here.  An update of a
+// present key rewrites its value word (which of a repeated key's values
 // survives is unspecified, as for the 32-bit table).  Hash: h1 and h2 are the
 // low and high halves of fmix64(k ^ seed), MurmurHash3's 64-bit finaliser.
 #include "hc_kernels.hpp"
@@ -41,8 +48,27 @@ __device__ __forceinline__ void seq_start64(const TableView& t, uint64_t k, Seq&
 
 __device__ __forceinline__ bool reserved64(uint64_t k) { return k == KEY64_EMPTY || k == KEY64_TOMB; }
 
-// One group's view of a window: SPL slots per lane, keys and values.
-template <int G, int W>
+// Key and value words of slot idx (C = P * W slots).
+template <bool SOA>
+__device__ __forceinline__ unsigned long long* key_word(const TableView& t, uint64_t idx) {
+  return (unsigned long long*)(SOA ? t.slots + idx : t.slots + 2 * idx);
+}
+template <bool SOA, int W>
+__device__ __forceinline__ unsigned long long* value_word(const TableView& t, uint64_t idx) {
+  return (unsigned long long*)(SOA ? t.slots + (uint64_t)t.P * W + idx : t.slots + 2 * idx + 1);
+}
+template <bool SOA, int W>
+__device__ __forceinline__ void store_value(const TableView& t, uint64_t idx, uint64_t v) {
+  if constexpr (SOA) {
+    __hip_atomic_store(value_word<true, W>(t, idx), (unsigned long long)v, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    atomicExch(value_word<false, W>(t, idx), (unsigned long long)v);
+  }
+}
+
+// One group's view of a window: SPL slots per lane, keys (and values, AoS).
+template <int G, int W, bool SOA>
 struct Wide {
   static_assert(G <= W, "64-bit tables take groups no larger than the window");
   static constexpr int SPL = W / G;
@@ -57,30 +83,45 @@ struct Wide {
   __device__ __forceinline__ void advance(const TableView& t) { seq_next(t, s); }
   __device__ __forceinline__ void load(const TableView& t, uint64_t k) {
     first = (uint64_t)s.w * W + (uint64_t)g.glane * SPL;
-    const ulonglong2* p = reinterpret_cast<const ulonglong2*>(t.slots) + first;
+    if constexpr (SOA) {
+      if constexpr (SPL % 2 == 0) {
+        const ulonglong2* p = reinterpret_cast<const ulonglong2*>(t.slots + first);
+#pragma unroll
+        for (int j = 0; j < SPL / 2; ++j) {
+          const ulonglong2 q = p[j];
+          key[2 * j] = q.x;
+          key[2 * j + 1] = q.y;
+        }
+      } else {
+        key[0] = t.slots[first];
+      }
+    } else {
+      const ulonglong2* p = reinterpret_cast<const ulonglong2*>(t.slots) + first;
+#pragma unroll
+      for (int j = 0; j < SPL; ++j) {
+        const ulonglong2 q = p[j];
+        key[j] = q.x;
+        val[j] = q.y;
+      }
+    }
     match = empty = tomb = 0;
 #pragma unroll
     for (int j = 0; j < SPL; ++j) {
-      const ulonglong2 q = p[j];
-      key[j] = q.x;
-      val[j] = q.y;
-      match |= (MaskT<SPL>)(q.x == k) << j;
-      empty |= (MaskT<SPL>)(q.x == KEY64_EMPTY) << j;
-      tomb |= (MaskT<SPL>)(q.x == KEY64_TOMB) << j;
+      match |= (MaskT<SPL>)(key[j] == k) << j;
+      empty |= (MaskT<SPL>)(key[j] == KEY64_EMPTY) << j;
+      tomb |= (MaskT<SPL>)(key[j] == KEY64_TOMB) << j;
     }
+  }
+  // Value of this lane's lowest matching slot (AoS: already loaded; SoA: one load).
+  __device__ __forceinline__ uint64_t matched_value(const TableView& t) const {
+    if constexpr (SOA) return *value_word<true, W>(t, first + lowbit(match));
+    else return pick_lowest<SPL>(val, match);
   }
 };
 
-__device__ __forceinline__ unsigned long long* key_word(const TableView& t, uint64_t idx) {
-  return (unsigned long long*)(t.slots + 2 * idx);
-}
-__device__ __forceinline__ unsigned long long* value_word(const TableView& t, uint64_t idx) {
-  return (unsigned long long*)(t.slots + 2 * idx + 1);
-}
-
-template <int G, int W>
+template <int G, int W, bool SOA>
 struct WideInsert {
-  Wide<G, W> ln;
+  Wide<G, W, SOA> ln;
   TableView t;
   const uint64_t* __restrict__ keys;
   const uint64_t* __restrict__ values;
@@ -106,14 +147,14 @@ struct WideInsert {
   }
   // CAS the key word of a reusable slot: 1 claimed, 2 found the key there (updated), 3 lost to another key.
   __device__ __forceinline__ uint32_t claim(uint64_t idx, uint64_t expect) {
-    const uint64_t r = atomicCAS(key_word(t, idx), (unsigned long long)expect, (unsigned long long)k);
+    const uint64_t r = atomicCAS(key_word<SOA>(t, idx), (unsigned long long)expect, (unsigned long long)k);
     if (r == expect) {
-      atomicExch(value_word(t, idx), (unsigned long long)v);
+      store_value<SOA, W>(t, idx, v);
       ++added;
       return 1;
     }
     if (r == k) {
-      atomicExch(value_word(t, idx), (unsigned long long)v);
+      store_value<SOA, W>(t, idx, v);
       return 2;
     }
     return 3;
@@ -124,11 +165,11 @@ struct WideInsert {
     ln.load(t, k);
     const uint64_t b_match = g.bits(ln.match != 0);
     if (b_match) {  // present: replace the value
-      if (g.glane == (uint32_t)ffs64(b_match)) atomicExch(value_word(t, ln.first + lowbit(ln.match)), (unsigned long long)v);
+      if (g.glane == (uint32_t)ffs64(b_match)) store_value<SOA, W>(t, ln.first + lowbit(ln.match), v);
       return done(ST_DUPLICATE);
     }
     const bool any_empty = g.bits(ln.empty != 0) != 0;
-    MaskT<Wide<G, W>::SPL> reuse = ln.empty | ln.tomb;
+    MaskT<Wide<G, W, SOA>::SPL> reuse = ln.empty | ln.tomb;
     uint64_t b_reuse = g.bits(reuse != 0);
     const bool last = ln.exhausted(t);
     if (any_empty || last) {
@@ -168,9 +209,9 @@ struct WideInsert {
   __device__ __forceinline__ void end() { wave_add_to(t.size, added); }
 };
 
-template <int G, int W>
+template <int G, int W, bool SOA>
 struct WideRetrieve {
-  Wide<G, W> ln;
+  Wide<G, W, SOA> ln;
   TableView t;
   const uint64_t* __restrict__ keys;
   uint64_t* __restrict__ values_out;
@@ -194,7 +235,7 @@ struct WideRetrieve {
     ln.load(t, k);
     const uint64_t b_match = g.bits(ln.match != 0);
     if (b_match) {
-      if (g.glane == (uint32_t)ffs64(b_match)) out(pick_lowest<Wide<G, W>::SPL>(ln.val, ln.match), 1);
+      if (g.glane == (uint32_t)ffs64(b_match)) out(ln.matched_value(t), 1);
       return true;
     }
     if (g.bits(ln.empty != 0) || ln.exhausted(t)) return g.glane == 0 ? out(0, 0) : true;
@@ -204,9 +245,9 @@ struct WideRetrieve {
   __device__ __forceinline__ void end() {}
 };
 
-template <int G, int W>
+template <int G, int W, bool SOA>
 struct WideErase {
-  Wide<G, W> ln;
+  Wide<G, W, SOA> ln;
   TableView t;
   const uint64_t* __restrict__ keys;
   uint8_t* __restrict__ status;
@@ -233,8 +274,8 @@ struct WideErase {
       uint32_t ok = 0;
       if (g.glane == r) {
         const uint64_t idx = ln.first + lowbit(ln.match);
-        if (atomicCAS(key_word(t, idx), (unsigned long long)k, (unsigned long long)KEY64_TOMB) == k) {
-          atomicExch(value_word(t, idx), 0ull);
+        if (atomicCAS(key_word<SOA>(t, idx), (unsigned long long)k, (unsigned long long)KEY64_TOMB) == k) {
+          store_value<SOA, W>(t, idx, 0);
           ok = 1;
           --added;
         }
@@ -248,11 +289,11 @@ struct WideErase {
   __device__ __forceinline__ void end() { wave_add_to(t.size, added); }
 };
 
-template <int G, int W>
+template <int G, int W, bool SOA>
 __global__ __launch_bounds__(BLOCK) void k_wide_insert(TableView t, WorkCtl ctl, const uint64_t* __restrict__ keys,
                                                        const uint64_t* __restrict__ values, uint64_t n,
                                                        uint8_t* __restrict__ status) {
-  WideInsert<G, W> op;
+  WideInsert<G, W, SOA> op;
   op.t = t;
   op.keys = keys;
   op.values = values;
@@ -260,11 +301,11 @@ __global__ __launch_bounds__(BLOCK) void k_wide_insert(TableView t, WorkCtl ctl,
   drive<G>(n, ctl, op);
 }
 
-template <int G, int W>
+template <int G, int W, bool SOA>
 __global__ __launch_bounds__(BLOCK) void k_wide_retrieve(TableView t, WorkCtl ctl, const uint64_t* __restrict__ keys,
                                                          uint64_t n, uint64_t* __restrict__ values_out,
                                                          uint8_t* __restrict__ found_out) {
-  WideRetrieve<G, W> op;
+  WideRetrieve<G, W, SOA> op;
   op.t = t;
   op.keys = keys;
   op.values_out = values_out;
@@ -272,10 +313,10 @@ __global__ __launch_bounds__(BLOCK) void k_wide_retrieve(TableView t, WorkCtl ct
   drive<G>(n, ctl, op);
 }
 
-template <int G, int W>
+template <int G, int W, bool SOA>
 __global__ __launch_bounds__(BLOCK) void k_wide_erase(TableView t, WorkCtl ctl, const uint64_t* __restrict__ keys,
                                                       uint64_t n, uint8_t* __restrict__ status) {
-  WideErase<G, W> op;
+  WideErase<G, W, SOA> op;
   op.t = t;
   op.keys = keys;
   op.status = status;
@@ -296,25 +337,33 @@ static hc_err dispatch_wide(uint32_t G, uint32_t W, F&& f) {
   });
 }
 
-hc_err launch_wide(int op, const TableView& t, uint32_t G, uint32_t W, const uint64_t* keys, const uint64_t* values,
-                   uint64_t n, uint64_t* values_out, uint8_t* flags, hipStream_t s) {
+template <bool SOA>
+static hc_err launch_wide_layout(int op, const TableView& t, uint32_t G, uint32_t W, const uint64_t* keys,
+                                 const uint64_t* values, uint64_t n, uint64_t* values_out, uint8_t* flags,
+                                 hipStream_t s) {
   return dispatch_wide(G, W, [&](auto g, auto w) -> hc_err {
     constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
     if (op == WIDE_INSERT) {
-      auto k = k_wide_insert<GG, WW>;
+      auto k = k_wide_insert<GG, WW, SOA>;
       const unsigned grid = grid_for(k, n, GG);
       hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid), keys, values, n, flags);
     } else if (op == WIDE_RETRIEVE) {
-      auto k = k_wide_retrieve<GG, WW>;
+      auto k = k_wide_retrieve<GG, WW, SOA>;
       const unsigned grid = grid_for(k, n, GG);
       hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid), keys, n, values_out, flags);
     } else {
-      auto k = k_wide_erase<GG, WW>;
+      auto k = k_wide_erase<GG, WW, SOA>;
       const unsigned grid = grid_for(k, n, GG);
       hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid), keys, n, flags);
     }
     return check_launch("64-bit table");
   });
+}
+
+hc_err launch_wide(int op, bool soa, const TableView& t, uint32_t G, uint32_t W, const uint64_t* keys,
+                   const uint64_t* values, uint64_t n, uint64_t* values_out, uint8_t* flags, hipStream_t s) {
+  return soa ? launch_wide_layout<true>(op, t, G, W, keys, values, n, values_out, flags, s)
+             : launch_wide_layout<false>(op, t, G, W, keys, values, n, values_out, flags, s);
 }
 
 }  // namespace hc

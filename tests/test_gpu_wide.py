@@ -29,16 +29,22 @@ def _vals64(seed, n):
 
 
 def _layout(t):
-    rc, st = oracle.check_layout64(h(t.dump_slots()), t.windows, t.window, t.scheme, t.seed)
+    raw = h(t.dump_slots())
+    if t.kind == 6:  # structure of arrays: C keys, then C values -> interleave for the checker
+        pairs = np.empty(2 * t.capacity, dtype=np.uint64)
+        pairs[0::2], pairs[1::2] = raw[: t.capacity], raw[t.capacity:]
+        raw = pairs
+    rc, st = oracle.check_layout64(raw, t.windows, t.window, t.scheme, t.seed)
     assert rc == 0, f"layout code {rc} at slot {st['first_bad_slot']}"
     return st
 
 
+@pytest.mark.parametrize("kind", ["single64", "single64_soa"])
 @pytest.mark.parametrize("scheme", list(SCHEMES))
-@pytest.mark.parametrize("window,group", [(8, 1), (8, 2), (8, 4), (8, 8), (16, 4), (32, 16)])
-def test_wide_roundtrip(hc, scheme, window, group):
+@pytest.mark.parametrize("window,group", [(8, 1), (8, 2), (8, 4), (8, 8), (16, 4), (16, 1), (32, 16)])
+def test_wide_roundtrip(hc, kind, scheme, window, group):
     cap = 1 << 15
-    t = hc.Table("single64", cap, scheme=scheme, window=window, group=group, seed=0x5EED)
+    t = hc.Table(kind, cap, scheme=scheme, window=window, group=group, seed=0x5EED)
     n = int(0.85 * t.capacity)
     keys, vals = _keys64(11, 1, n), _vals64(12, n)
     absent = _keys64(11, n + 1, n)
@@ -65,8 +71,9 @@ def test_wide_roundtrip(hc, scheme, window, group):
     assert lay["live"] == n
 
 
-def test_wide_duplicates_reserved_full(hc):
-    t = hc.Table("single64", 64, scheme="double", window=8, group=4)
+@pytest.mark.parametrize("kind", ["single64", "single64_soa"])
+def test_wide_duplicates_reserved_full(hc, kind):
+    t = hc.Table(kind, 64, scheme="double", window=8, group=4)
     M = np.uint64(2**64 - 1)
     k = np.array([0, 2**64 - 1, 5, 5, 2**63, 2**63], dtype=np.uint64)
     v = np.array([1, 2, 3, 4, 5, 5], dtype=np.uint64)
@@ -86,5 +93,20 @@ def test_wide_duplicates_reserved_full(hc):
         hc.hc_retrieve(t.handle, d(np.array([1], np.uint32)), torch.empty(1, dtype=torch.uint32, device="cuda"))
     assert e.value.code == hc.E_KIND
     with pytest.raises(hc.HcError) as e:
-        hc.Table("single64", 64, window=8, group=16)
+        hc.Table(kind, 64, window=8, group=16)
     assert e.value.code == hc.E_ARG
+
+
+def test_wide_soa_layout_is_keys_then_values(hc):
+    """The structure-of-arrays dump holds key i at word i and its value at word C + i."""
+    t = hc.Table("single64_soa", 1 << 12, scheme="linear", window=16, group=4)
+    n = 3000
+    keys, vals = _keys64(51, 1, n), _vals64(52, n)
+    assert np.all(h(t.insert(d(keys), d(vals), status=True)) == hc.S_OK)
+    raw = h(t.dump_slots())
+    ks, vs = raw[: t.capacity], raw[t.capacity:]
+    live = (ks != 0) & (ks != np.uint64(2**64 - 1))
+    assert live.sum() == n
+    got = dict(zip(ks[live].tolist(), vs[live].tolist()))
+    assert got == dict(zip(keys.tolist(), vals.tolist()))
+    assert np.all(vs[~live] == 0)
