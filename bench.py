@@ -234,6 +234,9 @@ def main():
                      "traffic": tr},
         "cpu_baseline": None,
     }
+    out["ceilings"] = _ceilings(hc, table, dev, stream)
+    out["ceilings"]["retrieve_frac_of_gather128"] = round(ret_gbs / out["ceilings"]["gather128_gbs"], 4)
+    out["ceilings"]["insert_frac_of_gather128"] = round(ins_gbs / out["ceilings"]["gather128_gbs"], 4)
     if args.calibrate_copy_mib:
         a = torch.empty(args.calibrate_copy_mib << 20, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)
@@ -244,6 +247,41 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(w, args.cpu_sample_log2)
     print(json.dumps(out), flush=True)
+
+
+def _ceilings(hc, table, dev, s):
+    """Practical bandwidth ceilings of this GPU, measured with the library's diagnostic kernels: a streaming
+    copy of 1 GiB (read + write bytes), a streaming read of it, and gathers of random 64- and 128-byte lines over the table's own
+    2 GiB slot array (as many lines as it holds; no cache holds a useful share of it)."""
+    import torch
+
+    info = hc.hc_info(table.handle)
+    nbytes = info.capacity * 8
+    sink = torch.zeros(1, dtype=torch.uint32, device=dev)
+
+    def timed(fn, reps=5):
+        fn()
+        ms = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(s)
+            fn()
+            b.record(s)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        return statistics.mean(ms)
+
+    res = {}
+    a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    res["copy_gbs"] = round(2 * a.numel() / timed(lambda: hc.hc_diag_copy(b, a, s)) / 1e6, 1)
+    res["read_gbs"] = round(a.numel() / timed(lambda: hc.hc_diag_read(a, sink, s)) / 1e6, 1)
+    del a, b
+    for lb in (64, 128):
+        n_lines = nbytes // lb
+        ms = timed(lambda: hc.hc_diag_gather(info.d_slots, nbytes, lb, n_lines, sink, 0x5EED, s))
+        res[f"gather{lb}_gbs"] = round(n_lines * lb / ms / 1e6, 1)
+    return res
 
 
 def bench_batched(args):

@@ -210,6 +210,19 @@ hc_err hc_bloom_info(hc_bloom filter, hc_bloom_info_t* h_out);
 /* Copy the B * block_words words of the bit array into d_dst (device), on the stream. */
 hc_err hc_bloom_dump(hc_bloom filter, uint32_t* d_dst, void* stream);
 
+/* ---- bandwidth diagnostics (measurement support; not part of any table) -----------------
+ * hc_diag_copy: copy `bytes` (a multiple of 16) from d_src to d_dst with 16-byte vector loads
+ * and stores; hc_diag_read: read them (XOR-reduced into registers): the practical streaming
+ * peaks.  hc_diag_gather: read n_lines lines of line_bytes
+ * (32, 64 or 128) at pseudo-random line indices of the region [d_base, d_base + bytes) (d_base
+ * aligned to line_bytes, at most 2^32 lines): the random-access ceiling a probe of a large table
+ * pays.  d_sink is one device word the kernel may write.  Both are asynchronous on the stream.
+ * Errors: HC_E_ARG for NULL pointers, sizes or alignment as stated. */
+hc_err hc_diag_copy(void* d_dst, const void* d_src, uint64_t bytes, void* stream);
+hc_err hc_diag_read(const void* d_src, uint64_t bytes, uint32_t* d_sink, void* stream);
+hc_err hc_diag_gather(const void* d_base, uint64_t bytes, uint32_t line_bytes, uint64_t n_lines, uint32_t seed,
+                      uint32_t* d_sink, void* stream);
+
 /* ---- bucket list tables (Sec. IV-C) ------------------------------------------------
  * A multi-value table that stores each distinct key once: the key's slot in a
  * cooperative-probing table holds its number of values, and the values live in a list of

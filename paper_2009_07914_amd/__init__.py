@@ -114,6 +114,9 @@ _SIGS = {
     "hc_insert64": ([_p, _p, _p, _u64, _p, _u32, _p], ctypes.c_int),
     "hc_retrieve64": ([_p, _p, _u64, _p, _p, _u32, _p], ctypes.c_int),
     "hc_erase64": ([_p, _p, _u64, _p, _u32, _p], ctypes.c_int),
+    "hc_diag_copy": ([_p, _p, _u64, _p], ctypes.c_int),
+    "hc_diag_read": ([_p, _u64, _p, _p], ctypes.c_int),
+    "hc_diag_gather": ([_p, _u64, _u32, _u64, _u32, _p, _p], ctypes.c_int),
     "hc_default_bloom_params": ([ctypes.POINTER(HcBloomParams)], None),
     "hc_bloom_create": ([ctypes.POINTER(_p), _u64, ctypes.POINTER(HcBloomParams)], ctypes.c_int),
     "hc_bloom_destroy": ([_p], ctypes.c_int),
@@ -775,3 +778,25 @@ class Bloom:
         out = torch.empty(self.blocks * self.block_words, dtype=torch.uint32, device=self.device)
         hc_bloom_dump(self.handle, out, stream)
         return out
+
+
+# ---- bandwidth diagnostics ------------------------------------------------------
+
+def hc_diag_copy(dst, src, stream=None):
+    """Copy src into dst (same byte size, a multiple of 16) with the library's streaming kernel."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nbytes:
+        raise ValueError("dst is smaller than src")
+    _check(_lib.hc_diag_copy(dst.data_ptr(), src.data_ptr(), nbytes, _stream(stream)), "hc_diag_copy")
+
+
+def hc_diag_read(src, sink, stream=None):
+    """Read all of src (a multiple of 16 bytes) with the library's streaming kernel."""
+    _check(_lib.hc_diag_read(src.data_ptr(), src.numel() * src.element_size(), _dptr(sink, torch.uint32, "sink", 1),
+                             _stream(stream)), "hc_diag_read")
+
+
+def hc_diag_gather(base_ptr: int, nbytes: int, line_bytes: int, n_lines: int, sink, seed: int = 1, stream=None):
+    """Read n_lines random lines of line_bytes inside [base_ptr, base_ptr + nbytes) (device memory)."""
+    _check(_lib.hc_diag_gather(base_ptr, nbytes, line_bytes, n_lines, seed, _dptr(sink, torch.uint32, "sink", 1),
+                               _stream(stream)), "hc_diag_gather")
