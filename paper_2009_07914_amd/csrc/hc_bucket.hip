@@ -210,15 +210,23 @@ __global__ __launch_bounds__(256) void k_bl_expand(const uint64_t* __restrict__ 
 // ---- phase 2: buckets per key -----------------------------------------------------------
 
 // Run by every pair; the pair whose ticket is its key's first of the batch
-// allocates.  Pool words are taken with one atomic per wavefront.
-__global__ __launch_bounds__(256) void k_bl_alloc(TableView t, BucketView b, uint64_t n,
-                                                  const uint64_t* __restrict__ pos,
-                                                  const uint32_t* __restrict__ ticket,
-                                                  const uint8_t* __restrict__ st) {
-  const uint64_t stride = (uint64_t)gridDim.x * 256;
-  const uint32_t lane = __lane_id();
-  for (uint64_t i0 = (uint64_t)blockIdx.x * 256 + (threadIdx.x & ~63u); i0 < n; i0 += stride) {
-    const uint64_t i = i0 + lane;
+// allocates.  Pool words are taken with one atomic per block of 1024 pairs (a
+// scan over the block's wavefronts in LDS): every pool atomic hits the same
+// word, so their number, not their bytes, bounds this kernel.
+constexpr int ALLOC_BLOCK = 1024;
+
+__global__ __launch_bounds__(ALLOC_BLOCK) void k_bl_alloc(TableView t, BucketView b, uint64_t n,
+                                                          const uint64_t* __restrict__ pos,
+                                                          const uint32_t* __restrict__ ticket,
+                                                          const uint8_t* __restrict__ st) {
+  constexpr int NW = ALLOC_BLOCK / 64;
+  __shared__ unsigned long long wave_off[NW];
+  __shared__ unsigned long long block_base;
+  const uint64_t stride = (uint64_t)gridDim.x * ALLOC_BLOCK;
+  const uint32_t lane = __lane_id(), wv = threadIdx.x / 64;
+  // the trip count depends only on blockIdx, so every thread of a block reaches each barrier
+  for (uint64_t i0 = (uint64_t)blockIdx.x * ALLOC_BLOCK; i0 < n; i0 += stride) {
+    const uint64_t i = i0 + threadIdx.x;
     uint64_t p = 0, word = 0, b0 = 0, b1 = 0, words = 0;
     bool mine = false;
     if (i < n && st[i] == ST_OK) {
@@ -232,22 +240,32 @@ __global__ __launch_bounds__(256) void k_bl_alloc(TableView t, BucketView b, uin
         words = bl_words(b, b0, b1);
       }
     }
-    // wavefront-wide exclusive scan of the words, one pool atomic
+    // inclusive scan of the words over the wavefront, then over the block's wavefronts
     uint64_t incl = words;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
       const uint32_t lo = __shfl_up((uint32_t)incl, d, 64), hi = __shfl_up((uint32_t)(incl >> 32), d, 64);
       if (lane >= (uint32_t)d) incl += (uint64_t)lo | ((uint64_t)hi << 32);
     }
-    const uint64_t total = ((uint64_t)__shfl((uint32_t)(incl >> 32), 63, 64) << 32) | __shfl((uint32_t)incl, 63, 64);
-    unsigned long long wbase = 0;
-    if (lane == 63 && total) wbase = atomicAdd(b.pool_next, (unsigned long long)total);
-    wbase = ((uint64_t)__shfl((uint32_t)(wbase >> 32), 63, 64) << 32) | __shfl((uint32_t)wbase, 63, 64);
+    if (lane == 63) wave_off[wv] = incl;
+    __syncthreads();
+    if (wv == 0) {
+      const uint64_t tot = lane < (uint32_t)NW ? wave_off[lane] : 0;
+      uint64_t x = tot;
+#pragma unroll
+      for (int d = 1; d < NW; d <<= 1) {
+        const uint32_t lo = __shfl_up((uint32_t)x, d, 64), hi = __shfl_up((uint32_t)(x >> 32), d, 64);
+        if (lane >= (uint32_t)d) x += (uint64_t)lo | ((uint64_t)hi << 32);
+      }
+      if (lane < (uint32_t)NW) wave_off[lane] = x - tot;  // exclusive offset of each wavefront
+      if (lane == NW - 1) block_base = x ? atomicAdd(b.pool_next, (unsigned long long)x) : 0ull;
+    }
+    __syncthreads();
     if (mine) {
       const uint32_t old_last = b.last[p];
       uint32_t first_new = 0xFFFFFFFFu;
       if (b1 > b0) {
-        const uint64_t base = wbase + incl - words;
+        const uint64_t base = block_base + wave_off[wv] + incl - words;
         if (base + words > b.pool_cap || base + words > 0xFFFFFFFFull) {
           // pool exhausted: keep what the existing buckets hold; a key left with no value leaves the table
           const uint64_t keep = bl_S(b, b0);
@@ -266,6 +284,7 @@ __global__ __launch_bounds__(256) void k_bl_alloc(TableView t, BucketView b, uin
       }
       b.batch[p] = (uint64_t)old_last | ((uint64_t)first_new << 32);
     }
+    __syncthreads();  // wave_off and block_base are rewritten by the next round
   }
 }
 
@@ -574,7 +593,10 @@ hc_err launch_bl_expand(const uint64_t* scan, const uint64_t* starts, uint64_t n
 hc_err launch_bl_finish(const TableView& t, const BucketView& b, const uint32_t* values, uint64_t n,
                         const uint64_t* pos, const uint32_t* ticket, const uint8_t* st, uint8_t* status,
                         hipStream_t s) {
-  hipLaunchKernelGGL(k_bl_alloc, dim3(stream_grid(n)), dim3(256), 0, s, t, b, n, pos, ticket, st);
+  uint64_t ga = (n + ALLOC_BLOCK - 1) / ALLOC_BLOCK;
+  const uint64_t cap = (uint64_t)device_cu_count() * 2;
+  if (ga > cap) ga = cap;
+  hipLaunchKernelGGL(k_bl_alloc, dim3((unsigned)(ga ? ga : 1)), dim3(ALLOC_BLOCK), 0, s, t, b, n, pos, ticket, st);
   if (hc_err r = check_launch("bucket list allocation"); r != HC_OK) return r;
   hipLaunchKernelGGL(k_bl_place, dim3(stream_grid(n)), dim3(256), 0, s, t, b, values, n, pos, ticket,
                      const_cast<uint8_t*>(st), status);
