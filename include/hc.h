@@ -174,12 +174,14 @@ hc_err hc_erase64(hc_table table, const uint64_t* d_keys, uint64_t n, uint8_t* d
  * key with the seed's low / high half; mask for a power-of-two B, multiply-high otherwise).
  * Every 32-bit key is valid.  No false negatives; the false-positive rate with n keys is
  * sum_j Binomial(j; n, 1/B) (1 - (31/32)^j)^block_words.  A group of g lanes (power of two,
- * g <= block_words) takes one key; group is a tuning knob and never changes results. */
+ * g <= block_words) takes one key; group is a tuning knob and never changes results.  Group 0
+ * in a call means the filter's default; a default of 0 means one lane per word for inserts (the
+ * block's atomic ORs leave as one request) and one lane per key for queries. */
 typedef struct hc_bloom_s* hc_bloom;
 
 typedef struct {
   uint32_t block_words; /* 8, 16 or 32 (bits per key) */
-  uint32_t group;       /* default group size g */
+  uint32_t group;       /* default group size g; 0: per operation (insert: block_words, query: 1) */
   uint64_t seed;
 } hc_bloom_params;
 
@@ -191,7 +193,7 @@ typedef struct {
   uint32_t* d_bits;     /* B * block_words uint32 words, block j at words [j * block_words, ...) */
 } hc_bloom_info_t;
 
-/* Defaults: 16 words (one 64-byte block, 16 bits per key), g = 4, a fixed seed. */
+/* Defaults: 16 words (one 64-byte block, 16 bits per key), group 0 (per operation), a fixed seed. */
 void hc_default_bloom_params(hc_bloom_params* params);
 /* A cleared filter of at least `bits` bits (B = ceil(bits / (32 * block_words)) blocks,
  * B <= 2^32) on the current device; params may be NULL (defaults).  The call synchronises.

@@ -739,7 +739,7 @@ def hc_bloom_dump(h: int, dst, stream=None):
 class Bloom:
     """Blocked Bloom filter handle (see ``hc_bloom_create``)."""
 
-    def __init__(self, bits, block_words=16, group=4, seed=None, device=None):
+    def __init__(self, bits, block_words=16, group=0, seed=None, device=None):
         p = hc_default_bloom_params()
         p.block_words, p.group = block_words, group
         if seed is not None:

@@ -173,8 +173,12 @@ static hc_err bloom_device(hc_bloom b) {
   return HC_OK;
 }
 
-static hc_err bloom_group(hc_bloom b, uint32_t group, uint32_t* out) {
-  const uint32_t g = group ? group : b->group;
+// Group 0 (in the call and in the filter's default): per operation, the fastest
+// measured: inserts one lane per word (the block's atomic ORs leave as one
+// request), queries one lane per key (a 64-byte block is one vector load).
+static hc_err bloom_group(hc_bloom b, uint32_t group, bool insert, uint32_t* out) {
+  uint32_t g = group ? group : b->group;
+  if (g == 0) g = insert ? b->words : 1;
   if (g == 0 || (g & (g - 1)) != 0 || g > b->words)
     return fail(HC_E_ARG, "group size %u is not a power of two in [1, %u]", g, b->words);
   *out = g;
@@ -186,7 +190,7 @@ extern "C" {
 void hc_default_bloom_params(hc_bloom_params* p) {
   if (p == nullptr) return;
   p->block_words = 16;
-  p->group = 4;
+  p->group = 0;
   p->seed = 0x9E3779B97F4A7C15ull;
 }
 
@@ -198,7 +202,7 @@ hc_err hc_bloom_create(hc_bloom* out, uint64_t bits, const hc_bloom_params* para
   if (params != nullptr) p = *params;
   if (p.block_words != 8 && p.block_words != 16 && p.block_words != 32)
     return fail(HC_E_ARG, "block words %u is not 8, 16 or 32", p.block_words);
-  if (p.group == 0 || (p.group & (p.group - 1)) != 0 || p.group > p.block_words)
+  if ((p.group & (p.group - 1)) != 0 || p.group > p.block_words)
     return fail(HC_E_ARG, "group size %u is not a power of two in [1, %u]", p.group, p.block_words);
   if (bits == 0) return fail(HC_E_ARG, "bits is 0");
   const uint64_t per = 32ull * p.block_words;
@@ -252,7 +256,7 @@ hc_err hc_bloom_insert(hc_bloom b, const uint32_t* d_keys, uint64_t n, uint32_t 
   hc_err r = bloom_device(b);
   if (r != HC_OK) return r;
   uint32_t G;
-  if ((r = bloom_group(b, group, &G)) != HC_OK) return r;
+  if ((r = bloom_group(b, group, true, &G)) != HC_OK) return r;
   if (n == 0) return HC_OK;
   if (d_keys == nullptr) return fail(HC_E_ARG, "keys is NULL");
   const BloomView v = bloom_view(b);
@@ -269,7 +273,7 @@ hc_err hc_bloom_contains(hc_bloom b, const uint32_t* d_keys, uint64_t n, uint8_t
   hc_err r = bloom_device(b);
   if (r != HC_OK) return r;
   uint32_t G;
-  if ((r = bloom_group(b, group, &G)) != HC_OK) return r;
+  if ((r = bloom_group(b, group, false, &G)) != HC_OK) return r;
   if (n == 0) return HC_OK;
   if (d_keys == nullptr || d_found_out == nullptr) return fail(HC_E_ARG, "keys or found is NULL");
   const BloomView v = bloom_view(b);

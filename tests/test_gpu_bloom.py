@@ -70,6 +70,19 @@ def test_bloom_bits_and_answers_match_oracle(hc, words, group, blocks):
     assert np.array_equal(h(f.contains(d(q), group=other)), got)
 
 
+def test_bloom_default_group_per_operation(hc):
+    # group 0: inserts one lane per word, queries one lane per key; same bits and answers as any explicit group
+    keys = gen.keys(9, 1, 200000)
+    q = np.concatenate([keys[:1000], gen.keys(9, 200001, 100000)])
+    a = hc.Bloom(1 << 22, block_words=32, seed=3)
+    assert a.group == 0
+    b = hc.Bloom(1 << 22, block_words=32, group=2, seed=3)
+    a.insert(d(keys))
+    b.insert(d(keys))
+    assert np.array_equal(h(a.dump()), h(b.dump()))
+    assert np.array_equal(h(a.contains(d(q))), h(b.contains(d(q))))
+
+
 def test_bloom_clear_and_empty(hc):
     f = hc.Bloom(1 << 20, block_words=16, group=4)
     keys = gen.keys(3, 1, 50000)
@@ -86,7 +99,7 @@ def test_bloom_full_size_sampled_blocks_and_closed_form(hc):
     # 2^32 bits (2^23 blocks of 16 words), 2^28 keys: the oracle rebuilds 4096 sampled blocks
     # from exactly the keys that map to them, and answers the queries that fall into them
     words, log2_bits, log2_n = 16, 32, 28
-    f = hc.Bloom(1 << log2_bits, block_words=words, group=4, seed=0x5EED)
+    f = hc.Bloom(1 << log2_bits, block_words=words, seed=0x5EED)  # per-operation default groups
     n = 1 << log2_n
     keys = gen.keys(41, 1, n)
     f.insert(d(keys))
