@@ -11,7 +11,8 @@
 //
 // Cooperation follows the tables' groups (Sec. IV-B2): a group of G lanes takes
 // one key, lane r owning the block's words [r * words/G, (r+1) * words/G).
-// Insert: each lane ORs its words' bits in with atomic ORs (no return value).
+// Insert: each lane ORs its words' bits in with atomic ORs (no return value; word
+// pairs as one 64-bit OR).
 // Query: each lane loads its words (vector loads) and checks its bits; the key
 // is reported present iff every lane's bits are all set (a group ballot).
 #include <new>
@@ -54,8 +55,13 @@ __global__ __launch_bounds__(BLOCK) void k_bloom_insert(BloomView f, const uint3
     uint32_t m[WPL];
     key.masks<WPL>(r * WPL, m);
     uint32_t* blk = f.bits + key.block * WORDS + r * WPL;
+    if constexpr (WPL % 2 == 0) {  // word pairs as 64-bit atomic ORs: half the atomic lanes per key
 #pragma unroll
-    for (int j = 0; j < WPL; ++j) atomicOr(blk + j, m[j]);
+      for (int j = 0; j < WPL; j += 2)
+        atomicOr(reinterpret_cast<unsigned long long*>(blk + j), (unsigned long long)m[j] | ((unsigned long long)m[j + 1] << 32));
+    } else {
+      atomicOr(blk, m[0]);
+    }
   }
 }
 
