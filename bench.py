@@ -237,6 +237,7 @@ def main():
     out["ceilings"] = _ceilings(hc, table, dev, stream)
     out["ceilings"]["retrieve_frac_of_gather128"] = round(ret_gbs / out["ceilings"]["gather128_gbs"], 4)
     out["ceilings"]["insert_frac_of_gather128"] = round(ins_gbs / out["ceilings"]["gather128_gbs"], 4)
+    out["ceilings"]["insert_frac_of_atomic_cas"] = round(ins_gops / out["ceilings"]["atomic_cas_gops"], 4)
     if args.calibrate_copy_mib:
         a = torch.empty(args.calibrate_copy_mib << 20, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)
@@ -281,6 +282,12 @@ def _ceilings(hc, table, dev, s):
         n_lines = nbytes // lb
         ms = timed(lambda: hc.hc_diag_gather(info.d_slots, nbytes, lb, n_lines, sink, 0x5EED, s))
         res[f"gather{lb}_gbs"] = round(n_lines * lb / ms / 1e6, 1)
+    # random atomics over a scratch region of the table's size: claims (CAS with return) and ORs
+    region = torch.zeros(nbytes // 8, dtype=torch.int64, device=dev)
+    n_ops = nbytes // 16
+    res["atomic_cas_gops"] = round(n_ops / timed(lambda: hc.hc_diag_atomic(region, True, n_ops, sink, 7, s)) / 1e6, 2)
+    res["atomic_or_gops"] = round(n_ops / timed(lambda: hc.hc_diag_atomic(region, False, n_ops, sink, 9, s)) / 1e6, 2)
+    del region
     return res
 
 

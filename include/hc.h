@@ -218,10 +218,15 @@ hc_err hc_bloom_dump(hc_bloom filter, uint32_t* d_dst, void* stream);
  * peaks.  hc_diag_gather: read n_lines lines of line_bytes
  * (32, 64 or 128) at pseudo-random line indices of the region [d_base, d_base + bytes) (d_base
  * aligned to line_bytes, at most 2^32 lines): the random-access ceiling a probe of a large table
- * pays.  d_sink is one device word the kernel may write.  Both are asynchronous on the stream.
+ * pays.  hc_diag_atomic: n_ops atomics on pseudo-random 8-byte words of the region (8-byte aligned,
+ * at most 2^32 words), one per lane: cas = 0 an OR without return (the region's bits change), cas
+ * != 0 a CAS of 0 with return (zero words change): the rate of Bloom inserts and table claims.
+ * d_sink is one device word the kernel may write.  All are asynchronous on the stream.
  * Errors: HC_E_ARG for NULL pointers, sizes or alignment as stated. */
 hc_err hc_diag_copy(void* d_dst, const void* d_src, uint64_t bytes, void* stream);
 hc_err hc_diag_read(const void* d_src, uint64_t bytes, uint32_t* d_sink, void* stream);
+hc_err hc_diag_atomic(void* d_base, uint64_t bytes, uint32_t cas, uint64_t n_ops, uint32_t seed, uint32_t* d_sink,
+                      void* stream);
 hc_err hc_diag_gather(const void* d_base, uint64_t bytes, uint32_t line_bytes, uint64_t n_lines, uint32_t seed,
                       uint32_t* d_sink, void* stream);
 

@@ -116,6 +116,7 @@ _SIGS = {
     "hc_erase64": ([_p, _p, _u64, _p, _u32, _p], ctypes.c_int),
     "hc_diag_copy": ([_p, _p, _u64, _p], ctypes.c_int),
     "hc_diag_read": ([_p, _u64, _p, _p], ctypes.c_int),
+    "hc_diag_atomic": ([_p, _u64, _u32, _u64, _u32, _p, _p], ctypes.c_int),
     "hc_diag_gather": ([_p, _u64, _u32, _u64, _u32, _p, _p], ctypes.c_int),
     "hc_default_bloom_params": ([ctypes.POINTER(HcBloomParams)], None),
     "hc_bloom_create": ([ctypes.POINTER(_p), _u64, ctypes.POINTER(HcBloomParams)], ctypes.c_int),
@@ -794,6 +795,12 @@ def hc_diag_read(src, sink, stream=None):
     """Read all of src (a multiple of 16 bytes) with the library's streaming kernel."""
     _check(_lib.hc_diag_read(src.data_ptr(), src.numel() * src.element_size(), _dptr(sink, torch.uint32, "sink", 1),
                              _stream(stream)), "hc_diag_read")
+
+
+def hc_diag_atomic(region, cas: bool, n_ops: int, sink, seed: int = 1, stream=None):
+    """n_ops random 8-byte atomics (OR, or CAS of 0) inside the device tensor ``region``."""
+    _check(_lib.hc_diag_atomic(region.data_ptr(), region.numel() * region.element_size(), int(cas), n_ops, seed,
+                               _dptr(sink, torch.uint32, "sink", 1), _stream(stream)), "hc_diag_atomic")
 
 
 def hc_diag_gather(base_ptr: int, nbytes: int, line_bytes: int, n_lines: int, sink, seed: int = 1, stream=None):

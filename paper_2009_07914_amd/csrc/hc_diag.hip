@@ -1,7 +1,7 @@
 // Bandwidth diagnostics for the measurement: a streaming copy and a streaming
-// read (the practical HBM peaks) and a gather of random lines (the
-// random-access ceiling that every probe of a table larger than the caches
-// pays).  Not part of the tables.
+// read (the practical HBM peaks), a gather of random lines (the random-access
+// ceiling that every probe of a table larger than the caches pays) and random
+// atomics (the rate of claims and Bloom ORs).  Not part of the tables.
 #include "hc_device.hpp"
 #include "hc_launch.hpp"
 
@@ -56,6 +56,26 @@ __global__ __launch_bounds__(BLOCK) void k_diag_gather(const uint4* __restrict__
   if (acc == 0x9E3779B9u) sink[0] = acc;  // keeps the loads; practically never stores
 }
 
+// One atomic per lane on a pseudo-random 8-byte word of [base, base + words):
+// an OR without return (as a Bloom insert) or a CAS with return (as a table
+// claim).  The words are random, so nearly every atomic hits its own line.
+template <bool CAS>
+__global__ __launch_bounds__(BLOCK) void k_diag_atomic(unsigned long long* __restrict__ base, uint64_t words,
+                                                       uint64_t n, uint32_t seed, uint32_t* __restrict__ sink) {
+  const uint64_t stride = (uint64_t)gridDim.x * BLOCK;
+  uint32_t acc = 0;
+  for (uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; i < n; i += stride) {
+    const uint32_t h = fmix32((uint32_t)i ^ fmix32(seed + (uint32_t)(i >> 32)));
+    unsigned long long* p = base + (((uint64_t)h * words) >> 32);
+    if constexpr (CAS) {
+      acc ^= (uint32_t)atomicCAS(p, 0ull, (unsigned long long)(i | 1));
+    } else {
+      atomicOr(p, 1ull << (h & 63));
+    }
+  }
+  if (acc == 0x9E3779B9u) sink[0] = acc;
+}
+
 }  // namespace hc
 
 using namespace hc;
@@ -82,6 +102,24 @@ hc_err hc_diag_read(const void* d_src, uint64_t bytes, uint32_t* d_sink, void* s
   hipLaunchKernelGGL(k_diag_read, dim3(grid), dim3(BLOCK), 0, (hipStream_t)stream, static_cast<const uint4*>(d_src), n,
                      d_sink);
   return check_launch("diagnostic read");
+}
+
+hc_err hc_diag_atomic(void* d_base, uint64_t bytes, uint32_t cas, uint64_t n_ops, uint32_t seed, uint32_t* d_sink,
+                      void* stream) {
+  if (d_base == nullptr || d_sink == nullptr) return fail(HC_E_ARG, "base or sink is NULL");
+  if ((reinterpret_cast<uintptr_t>(d_base) & 7) != 0) return fail(HC_E_ARG, "base is not 8-byte aligned");
+  const uint64_t words = bytes / 8;
+  if (words == 0 || words > (1ull << 32)) return fail(HC_E_ARG, "region holds %llu words", (unsigned long long)words);
+  if (n_ops == 0) return HC_OK;
+  auto* base = static_cast<unsigned long long*>(d_base);
+  if (cas) {
+    hipLaunchKernelGGL(k_diag_atomic<true>, dim3(grid_for(k_diag_atomic<true>, n_ops, 1)), dim3(BLOCK), 0,
+                       (hipStream_t)stream, base, words, n_ops, seed, d_sink);
+  } else {
+    hipLaunchKernelGGL(k_diag_atomic<false>, dim3(grid_for(k_diag_atomic<false>, n_ops, 1)), dim3(BLOCK), 0,
+                       (hipStream_t)stream, base, words, n_ops, seed, d_sink);
+  }
+  return check_launch("diagnostic atomics");
 }
 
 hc_err hc_diag_gather(const void* d_base, uint64_t bytes, uint32_t line_bytes, uint64_t n_lines, uint32_t seed,

@@ -37,3 +37,20 @@ def test_diag_gather_runs_in_bounds(hc, line_bytes):
     with pytest.raises(hc.HcError) as e:
         hc.hc_diag_gather(region.data_ptr() + 4, region.numel() - 128, line_bytes, 16, sink)
     assert e.value.code == hc.E_ARG
+
+
+def test_diag_atomics_stay_in_region(hc):
+    region = torch.zeros(1 << 16, dtype=torch.int64, device="cuda")
+    sink = torch.zeros(1, dtype=torch.uint32, device="cuda")
+    hc.hc_diag_atomic(region, True, 1 << 15, sink, 3)  # CAS of 0 into zero words: every word changes at most once
+    torch.cuda.synchronize()
+    changed = int((region != 0).sum().item())
+    assert 0 < changed <= 1 << 15
+    region.zero_()
+    hc.hc_diag_atomic(region, False, 1 << 15, sink, 5)  # ORs: at most one bit per op
+    torch.cuda.synchronize()
+    bits = int(np.unpackbits(region.cpu().numpy().view(np.uint8)).sum())
+    assert 0 < bits <= 1 << 15
+    with pytest.raises(hc.HcError) as e:
+        hc.hc_diag_atomic(region[:0], True, 16, sink)
+    assert e.value.code == hc.E_ARG
