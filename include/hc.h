@@ -131,8 +131,8 @@ hc_err hc_create_in(hc_table* out, uint32_t kind, void* d_slots, uint64_t slot_b
 /* ---- single-value tables with 64-bit keys and values (Sec. IV-B1 wider types) ------
  * Kind HC_SINGLE_VALUE_64 (hc_create): slots of 16 bytes (key word, then value word), so a
  * window of W = 8 slots is one 128-byte line; group sizes g <= W.  Keys 0 and 2^64-1 are
- * reserved.  A claim is a 64-bit CAS of the key word followed by an atomic exchange of the
- * value word; a present key's value is replaced by an exchange (status DUPLICATE).  Results,
+ * reserved.  A claim is a 64-bit CAS of the key word followed by a relaxed atomic store of the
+ * value word; a present key's value is replaced by such a store (status DUPLICATE).  Results,
  * statuses and errors as hc_insert / hc_retrieve / hc_erase with uint64 keys and values.
  * hc_size, hc_load_factor, hc_capacity, hc_info, hc_clear, hc_destroy apply; hc_dump_slots
  * copies 2*C uint64 words; hc_create_in needs 16 bytes per slot (hc_table_bytes counts 8).

@@ -11,8 +11,8 @@
 // of G <= W lanes loads a whole window (W/G slots per lane, 16-byte loads),
 // votes with a ballot and claims the first reusable slot once the window shows
 // the key absent up to an empty slot.  A claim is a 64-bit CAS of the key word
-// only; the value word is then written (AoS: atomic exchange; SoA: a relaxed
-// atomic store), so a reader in a later launch sees a whole pair.  Within one
+// only; the value word is then written with a relaxed atomic store, so a
+// reader in a later launch sees a whole pair.  Within one
 // launch a reader may find a freshly claimed key before its value store lands
 // (the torn-read hazard of a key-only CAS): inserts and queries of one table
 // belong in different launches, as for every table here.  An update of a
@@ -57,14 +57,11 @@ template <bool SOA, int W>
 __device__ __forceinline__ unsigned long long* value_word(const TableView& t, uint64_t idx) {
   return (unsigned long long*)(SOA ? t.slots + (uint64_t)t.P * W + idx : t.slots + 2 * idx + 1);
 }
+// The value word after a claim or for an update: a relaxed atomic store (a
+// whole 8-byte word, no return: not a second read-modify-write of the line).
 template <bool SOA, int W>
 __device__ __forceinline__ void store_value(const TableView& t, uint64_t idx, uint64_t v) {
-  if constexpr (SOA) {
-    __hip_atomic_store(value_word<true, W>(t, idx), (unsigned long long)v, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-  } else {
-    atomicExch(value_word<false, W>(t, idx), (unsigned long long)v);
-  }
+  __hip_atomic_store(value_word<SOA, W>(t, idx), (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // One group's view of a window: SPL slots per lane, keys (and values, AoS).
