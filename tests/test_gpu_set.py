@@ -123,3 +123,19 @@ def test_set_rejects_table_calls(hc):
     with pytest.raises(hc.HcError) as e:
         hc.Table("set", 1024, window=8, group=16)
     assert e.value.code == hc.E_ARG
+
+
+def test_set_empty_batches_and_info(hc):
+    t = hc.Table("set", 4096, scheme="quadratic", window=32, group=8)
+    info = hc.hc_info(t.handle)
+    assert info.kind == hc.HASH_SET and info.capacity == t.capacity and t.capacity % 32 == 0
+    empty = d(np.zeros(0, np.uint32))
+    assert h(t.insert(empty, status=True)).size == 0
+    assert h(t.retrieve(empty)[1]).size == 0
+    assert h(t.erase(empty, status=True)).size == 0
+    assert t.size() == 0
+    # a ragged batch (not a multiple of any tile) into a fresh set
+    keys = gen.keys(77, 1, 1001)
+    orc = oracle.OracleTable(oracle.SINGLE, t.capacity)
+    assert np.array_equal(h(t.insert(d(keys), status=True)), orc.insert(keys, _zeros(keys.size)))
+    _layout(t)

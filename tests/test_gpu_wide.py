@@ -110,3 +110,19 @@ def test_wide_soa_layout_is_keys_then_values(hc):
     got = dict(zip(ks[live].tolist(), vs[live].tolist()))
     assert got == dict(zip(keys.tolist(), vals.tolist()))
     assert np.all(vs[~live] == 0)
+
+
+@pytest.mark.parametrize("kind", ["single64", "single64_soa"])
+def test_wide_empty_and_ragged(hc, kind):
+    t = hc.Table(kind, 1000, scheme="double", window=8, group=2)  # P not a power of two: rounded up to a prime
+    empty = d(np.zeros(0, np.uint64))
+    assert h(t.insert(empty, empty, status=True)).size == 0
+    assert h(t.retrieve(empty)[1]).size == 0
+    assert t.size() == 0
+    keys, vals = _keys64(61, 1, 777), _vals64(62, 777)
+    orc = oracle.OracleTable64(t.capacity)
+    assert np.array_equal(h(t.insert(d(keys), d(vals), status=True)), orc.insert(keys, vals))
+    v, f = t.retrieve(d(keys))
+    vo, fo = orc.retrieve(keys)
+    assert np.array_equal(h(v), vo) and np.array_equal(h(f), fo)
+    _layout(t)
