@@ -15,7 +15,9 @@
 //      else adding 1 to the count with one 64-bit atomic): the count before the
 //      add is the pair's ticket, its rank among all values of the key.  The first
 //      ticket of each key in the batch is recorded with an atomic minimum on a
-//      per-slot stamp tagged with the batch number;
+//      per-slot stamp tagged with the batch number (a 16-byte per-slot record
+//      holds the stamp and the batch's bucket offsets, so phases 2 and 3 find
+//      both in one line);
 //   2. the pair holding that first ticket takes the buckets the key's new tickets
 //      need from the pool in one allocation (one pool atomic per wavefront),
 //      links them (previous-bucket offsets) and moves `last`; if the pool is
@@ -101,7 +103,7 @@ struct BlTicket {
     pos[i] = idx;
     ticket[i] = tk;
     st[i] = ST_OK;
-    atomicMin(b.stamp + idx, ((unsigned long long)(~b.epoch) << 32) | tk);  // older batches compare larger
+    atomicMin(&b.meta[idx].x, ((unsigned long long)(~b.epoch) << 32) | tk);  // older batches compare larger
   }
   __device__ __forceinline__ void add_one(uint64_t idx) {  // `inc` more values (tickets old .. old + inc - 1)
     const uint64_t old = atomicAdd((unsigned long long*)&t.slots[idx], (unsigned long long)inc << 32);
@@ -231,7 +233,7 @@ __global__ __launch_bounds__(ALLOC_BLOCK) void k_bl_alloc(TableView t, BucketVie
     bool mine = false;
     if (i < n && st[i] == ST_OK) {
       p = pos[i];
-      const uint64_t c0 = (uint32_t)b.stamp[p];  // first ticket of this batch = count before it
+      const uint64_t c0 = (uint32_t)b.meta[p].x;  // first ticket of this batch = count before it
       mine = ticket[i] == c0;
       if (mine) {
         word = t.slots[p];
@@ -282,7 +284,7 @@ __global__ __launch_bounds__(ALLOC_BLOCK) void k_bl_alloc(TableView t, BucketVie
           first_new = (uint32_t)base;
         }
       }
-      b.batch[p] = (uint64_t)old_last | ((uint64_t)first_new << 32);
+      b.meta[p].y = (uint64_t)old_last | ((uint64_t)first_new << 32);
     }
     __syncthreads();  // wave_off and block_base are rewritten by the next round
   }
@@ -304,9 +306,10 @@ __global__ __launch_bounds__(256) void k_bl_place(TableView t, BucketView b, con
       if (tk >= c) {
         code = ST_FULL;
       } else {
-        const uint64_t c0 = (uint32_t)b.stamp[p];
+        const ulonglong2 mt = b.meta[p];
+        const uint64_t c0 = (uint32_t)mt.x;
         const uint64_t b0 = bl_buckets(b, c0), bi = bl_bucket_of(b, tk);
-        const uint64_t bat = b.batch[p];
+        const uint64_t bat = mt.y;
         const uint64_t o = (bi < b0) ? (uint32_t)bat : (bat >> 32) + bl_words(b, b0, bi);
         b.pool[o + (bi >= 1 ? 1 : 0) + (tk - bl_S(b, bi))] = values[i];
         ++stored;
@@ -525,9 +528,9 @@ __global__ __launch_bounds__(64) void k_bl_zero1(unsigned long long* p) {
   if (threadIdx.x == 0) *p = 0ull;
 }
 
-__global__ __launch_bounds__(256) void k_bl_reset(unsigned long long* stamp, uint64_t C) {
+__global__ __launch_bounds__(256) void k_bl_reset(ulonglong2* meta, uint64_t C) {
   const uint64_t stride = (uint64_t)gridDim.x * 256;
-  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < C; i += stride) stamp[i] = ~0ull;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < C; i += stride) meta[i] = make_ulonglong2(~0ull, 0ull);
 }
 
 // ---- host side ----------------------------------------------------------------------------
@@ -653,7 +656,7 @@ hc_err launch_bl_erase(const TableView& t, uint32_t G, uint32_t W, const uint32_
 }
 
 hc_err launch_bl_reset(const BucketView& b, uint64_t C, hipStream_t s) {
-  hipLaunchKernelGGL(k_bl_reset, dim3(stream_grid(C)), dim3(256), 0, s, b.stamp, C);
+  hipLaunchKernelGGL(k_bl_reset, dim3(stream_grid(C)), dim3(256), 0, s, b.meta, C);
   return check_launch("bucket list reset");
 }
 

@@ -23,8 +23,11 @@ struct BucketView {
   uint64_t pool_cap;               // words
   unsigned long long* pool_next;   // first free word
   uint32_t* last;                  // per key slot: pool offset of the key's last bucket
-  unsigned long long* stamp;       // per key slot: (~batch << 32) | first ticket of the key in that batch
-  uint64_t* batch;                 // per key slot: old last bucket (low 32) | first new bucket (high 32)
+  // per key slot, one 16-byte record (the allocation reads the first word and writes the second,
+  // placement reads both: one line each):
+  //   stamp = (~batch << 32) | first ticket of the key in that batch
+  //   batch = old last bucket (low 32) | first new bucket (high 32)
+  ulonglong2* meta;
   uint32_t epoch;                  // batch number (1 ..)
 };
 
@@ -61,7 +64,7 @@ hc_err launch_bl_write(const TableView& t, const BucketView& b, uint32_t G, uint
                        uint64_t n, const uint64_t* offsets, uint32_t* out, void* ws, hipStream_t s);
 hc_err launch_bl_erase(const TableView& t, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n, uint8_t* status,
                        hipStream_t s);
-// stamp[0..C) = ~0 (a fill kernel).
+// stamp of every slot = ~0 (a fill kernel).
 hc_err launch_bl_reset(const BucketView& b, uint64_t C, hipStream_t s);
 
 }  // namespace hc

@@ -50,8 +50,7 @@ struct hc_table_s {
   uint32_t* d_pool = nullptr;
   uint64_t pool_cap = 0;
   uint32_t* d_last = nullptr;
-  unsigned long long* d_stamp = nullptr;
-  uint64_t* d_batch = nullptr;
+  ulonglong2* d_meta = nullptr;  // per slot: batch stamp, batch bucket offsets
   uint32_t epoch = 0;
 };
 
@@ -203,8 +202,7 @@ static BucketView bview_of(const hc_table_s* t) {
   b.pool_cap = t->pool_cap;
   b.pool_next = t->d_size + 1;  // the size counter and the pool counter share one allocation
   b.last = t->d_last;
-  b.stamp = t->d_stamp;
-  b.batch = t->d_batch;
+  b.meta = t->d_meta;
   b.epoch = t->epoch;
   return b;
 }
@@ -571,8 +569,7 @@ hc_err hc_create_bucket_list(hc_table* out, uint64_t key_capacity, const hc_para
   hipError_t e = hipMalloc((void**)&t->d_cum, (m + 1) * sizeof(uint64_t));
   if (e == hipSuccess) e = hipMalloc((void**)&t->d_pool, pool * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMalloc((void**)&t->d_last, t->C * sizeof(uint32_t));
-  if (e == hipSuccess) e = hipMalloc((void**)&t->d_stamp, t->C * sizeof(unsigned long long));
-  if (e == hipSuccess) e = hipMalloc((void**)&t->d_batch, t->C * sizeof(uint64_t));
+  if (e == hipSuccess) e = hipMalloc((void**)&t->d_meta, t->C * sizeof(ulonglong2));
   if (e != hipSuccess) {
     (void)hipGetLastError();
     hc_destroy(t);
@@ -651,7 +648,7 @@ hc_err hc_destroy(hc_table t) {
   if (t->d_size) (void)hipFree(t->d_size);
   if (t->d_tiles) (void)hipFree(t->d_tiles);
   if (t->d_ws) (void)hipFree(t->d_ws);
-  for (void* q : {(void*)t->d_cum, (void*)t->d_pool, (void*)t->d_last, (void*)t->d_stamp, (void*)t->d_batch})
+  for (void* q : {(void*)t->d_cum, (void*)t->d_pool, (void*)t->d_last, (void*)t->d_meta})
     if (q) (void)hipFree(q);
   delete t;
   if (e != hipSuccess) return hip_fail(e, "hc_destroy: synchronise");
@@ -670,7 +667,7 @@ hc_err hc_clear(hc_table t, void* stream) {
   hipLaunchKernelGGL(k_fill_empty, dim3((unsigned)blocks), dim3(BLOCK), 0, (hipStream_t)stream,
                      reinterpret_cast<ulonglong2*>(t->slots), pairs, t->d_size);
   if ((r = check_launch("clear")) != HC_OK) return r;
-  if (t->kind == HC_BUCKET_LIST && t->d_stamp != nullptr) {  // empty pool, fresh batch stamps (once allocated)
+  if (t->kind == HC_BUCKET_LIST && t->d_meta != nullptr) {  // empty pool, fresh batch stamps (once allocated)
     if ((r = launch_zero_u64(t->d_size + 1, 1, (hipStream_t)stream)) != HC_OK) return r;
     if ((r = launch_bl_reset(bview_of(t), t->C, (hipStream_t)stream)) != HC_OK) return r;
     t->epoch = 0;
