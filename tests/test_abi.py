@@ -114,3 +114,38 @@ def test_bucket_list_arguments(lib):
                              (1, 1 << 20, 1.0)]:  # the last never reaches smax: ramp too long
         bad = _BucketParams(0, s0, smax, growth)
         assert lib.hc_create_bucket_list(ctypes.byref(h), 1024, None, ctypes.byref(bad)) == 1, (s0, smax, growth)
+
+
+class _BloomParams(ctypes.Structure):
+    _fields_ = [("block_words", ctypes.c_uint32), ("group", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+
+
+def test_bloom_and_diagnostic_arguments(lib):
+    # every check below happens before any device call
+    lib.hc_bloom_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint64, ctypes.POINTER(_BloomParams)]
+    lib.hc_default_bloom_params.argtypes = [ctypes.POINTER(_BloomParams)]
+    lib.hc_bloom_info.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    lib.hc_diag_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
+    lib.hc_diag_gather.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32,
+                                   ctypes.c_void_p, ctypes.c_void_p]
+    lib.hc_diag_atomic.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32,
+                                   ctypes.c_void_p, ctypes.c_void_p]
+    p = _BloomParams()
+    lib.hc_default_bloom_params(ctypes.byref(p))
+    assert (p.block_words, p.group) == (16, 0)
+    h = ctypes.c_void_p()
+    for words, group in [(12, 0), (16, 3), (8, 16), (64, 0)]:
+        bad = _BloomParams(words, group, 1)
+        assert lib.hc_bloom_create(ctypes.byref(h), 1 << 20, ctypes.byref(bad)) == 1, (words, group)
+    assert lib.hc_bloom_create(ctypes.byref(h), 0, ctypes.byref(p)) == 1          # no bits
+    assert lib.hc_bloom_create(ctypes.byref(h), 1 << 50, ctypes.byref(p)) == 1    # more than 2^32 blocks
+    assert lib.hc_bloom_create(None, 1 << 20, ctypes.byref(p)) == 1
+    assert h.value is None
+    assert lib.hc_bloom_info(None, None) == 1
+    fake, sink = 0x100000, 0x200000  # never dereferenced: the checks fail first
+    assert lib.hc_diag_copy(None, fake, 64, None) == 1
+    assert lib.hc_diag_copy(fake, fake, 17, None) == 1
+    assert lib.hc_diag_gather(fake, 1 << 20, 48, 16, 1, sink, None) == 1           # line size
+    assert lib.hc_diag_gather(fake + 4, 1 << 20, 64, 16, 1, sink, None) == 1       # alignment
+    assert lib.hc_diag_atomic(fake + 4, 1 << 20, 1, 16, 1, sink, None) == 1        # alignment
+    assert lib.hc_diag_atomic(fake, 4, 0, 16, 1, sink, None) == 1                  # no whole word
