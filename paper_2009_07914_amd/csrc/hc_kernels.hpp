@@ -236,16 +236,16 @@ __device__ __forceinline__ void drive_range(uint64_t begin, uint64_t end, Op& op
 // as they are; a result that arrives after its entry was written back (seq below
 // the flush mark) goes straight to memory.
 // ------------------------------------------------------------------------------
-template <int RB>
+template <int RB, typename V = uint32_t>
 struct OutRing {
   uint64_t idx[RB];   // element index of each entry
-  uint32_t val[RB];
+  V val[RB];
   uint8_t found[RB];
   uint8_t done[RB];   // 0 pending, 1 finished, 2 no element
 };
 
-template <int G, int RB, typename Op>
-__device__ __forceinline__ void drive_staged(uint64_t n, const WorkCtl& ctl, Op& op, OutRing<RB>& ring) {
+template <int G, int RB, typename Op, typename V>
+__device__ __forceinline__ void drive_staged(uint64_t n, const WorkCtl& ctl, Op& op, OutRing<RB, V>& ring) {
   static_assert(RB % 64 == 0 && RB >= 128, "ring of whole 64-entry blocks, at least two");
   const GroupCtx<G>& g = op.ln.g;
   const uint32_t chunk = ctl.chunk;

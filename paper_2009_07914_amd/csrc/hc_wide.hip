@@ -214,6 +214,12 @@ struct WideRetrieve {
   uint64_t* __restrict__ values_out;
   uint8_t* __restrict__ found_out;
   uint64_t i = 0, k = 0, k_nx = 0;
+  // output staging (drive_staged), as for the 32-bit retrieve
+  uint64_t* ring_val = nullptr;
+  uint8_t* ring_found = nullptr;
+  uint8_t* ring_done = nullptr;
+  uint64_t seq = 0, flushed = 0;
+  static constexpr uint32_t RING = 128;
 
   __device__ __forceinline__ void load(uint64_t op) { k_nx = keys[op]; }
   __device__ __forceinline__ void begin(uint64_t op) {
@@ -221,21 +227,31 @@ struct WideRetrieve {
     k = k_nx;
     ln.start(t, k);
   }
-  __device__ __forceinline__ bool out(uint64_t v, uint8_t f) {
-    if (values_out != nullptr) values_out[i] = v;
-    if (found_out != nullptr) found_out[i] = f;
+  __device__ __forceinline__ void emit(uint64_t v, uint8_t f) {
+    if (ring_val != nullptr && seq >= flushed) {
+      const uint32_t r = (uint32_t)(seq % RING);
+      ring_val[r] = v;
+      ring_found[r] = f;
+      ring_done[r] = 1;
+    } else {
+      if (values_out != nullptr) values_out[i] = v;
+      if (found_out != nullptr) found_out[i] = f;
+    }
+  }
+  __device__ __forceinline__ bool miss() {
+    if (ln.g.glane == 0) emit(0, 0);
     return true;
   }
   __device__ __forceinline__ bool step() {
     const auto& g = ln.g;
-    if (reserved64(k)) return g.glane == 0 ? out(0, 0) : true;
+    if (reserved64(k)) return miss();
     ln.load(t, k);
     const uint64_t b_match = g.bits(ln.match != 0);
     if (b_match) {
-      if (g.glane == (uint32_t)ffs64(b_match)) out(ln.matched_value(t), 1);
+      if (g.glane == (uint32_t)ffs64(b_match)) emit(ln.matched_value(t), 1);
       return true;
     }
-    if (g.bits(ln.empty != 0) || ln.exhausted(t)) return g.glane == 0 ? out(0, 0) : true;
+    if (g.bits(ln.empty != 0) || ln.exhausted(t)) return miss();
     ln.advance(t);
     return false;
   }
@@ -302,12 +318,14 @@ template <int G, int W, bool SOA>
 __global__ __launch_bounds__(BLOCK) void k_wide_retrieve(TableView t, WorkCtl ctl, const uint64_t* __restrict__ keys,
                                                          uint64_t n, uint64_t* __restrict__ values_out,
                                                          uint8_t* __restrict__ found_out) {
-  WideRetrieve<G, W, SOA> op;
+  using R = WideRetrieve<G, W, SOA>;
+  __shared__ OutRing<R::RING, uint64_t> rings[BLOCK / 64];
+  R op;
   op.t = t;
   op.keys = keys;
   op.values_out = values_out;
   op.found_out = found_out;
-  drive<G>(n, ctl, op);
+  drive_staged<G, R::RING>(n, ctl, op, rings[threadIdx.x >> 6]);
 }
 
 template <int G, int W, bool SOA>
