@@ -261,11 +261,7 @@ __device__ __forceinline__ void drive_staged(uint64_t n, const WorkCtl& ctl, Op&
     const bool handed = e < hcount;
     const uint8_t st = handed ? ring.done[r] : (uint8_t)0;
     if (only_full && (flushed + 64 > hcount || __ballot(st != 0) != ~0ull)) return false;
-    if (st == 1) {
-      const uint64_t i = ring.idx[r];
-      if (op.values_out != nullptr) op.values_out[i] = ring.val[r];
-      if (op.found_out != nullptr) op.found_out[i] = ring.found[r];
-    }
+    if (st == 1) op.write_out(ring.idx[r], ring.val[r], ring.found[r]);
     if (handed) ring.done[r] = 0;
     flushed += 64;
     op.flushed = flushed;
@@ -549,6 +545,10 @@ struct Retrieve {
     k = k_nx;
     ln.start(t, k, s, lbase);
   }
+  __device__ __forceinline__ void write_out(uint64_t e, uint32_t v, uint8_t f) {
+    if (values_out != nullptr) values_out[e] = v;
+    if (found_out != nullptr) found_out[e] = f;
+  }
   __device__ __forceinline__ void emit(uint32_t v, uint8_t f) {
     if (ring_val != nullptr && seq >= flushed) {
       const uint32_t r = (uint32_t)(seq % RING);
@@ -556,8 +556,7 @@ struct Retrieve {
       ring_found[r] = f;
       ring_done[r] = 1;
     } else {
-      if (values_out != nullptr) values_out[i] = v;
-      if (found_out != nullptr) found_out[i] = f;
+      write_out(i, v, f);
     }
   }
   __device__ __forceinline__ bool miss() {
@@ -698,6 +697,13 @@ struct CountMulti {
   uint64_t i = 0;
   uint32_t k = 0, lbase = 0, cnt = 0, k_nx = 0;
   Seq s{};
+  // output staging (drive_staged): the count goes through the ring; a query handed over to the
+  // long rounds writes its partial count directly (its ring entry stays pending and is skipped)
+  uint32_t* ring_val = nullptr;
+  uint8_t* ring_found = nullptr;
+  uint8_t* ring_done = nullptr;
+  uint64_t seq = 0, flushed = 0;
+  static constexpr uint32_t RING = 128;
 
   __device__ __forceinline__ void load(uint64_t op) { k_nx = keys[op]; }
   __device__ __forceinline__ void begin(uint64_t op) {
@@ -706,11 +712,21 @@ struct CountMulti {
     ln.start(t, k, s, lbase);
     cnt = 0;
   }
+  __device__ __forceinline__ void write_out(uint64_t e, uint32_t c, uint8_t) {
+    if (counts != nullptr) counts[e] = c;
+    if (offsets != nullptr) offsets[e] = c;
+    if (found_out != nullptr) found_out[e] = c != 0;
+  }
   __device__ __forceinline__ bool done() {
     if (ln.g.glane == 0) {
-      if (counts != nullptr) counts[i] = cnt;
-      if (offsets != nullptr) offsets[i] = cnt;
-      if (found_out != nullptr) found_out[i] = cnt != 0;
+      if (ring_val != nullptr && seq >= flushed) {
+        const uint32_t r = (uint32_t)(seq % RING);
+        ring_val[r] = cnt;
+        ring_found[r] = 0;
+        ring_done[r] = 1;
+      } else {
+        write_out(i, cnt, 0);
+      }
     }
     return true;
   }
@@ -739,7 +755,9 @@ __global__ __launch_bounds__(BLOCK) void k_count_multi(TableView t, WorkCtl ctl,
                                                        uint32_t* __restrict__ counts, uint64_t* __restrict__ offsets,
                                                        uint8_t* __restrict__ found_out, uint32_t budget,
                                                        uint64_t* __restrict__ long_list, unsigned long long* long_n) {
-  CountMulti<G, W> op;
+  using C = CountMulti<G, W>;
+  __shared__ OutRing<C::RING> rings[BLOCK / 64];
+  C op;
   op.t = t;
   op.keys = keys;
   op.counts = counts;
@@ -748,7 +766,7 @@ __global__ __launch_bounds__(BLOCK) void k_count_multi(TableView t, WorkCtl ctl,
   op.budget = budget;
   op.long_list = long_list;
   op.long_n = long_n;
-  drive<G>(n, ctl, op);
+  drive_staged<G, C::RING>(n, ctl, op, rings[threadIdx.x >> 6]);
 }
 
 // ------------------------------------------------------------------------------

@@ -227,6 +227,10 @@ struct WideRetrieve {
     k = k_nx;
     ln.start(t, k);
   }
+  __device__ __forceinline__ void write_out(uint64_t e, uint64_t v, uint8_t f) {
+    if (values_out != nullptr) values_out[e] = v;
+    if (found_out != nullptr) found_out[e] = f;
+  }
   __device__ __forceinline__ void emit(uint64_t v, uint8_t f) {
     if (ring_val != nullptr && seq >= flushed) {
       const uint32_t r = (uint32_t)(seq % RING);
@@ -234,8 +238,7 @@ struct WideRetrieve {
       ring_found[r] = f;
       ring_done[r] = 1;
     } else {
-      if (values_out != nullptr) values_out[i] = v;
-      if (found_out != nullptr) found_out[i] = f;
+      write_out(i, v, f);
     }
   }
   __device__ __forceinline__ bool miss() {
