@@ -341,7 +341,17 @@ struct BlProbe {
   uint64_t i = 0, base_nx = 0, end_nx = 0, base = 0, limit = 0;
   uint32_t k = 0, lbase = 0, k_nx = 0;
   Seq s{};
+  // output staging of the count pass (drive_staged), as for the tables' queries
+  uint32_t* ring_val = nullptr;
+  uint8_t* ring_found = nullptr;
+  uint8_t* ring_done = nullptr;
+  uint64_t seq = 0, flushed = 0;
+  static constexpr uint32_t RING = 128;
 
+  __device__ __forceinline__ void write_out(uint64_t e, uint32_t c, uint8_t) {
+    offsets[e] = c;
+    if (counts != nullptr) counts[e] = c;
+  }
   __device__ __forceinline__ void load(uint64_t op) {
     k_nx = keys[op];
     if constexpr (WRITE) {
@@ -359,8 +369,14 @@ struct BlProbe {
   __device__ __forceinline__ bool found(uint64_t c, uint64_t p) {  // every lane of the group
     if constexpr (!WRITE) {
       if (ln.g.glane == 0) {
-        offsets[i] = c;
-        if (counts != nullptr) counts[i] = (uint32_t)c;
+        if (ring_val != nullptr && seq >= flushed) {
+          const uint32_t r = (uint32_t)(seq % RING);
+          ring_val[r] = (uint32_t)c;
+          ring_found[r] = 0;
+          ring_done[r] = 1;
+        } else {
+          write_out(i, (uint32_t)c, 0);
+        }
       }
     } else {
       if (c == 0 || limit == 0) return true;
@@ -415,7 +431,8 @@ __global__ __launch_bounds__(BLOCK) void k_bl_probe(TableView t, WorkCtl ctl, Bu
                                                     uint32_t* __restrict__ counts, uint64_t* __restrict__ offsets,
                                                     uint32_t* __restrict__ out, unsigned long long* long_n,
                                                     uint64_t* long_list) {
-  BlProbe<G, W, WRITE> op;
+  using P = BlProbe<G, W, WRITE>;
+  P op;
   op.t = t;
   op.b = b;
   op.keys = keys;
@@ -424,7 +441,12 @@ __global__ __launch_bounds__(BLOCK) void k_bl_probe(TableView t, WorkCtl ctl, Bu
   op.out = out;
   op.long_n = long_n;
   op.long_list = long_list;
-  drive<G>(n, ctl, op);
+  if constexpr (WRITE) {
+    drive<G>(n, ctl, op);
+  } else {
+    __shared__ OutRing<P::RING> rings[BLOCK / 64];
+    drive_staged<G, P::RING>(n, ctl, op, rings[threadIdx.x >> 6]);
+  }
 }
 
 // Long lists: one block per list walks it back from the last bucket, all its

@@ -148,6 +148,12 @@ struct SetContains {
   uint8_t* __restrict__ found_out;
   uint64_t i = 0;
   uint32_t k = 0, k_nx = 0;
+  // output staging (drive_staged), as for the tables' queries
+  uint32_t* ring_val = nullptr;
+  uint8_t* ring_found = nullptr;
+  uint8_t* ring_done = nullptr;
+  uint64_t seq = 0, flushed = 0;
+  static constexpr uint32_t RING = 128;
 
   __device__ __forceinline__ void load(uint64_t op) { k_nx = keys[op]; }
   __device__ __forceinline__ void begin(uint64_t op) {
@@ -155,8 +161,17 @@ struct SetContains {
     k = k_nx;
     ln.start(t, k);
   }
+  __device__ __forceinline__ void write_out(uint64_t e, uint32_t, uint8_t f) { found_out[e] = f; }
   __device__ __forceinline__ bool out(uint8_t f) {
-    if (ln.g.glane == 0) found_out[i] = f;
+    if (ln.g.glane == 0) {
+      if (ring_val != nullptr && seq >= flushed) {
+        const uint32_t r = (uint32_t)(seq % RING);
+        ring_found[r] = f;
+        ring_done[r] = 1;
+      } else {
+        write_out(i, 0, f);
+      }
+    }
     return true;
   }
   __device__ __forceinline__ bool step() {
@@ -227,12 +242,14 @@ __global__ __launch_bounds__(BLOCK) void k_set_insert(TableView t, WorkCtl ctl, 
 template <int G, int W>
 __global__ __launch_bounds__(BLOCK) void k_set_contains(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys,
                                                         uint64_t n, uint8_t* __restrict__ found_out) {
-  SetContains<G, W> op;
+  using C = SetContains<G, W>;
+  __shared__ OutRing<C::RING> rings[BLOCK / 64];
+  C op;
   op.t = t;
   op.slots = reinterpret_cast<const uint32_t*>(t.slots);
   op.keys = keys;
   op.found_out = found_out;
-  drive<G>(n, ctl, op);
+  drive_staged<G, C::RING>(n, ctl, op, rings[threadIdx.x >> 6]);
 }
 
 template <int G, int W>
