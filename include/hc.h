@@ -101,7 +101,8 @@ typedef struct {
   uint64_t windows;      /* P: number of windows */
   uint64_t capacity;     /* C = P * W slots */
   uint64_t seed;
-  uint64_t* d_slots;     /* the slot array, C uint64 words (key bits 0-31, value bits 32-63) */
+  uint64_t* d_slots;     /* the slot array: C uint64 words (key bits 0-31, value bits 32-63); 64-bit
+                            tables 2C words (pairs, or C keys then C values); sets C uint32 keys */
 } hc_table_info;
 
 /* Fill *params with the defaults: double hashing, W = 16, g = 4, a fixed seed. */
@@ -370,7 +371,8 @@ hc_err hc_stats(hc_table table, hc_table_stats* h_out, void* stream);
  * hc_device.hpp) by value; bytes must be its size.  The view stays valid until hc_destroy. */
 hc_err hc_device_view(hc_table table, void* h_view, uint64_t bytes);
 
-/* Copy the C slot words into caller memory d_dst (C uint64, device), on the stream. */
+/* Copy the slot array into caller memory d_dst (device), on the stream: C uint64 words (2C for
+ * 64-bit tables, C/2 for sets, whose C 4-byte keys fill them). */
 hc_err hc_dump_slots(hc_table table, uint64_t* d_dst, void* stream);
 
 /* ---- batched launches over many tables ------------------------------------------
