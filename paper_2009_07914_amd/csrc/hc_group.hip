@@ -38,6 +38,15 @@
 
 namespace hc {
 
+// A slot claimed with the placeholder (key, 0) takes its value: no other claim
+// can target it (it is neither empty nor a tombstone) and no query runs in the
+// same launch, so a relaxed atomic store suffices (an exchange would be a
+// second read-modify-write of the line).
+__device__ __forceinline__ void fill_claimed(unsigned long long* slot, unsigned long long word) {
+  __hip_atomic_store(slot, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+
 constexpr int GB = 1024;              // threads per block of the run / long-query kernels
 constexpr int GB_WAVES = GB / 64;
 constexpr int GB_SPL = 4;             // slots per lane in block mode
@@ -141,7 +150,7 @@ __device__ __forceinline__ void claim_run_block(const TableView& t, uint32_t k, 
 #pragma unroll
       for (int j = 0; j < GB_SPL; ++j) {
         if ((succ >> j) & 1u) {
-          atomicExch((unsigned long long*)&t.slots[first + j],
+          fill_claimed((unsigned long long*)&t.slots[first + j],
                      (unsigned long long)make_slot(k, vals[claimed + sex + rr]));
           ++rr;
         }
@@ -224,7 +233,7 @@ __device__ __forceinline__ void claim_run_wave(const TableView& t, uint32_t k, c
       }
       const uint64_t sb = __ballot(ok);
       if (ok)
-        atomicExch((unsigned long long*)&t.slots[idx],
+        fill_claimed((unsigned long long*)&t.slots[idx],
                    (unsigned long long)make_slot(k, vals[claimed + __popcll(sb & below)]));
       claimed += (uint64_t)__popcll(sb);
       if (claimed >= m) break;
@@ -330,7 +339,7 @@ struct ClaimRun {
 #pragma unroll
       for (int j = 0; j < SPL; ++j) {
         if ((succ >> j) & 1) {
-          atomicExch((unsigned long long*)&t.slots[win.first + j],
+          fill_claimed((unsigned long long*)&t.slots[win.first + j],
                      (unsigned long long)make_slot(k, vals[st + claimed + vr]));
           ++vr;
         }
@@ -588,7 +597,7 @@ __global__ __launch_bounds__(GB) void k_heavy_round(TableView t, WorkCtl ctl, co
     for (int j = 0; j < GB_SPL; ++j) {
       if ((succ >> j) & 1u) {
         if (rank < m)
-          atomicExch((unsigned long long*)&t.slots[first + j], (unsigned long long)make_slot(k, vals[st + rank]));
+          fill_claimed((unsigned long long*)&t.slots[first + j], (unsigned long long)make_slot(k, vals[st + rank]));
         ++rank;
       }
     }
