@@ -184,3 +184,52 @@ def test_batch_argument_errors(hc):
     b = hc.hc_batch_create([])  # an empty plan launches nothing
     hc.hc_batch_launch(b)
     hc.hc_batch_destroy(b)
+
+
+@pytest.mark.parametrize("kind", ["single", "counting"])
+def test_every_mixed_pair_in_one_launch(hc, kind):
+    """One table per (g, W) pair of the mixed set plus pairs outside it: every mixed pair runs in the
+    phase's single mixed launch, the others in launches of their own, and every result matches the
+    oracle replaying the list; a captured graph replays it to the same results."""
+    pairs = sorted(MIXED) + [(1, 16), (2, 32), (16, 8), (32, 64)]
+    tabs, ins, ret, outs = [], [], [], []
+    for j, (g, w) in enumerate(pairs):
+        t = hc.Table(kind, 3000 + 517 * j, scheme=["linear", "double", "quadratic"][j % 3], window=w, group=g,
+                     seed=900 + j)
+        n = int(0.85 * t.capacity)
+        keys = gen.keys(800 + j, 1, n)
+        vals = gen.values(850 + j, n)
+        q = np.concatenate([keys, gen.keys(800 + j, n + 1, n // 3)])
+        k_d, q_d = d(keys), d(q)
+        v_d = d(vals) if kind == "single" else None
+        st = torch.empty(n, dtype=torch.uint8, device="cuda")
+        vo = torch.empty(q.size, dtype=torch.uint32, device="cuda")
+        fo = torch.empty(q.size, dtype=torch.uint8, device="cuda")
+        ins.append((hc.hc_batch_op(t, hc.OP_INSERT, k_d, v_d, flags=st, group=g), [k_d, v_d, st]))
+        ret.append((hc.hc_batch_op(t, hc.OP_RETRIEVE, q_d, values_out=vo, flags=fo, group=g), [q_d, vo, fo]))
+        tabs.append((t, keys, vals, q))
+        outs.append((st, vo, fo))
+    b = hc.Batch(ins + ret)
+    assert b.phases == 2
+    assert b.launches == _expected_launches([pairs, pairs]) == 2 * (1 + 4)
+    okind = oracle.SINGLE if kind == "single" else oracle.COUNT
+
+    def check():
+        for (t, keys, vals, q), (st, vo, fo) in zip(tabs, outs):
+            orc = oracle.OracleTable(okind, t.capacity)
+            assert np.array_equal(h(st), orc.insert(keys, vals if kind == "single" else None))
+            vv, ff = orc.retrieve(q)
+            assert np.array_equal(h(vo), vv) and np.array_equal(h(fo), ff)
+            assert t.size() == orc.size()
+
+    b.launch()
+    torch.cuda.synchronize()
+    check()
+    b.capture()
+    for _ in range(2):
+        for t, *_ in tabs:
+            t.clear()
+        b.replay()
+        torch.cuda.synchronize()
+        check()
+    b.close()
