@@ -111,6 +111,42 @@ def _cpu_baseline(w, log2n: int):
                       f"retrieve {q.size / (t2 - t1) / 1e6:.2f} M/s, {t2 - t0:.1f} s"}
 
 
+def _cpu_multicore(w, log2n: int):
+    """The same sample on the oracle sharded by key hash across the host's cores (one independent oracle
+    table per thread; the library call releases the interpreter lock): the analogue of a multi-core CPU
+    hash map, reported beside the single-core baseline."""
+    import threading
+
+    import numpy as np
+    import oracle
+
+    threads = max(1, min(len(os.sched_getaffinity(0)), 16))
+    m = 1 << log2n
+    keys, vals = w["keys"][:m], w["values"][:m]
+    q = np.concatenate([keys, w["absent"][:m]])
+    shard_of = lambda k: ((k.astype(np.uint64) * np.uint64(0x9E3779B1)) >> np.uint64(16)) % np.uint64(threads)  # noqa: E731
+    ks, qs = shard_of(keys), shard_of(q)
+    parts = [(keys[ks == j], vals[ks == j], q[qs == j]) for j in range(threads)]
+    tables = [oracle.OracleTable(oracle.SINGLE, 1 << 28) for _ in range(threads)]
+
+    def phase(fn):
+        ths = [threading.Thread(target=fn, args=(j,)) for j in range(threads)]
+        t0 = time.perf_counter()
+        for th in ths:
+            th.start()
+        for th in ths:
+            th.join()
+        return time.perf_counter() - t0
+
+    ti = phase(lambda j: tables[j].insert(parts[j][0], parts[j][1]))
+    tr = phase(lambda j: tables[j].retrieve(parts[j][2]))
+    ops = keys.size + q.size
+    return {"value": round(ops / (ti + tr) / 1e9, 6), "unit": "G ops/s", "threads": threads,
+            "kind": "oracle sharded by key hash, one table per thread",
+            "sample": f"the single-core sample; insert {keys.size / ti / 1e6:.2f} M/s, "
+                      f"retrieve {q.size / tr / 1e6:.2f} M/s"}
+
+
 def main():
     args = _parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -247,6 +283,7 @@ def main():
     table.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(w, args.cpu_sample_log2)
+        out["cpu_multicore"] = _cpu_multicore(w, args.cpu_sample_log2)
     print(json.dumps(out), flush=True)
 
 
