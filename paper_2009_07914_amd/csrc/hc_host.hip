@@ -97,13 +97,16 @@ __device__ uint64_t block_exclusive_scan(uint64_t x, uint64_t* total) {
   return before + incl - x;
 }
 
+// Tile sums: coalesced loads (a sum does not care about order), one block reduction.
 __global__ __launch_bounds__(BLOCK) void k_scan_tile_sums(const uint64_t* __restrict__ a, uint64_t n,
                                                           uint64_t* __restrict__ tiles) {
-  const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
+  const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + threadIdx.x;
   uint64_t s = 0;
 #pragma unroll
-  for (int j = 0; j < SCAN_ITEMS; ++j)
-    if (base + j < n) s += a[base + j];
+  for (int j = 0; j < SCAN_ITEMS; ++j) {
+    const uint64_t i = base + (uint64_t)j * BLOCK;
+    if (i < n) s += a[i];
+  }
   uint64_t total;
   block_exclusive_scan(s, &total);
   if (threadIdx.x == 0) tiles[blockIdx.x] = total;
@@ -133,22 +136,37 @@ __global__ __launch_bounds__(BLOCK) void k_scan_tiles(uint64_t* __restrict__ til
   if (threadIdx.x == 0) offsets[n] = carry;
 }
 
+// Apply: the tile goes through LDS so that global loads and stores are coalesced while each
+// thread scans SCAN_ITEMS consecutive elements.
 __global__ __launch_bounds__(BLOCK) void k_scan_apply(uint64_t* __restrict__ a, uint64_t n,
                                                       const uint64_t* __restrict__ tiles) {
-  const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE + (uint64_t)threadIdx.x * SCAN_ITEMS;
+  __shared__ uint64_t buf[SCAN_TILE];
+  const uint64_t base = (uint64_t)blockIdx.x * SCAN_TILE;
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; ++j) {
+    const uint64_t i = base + (uint64_t)j * BLOCK + threadIdx.x;
+    buf[j * BLOCK + threadIdx.x] = i < n ? a[i] : 0;
+  }
+  __syncthreads();
   uint64_t v[SCAN_ITEMS];
   uint64_t s = 0;
 #pragma unroll
   for (int j = 0; j < SCAN_ITEMS; ++j) {
-    v[j] = (base + j < n) ? a[base + j] : 0;
+    v[j] = buf[threadIdx.x * SCAN_ITEMS + j];
     s += v[j];
   }
   uint64_t total;
   uint64_t p = tiles[blockIdx.x] + block_exclusive_scan(s, &total);
 #pragma unroll
   for (int j = 0; j < SCAN_ITEMS; ++j) {
-    if (base + j < n) a[base + j] = p;
+    buf[threadIdx.x * SCAN_ITEMS + j] = p;
     p += v[j];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < SCAN_ITEMS; ++j) {
+    const uint64_t i = base + (uint64_t)j * BLOCK + threadIdx.x;
+    if (i < n) a[i] = buf[j * BLOCK + threadIdx.x];
   }
 }
 
