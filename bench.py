@@ -150,7 +150,7 @@ def _cpu_multicore(w, log2n: int):
 def main():
     args = _parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only (no sharding); use --gpus 1", file=sys.stderr)
+        print("bench.py: the tables run on one GPU (no sharding across GPUs); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batched":
         return bench_batched(args)
