@@ -1,10 +1,17 @@
 """The autotuner's table (CPU): every entry is a configuration the batched launcher can run in one
 mixed launch, choose() returns the nearest grid point, and a missing table falls back to the defaults."""
+import importlib.util
 import json
+import os
 
 import pytest
 
-from paper_2009_07914_amd import autotune
+# loaded from its file: the package itself loads the HIP library, which these CPU tests do not need
+_PATH = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2009_07914_amd",
+                     "autotune.py")
+_spec = importlib.util.spec_from_file_location("hc_autotune", _PATH)
+autotune = importlib.util.module_from_spec(_spec)
+_spec.loader.exec_module(autotune)
 
 # (group size, window) pairs of the batched launcher's mixed launch
 MIXED = {(1, 8), (2, 8), (4, 8), (8, 8), (2, 16), (4, 16), (8, 16), (16, 16), (4, 32), (8, 32), (16, 32)}
