@@ -83,3 +83,14 @@ class BruteTable:
 
     def size(self):
         return len(self.pairs)
+
+    def num_keys(self):
+        seen = []
+        for pk, _ in self.pairs:
+            if pk not in seen:
+                seen.append(pk)
+        return len(seen)
+
+    def contents(self):
+        """Every stored (key, value) pair (one per key for single-value / counting), sorted."""
+        return sorted((pk, v) for pk, v in self.pairs)

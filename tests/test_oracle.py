@@ -2,7 +2,8 @@
 
 * brute force: a linear-scan list model (tests/brute.py) on random op sequences
   with tiny capacities and key ranges, every kind and op, reserved keys, full
-  tables, erase then re-insert -- exact agreement;
+  tables, erase then re-insert -- exact agreement of every result, the size, the
+  number of distinct keys and the full sorted content after every operation;
 * library routines on larger inputs: counting = numpy.unique counts,
   multi-value segments = lexsort grouping, offsets = cumsum;
 * invariants: every inserted key found with its last-written value, absent keys
@@ -57,6 +58,9 @@ def test_oracle_equals_brute_force(kind, seed):
             off_b, val_b = b.retrieve_all(batch)
             assert list(off_o) == off_b and list(val_o) == val_b
         assert o.size() == b.size()
+        assert o.num_keys() == b.num_keys()
+        k_o, v_o = o.dump()
+        assert list(zip(k_o.tolist(), v_o.tolist())) == b.contents()
 
 
 def test_counting_equals_numpy_unique():
