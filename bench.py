@@ -501,24 +501,42 @@ def bench_multi(args):
     pos = np.searchsorted(u, w["queries"])
     hit = (pos < u.size) & (u[np.minimum(pos, u.size - 1)] == w["queries"])
     expect[hit] = c[pos[hit]]
-    # per-key insert (the paper's): one atomic per occurrence, so the hottest key serialises
-    ins = ev_time((ct.clear, lambda: hc.hc_insert(ct.handle, keys, None, None, args.group_insert, s)),
-                  1 + min(args.steps, 2))[1:]
+    # per-key insert: equal keys of each 1024-key tile are combined in LDS, then one upsert per
+    # distinct key of the tile (the hottest key costs one atomic per tile, not one per occurrence)
+    st_ct = torch.empty(n, dtype=torch.uint8, device=dev)
+    ins = ev_time((ct.clear, lambda: hc.hc_insert(ct.handle, keys, None, None, args.group_insert, s)), reps)[args.warmup:]
+    ins_st = ev_time((ct.clear, lambda: hc.hc_insert(ct.handle, keys, None, st_ct, args.group_insert, s)),
+                     reps)[args.warmup:]
     hc.hc_retrieve(ct.handle, q, cnt, fnd, args.group_query, s)
     assert np.array_equal(cnt.cpu().numpy(), expect), "counts disagree with numpy.unique"
+    assert int((st_ct == hc.S_OK).sum()) == u.size, "one OK status per distinct key"
+    fails = ct.stats()["cas_fails"]
     # grouped insert: one insert per distinct key with its multiplicity
     gins = ev_time((ct.clear, lambda: hc.hc_insert_grouped(ct.handle, keys, None, s)), reps)[args.warmup:]
     ret = ev_time((None, lambda: hc.hc_retrieve(ct.handle, q, cnt, fnd, args.group_query, s)), reps)[args.warmup:]
     assert np.array_equal(cnt.cpu().numpy(), expect), "counts disagree with numpy.unique"
     assert ct.size() == u.size
     res["counting_zipf"] = {"insert_per_key_ms": round(statistics.mean(ins), 4),
+                            "insert_per_key_status_ms": round(statistics.mean(ins_st), 4),
+                            "insert_per_key_cas_fails": int(fails),
                             "insert_grouped_ms": round(statistics.mean(gins), 4),
                             "retrieve_ms": round(statistics.mean(ret), 4),
                             "insert_per_key_gops": round(n / statistics.mean(ins) / 1e6, 4),
                             "insert_grouped_gops": round(n / statistics.mean(gins) / 1e6, 4),
                             "retrieve_gops": round(q.numel() / statistics.mean(ret) / 1e6, 4),
                             "distinct_keys": int(u.size), "top_key_count": int(c.max())}
-    del keys, q, cnt, fnd, ct, w
+    del keys, q, cnt, fnd, ct, w, st_ct
+    # ---- counting, keys uniform on 1..2^26 (few repeats): the cost of combining where it saves little
+    w = gen.multi_value_uniform_r_workload(n, 1, gen.SEED_BASE + 4)
+    keys = torch.from_numpy(w["keys"]).to(dev)
+    ct = hc.Table("counting", cap, scheme="double", window=16, group=4, device=dev)
+    ins = ev_time((ct.clear, lambda: hc.hc_insert(ct.handle, keys, None, None, args.group_insert, s)), reps)[args.warmup:]
+    u = np.unique(w["keys"])
+    assert ct.size() == u.size
+    res["counting_uniform"] = {"insert_per_key_ms": round(statistics.mean(ins), 4),
+                               "insert_per_key_gops": round(n / statistics.mean(ins) / 1e6, 4),
+                               "distinct_keys": int(u.size)}
+    del keys, ct, w
     # ---- multi-value, uniform multiplicity r
     mv = hc.Table("multi", cap, scheme="double", window=16, group=4, device=dev)
     for r in (1, 4, 16, 64):

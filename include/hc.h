@@ -32,8 +32,18 @@
  *   - Element outcomes go to the optional d_status array (uint8, one per
  *     input): HC_S_*.  A duplicate key is a warning, not an error.
  *   - Concurrency (Sec. IV-D): calls of the same kind, and reads, may
- *     overlap on one table; a write call must not overlap a call of another
- *     kind on the same table.  A handle is used by one host thread at a time.
+ *     overlap on one table (e.g. on several streams); a write call must not
+ *     overlap a call of another kind on the same table.  Two calls are exempt
+ *     and ordered by the library instead: hc_insert_grouped, and hc_insert on
+ *     a bucket list table, run one after another per table on the device (each
+ *     waits for the table's previous such call through an event, without
+ *     blocking the host).  A handle is used by one host thread at a time.
+ *   - Scratch memory: calls that need device workspace (multi-value and
+ *     bucket list passes, grouped inserts, hc_stats) take it per call from a
+ *     library-owned pool of the current device, ordered on the call's stream
+ *     (hipMallocFromPoolAsync / hipFreeAsync): concurrent calls never share
+ *     it and no call synchronises the device for it.  Freed blocks stay in
+ *     the pool for later calls.  HC_E_NOMEM if the pool cannot grow.
  *   - Errors: every call returns hc_err; hc_last_error() gives a message for
  *     the calling thread's last failure.  No C++ exception crosses the ABI.
  *     A device fault inside a kernel is not recoverable by the library.
@@ -307,22 +317,25 @@ hc_err hc_erase(hc_table table, const uint32_t* d_keys, uint64_t n, uint8_t* d_s
 /* Multi-value pass 1 (Sec. IV-B4): d_offsets (n+1 uint64) receives the exclusive prefix sum
  * of the per-query value counts, d_offsets[n] = total; d_counts (optional, n uint32) the
  * counts themselves; *h_total (optional) the total, which synchronises the stream.
- * A query still open after 64 windows is finished by a block of 1024 threads (keys with
- * very many values).  Uses the table's workspace (8 bytes per query).
- * Multi-value tables only (HC_E_KIND otherwise). */
+ * A query still open after 64 windows is handed to rounds in which blocks of 1024 threads scan
+ * segments of its window sequence in parallel (keys with very many values); the hand-over list
+ * holds n/16 + 1024 queries, past which groups walk on by themselves.  Workspace (per call,
+ * from the pool): 8 bytes per 2048 queries for the scan plus 32 bytes per hand-over entry.
+ * Multi-value and bucket list tables (HC_E_KIND otherwise). */
 hc_err hc_count_values(hc_table table, const uint32_t* d_keys, uint64_t n, uint32_t* d_counts,
                        uint64_t* d_offsets, uint64_t* h_total, uint32_t group, void* stream);
 
 /* Multi-value pass 2 (Sec. IV-B4): writes the values of d_keys[i] to
  * d_values_out[d_offsets[i] .. d_offsets[i+1]); the order inside a segment is unspecified.
  * d_offsets must come from hc_count_values on the same keys with no write call in between;
- * writes never leave a segment.  Multi-value tables only. */
+ * writes never leave a segment.  Long queries as in hc_count_values (40 bytes of workspace per
+ * hand-over entry).  Multi-value and bucket list tables. */
 hc_err hc_retrieve_all(hc_table table, const uint32_t* d_keys, uint64_t n, const uint64_t* d_offsets,
                        uint32_t* d_values_out, uint32_t group, void* stream);
 
 /* Insert of n keys grouped by key, for batches in which some keys repeat very often (not in the
- * paper).  The batch is sorted by key in a workspace (about 48 bytes per element, allocated by the
- * table; growing it synchronises the device) and handled run by run:
+ * paper).  The batch is sorted by key in a per-call workspace (about 48 bytes per element, from the
+ * pool) and handled run by run:
  *  - multi-value tables: the paper's per-pair insert, hc_insert, makes the i-th copy of a key scan past
  *    the i-1 earlier ones, so a key with m copies costs about m^2/(2W) window visits (Sec. V-B); here
  *    each key's run claims its slots in one pass along its window sequence (long runs spread over the
@@ -352,7 +365,11 @@ hc_err hc_info(hc_table table, hc_table_info* h_out);
 /* Full scan of the slot array (a diagnostic, not on the hot path).  The probe length of a
  * live slot is the number of windows a retrieval of its key visits up to and including the
  * slot's window: its index l in the key's window sequence (Sec. II), plus one.  It grows with
- * the load factor (Sec. IV-B); live counts the same entries as hc_size. */
+ * the load factor (Sec. IV-B); live counts the same entries as hc_size.  cas_fails is not from
+ * the scan: it counts, since hc_create or the last hc_clear, the claim CASes of per-element
+ * inserts (hc_insert, batched launches and the device-side insert) that found their slot
+ * changed by another insert -- the collisions Sec. IV-B2 names as the cost of concurrent
+ * insertion.  Each such failure is followed by a retry at the next candidate or an update. */
 #define HC_PROBE_BUCKETS 16
 typedef struct {
   uint64_t live;        /* slots holding a key */
@@ -361,6 +378,7 @@ typedef struct {
   uint64_t max_probe;   /* largest probe length over live slots (<= P) */
   uint64_t probe_sum;   /* sum of probe lengths over live slots */
   uint64_t probe_hist[HC_PROBE_BUCKETS];  /* live slots with probe length in [2^b, 2^(b+1)); last bucket open */
+  uint64_t cas_fails;   /* failed claim CASes of inserts since create / clear */
 } hc_table_stats;
 /* Synchronises the stream.  Errors: HC_E_ARG (NULL output), HC_E_NOMEM. */
 hc_err hc_stats(hc_table table, hc_table_stats* h_out, void* stream);
@@ -413,8 +431,11 @@ typedef struct hc_batch_s* hc_batch;
 hc_err hc_batch_create(hc_batch* out, const hc_batch_op* ops, uint32_t count);
 
 /* Enqueue every phase of the plan on `stream` (asynchronous; no allocation and no
- * memset, so it may be captured into a graph).  Two launches of one plan must not
- * run concurrently. */
+ * memset, so it may be captured into a graph).  Each launch of the plan uses work
+ * counters that belong to the plan (allocated by hc_batch_create and reset by the
+ * launch itself), never the counters other calls take, so launches of other plans and
+ * other calls may run beside it on other streams; two launches of one plan (or of its
+ * captured graph) must not run concurrently. */
 hc_err hc_batch_launch(hc_batch batch, void* stream);
 
 /* Number of phases and of kernel launches per hc_batch_launch. */
@@ -427,28 +448,40 @@ hc_err hc_batch_destroy(hc_batch batch);
 hc_err hc_batch_run(const hc_batch_op* ops, uint32_t count, void* stream);
 
 /* Capture hc_batch_launch(batch) into an instantiated hipGraphExec (returned as
- * void*); replay it with hc_graph_launch.  Replays must not overlap each other. */
+ * void*); replay it with hc_graph_launch.  The graph uses the plan's own work counters:
+ * replays of it must not overlap each other or a hc_batch_launch of the same plan, and
+ * the plan must outlive the graph. */
 hc_err hc_batch_capture(hc_batch batch, void** h_graph_exec);
 hc_err hc_graph_launch(void* graph_exec, void* stream);
 hc_err hc_graph_destroy(void* graph_exec);
 
 /* ---- serving loop -----------------------------------------------------------------
- * Not in the paper.  A server owns a worker thread that admits requests (host-side
- * key/value buffers on resident single-value or counting tables) in arrival order
- * while its device staging ring has room, coalesces everything admitted at once into
- * one batched launch group (whose phases keep every table's operations in arrival
- * order), overlaps the input/output copies of a group with the kernels of its
- * neighbours on rotating streams, and orders the kernels of consecutive groups, so
- * every request's results equal those of running the requests one by one in
- * arrival order -- except where requests admitted together write the same key of one
- * table with the same kind of operation (then which write wins is unspecified).
+ * Not in the paper (built from the bulk calls and the concurrency rules of Sec. IV-D).
+ * A server owns a worker thread that admits requests (host-side key/value buffers on
+ * resident single-value or counting tables) in arrival order while its device staging
+ * ring (the admission budget) has room, coalesces everything admitted at once into one
+ * batched launch group (whose phases keep every table's operations in arrival order),
+ * overlaps the input/output copies of a group with the kernels of its neighbours on
+ * rotating streams, and makes a group's kernels wait on the device for the unfinished
+ * earlier groups that share one of its tables (groups on disjoint tables run side by
+ * side, and may complete out of arrival order).  Every request's results equal those of
+ * running the requests one by one in arrival order, except where requests admitted into
+ * one group write the same key of one table with the same kind of operation: those
+ * writes run in one launch (one epoch), and the results are those of one of their
+ * orders.  For single-value inserts of key k with values v1..vm in one epoch: the value
+ * left is one of v1..vm; if k was absent before, exactly one of those inserts reports OK
+ * and the others DUPLICATE, else all report DUPLICATE.  Counting inserts: counts are
+ * exact (addition commutes), statuses as above.  Erases: if k was present, exactly one
+ * reports OK and the others NOT_FOUND.  A retrieve that follows in arrival order sees the
+ * value left by the epoch.
  * Host buffers should be pinned (hipHostMalloc) for asynchronous copies; they must
  * stay valid until the request completes. */
 
 typedef struct hc_server_s* hc_server;
 
 typedef struct {
-  uint64_t staging_bytes;       /* device staging ring = admission budget (>= 1 MiB) */
+  uint64_t staging_bytes;       /* device staging ring = admission budget (>= 1 MiB); at most half
+                                   the HBM free at creation (a larger request is cut to that) */
   uint64_t max_group_ops;       /* most elements coalesced into one launch group; 0 = no limit */
   uint32_t max_group_requests;  /* most requests per launch group; 0 = 1024 */
   uint32_t streams;             /* streams rotated over launch groups; 0 = 3 */
@@ -469,6 +502,7 @@ typedef struct {
 
 typedef struct {
   uint64_t submitted, completed, launch_groups, ops_completed, staging_in_use;
+  uint64_t staging_bytes;       /* the admission budget in use (staging ring size) */
 } hc_server_counts;
 
 /* Defaults: 1 GiB staging, no element limit, 1024 requests per group, 3 streams. */

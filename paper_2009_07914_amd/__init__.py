@@ -72,7 +72,7 @@ class HcBloomInfo(ctypes.Structure):
 class HcTableStats(ctypes.Structure):
     _fields_ = [("live", ctypes.c_uint64), ("tombstones", ctypes.c_uint64), ("empty", ctypes.c_uint64),
                 ("max_probe", ctypes.c_uint64), ("probe_sum", ctypes.c_uint64),
-                ("probe_hist", ctypes.c_uint64 * PROBE_BUCKETS)]
+                ("probe_hist", ctypes.c_uint64 * PROBE_BUCKETS), ("cas_fails", ctypes.c_uint64)]
 
 
 class HcBatchOp(ctypes.Structure):
@@ -95,7 +95,8 @@ class HcRequest(ctypes.Structure):
 
 class HcServerCounts(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64), ("launch_groups", ctypes.c_uint64),
-                ("ops_completed", ctypes.c_uint64), ("staging_in_use", ctypes.c_uint64)]
+                ("ops_completed", ctypes.c_uint64), ("staging_in_use", ctypes.c_uint64),
+                ("staging_bytes", ctypes.c_uint64)]
 
 
 _p, _u32, _u64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
@@ -683,7 +684,7 @@ class Table:
     def stats(self, stream=None) -> dict:
         st = hc_stats(self.handle, stream)
         return {"live": st.live, "tombstones": st.tombstones, "empty": st.empty, "max_probe": st.max_probe,
-                "probe_sum": st.probe_sum, "probe_hist": list(st.probe_hist)}
+                "probe_sum": st.probe_sum, "probe_hist": list(st.probe_hist), "cas_fails": st.cas_fails}
 
     def dump_slots(self, stream=None):
         """The slot array: C uint64 words (2C for 64-bit tables: pairs, or C keys then C values in the

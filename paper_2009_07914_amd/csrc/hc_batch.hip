@@ -131,52 +131,58 @@ uint32_t mixed_variant(uint32_t G, uint32_t W) {
 
 template <typename K>
 static hc_err launch_persistent(K k, const BatchDesc* d_descs, const uint64_t* d_chunk_start, uint32_t ndesc,
-                                uint64_t total_chunks, hipStream_t stream) {
+                                uint64_t total_chunks, unsigned long long* counters, hipStream_t stream) {
   const uint64_t cap = (uint64_t)device_cu_count() * (uint64_t)blocks_per_cu(reinterpret_cast<const void*>(k));
   const uint64_t need = (total_chunks + (BLOCK / 64) - 1) / (BLOCK / 64);
   const unsigned grid = (unsigned)(need < cap ? need : cap);
   WorkCtl ctl = work_for(0, 64, grid);
+  if (counters != nullptr) ctl.counters = counters;
   hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, d_descs, d_chunk_start, ndesc, ctl);
   return check_launch("batch");
 }
 
 template <uint32_t OP>
 static hc_err launch_batch_op(uint32_t G, uint32_t W, const BatchDesc* d_descs, const uint64_t* d_chunk_start,
-                              uint32_t ndesc, uint64_t total_chunks, hipStream_t stream) {
+                              uint32_t ndesc, uint64_t total_chunks, unsigned long long* counters,
+                              hipStream_t stream) {
   return dispatch_gw(G, W, [&](auto g, auto w) -> hc_err {
     constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
-    return launch_persistent(k_batch<OP, GG, WW>, d_descs, d_chunk_start, ndesc, total_chunks, stream);
+    return launch_persistent(k_batch<OP, GG, WW>, d_descs, d_chunk_start, ndesc, total_chunks, counters, stream);
   });
 }
 
 hc_err launch_batch(uint32_t op, uint32_t G, uint32_t W, const BatchDesc* d_descs, const uint64_t* d_chunk_start,
-                    uint32_t ndesc, uint64_t total_chunks, hipStream_t stream) {
+                    uint32_t ndesc, uint64_t total_chunks, unsigned long long* counters, hipStream_t stream) {
   if (ndesc == 0 || total_chunks == 0) return HC_OK;
   switch (op) {
     case BATCH_INSERT:
-      return launch_batch_op<BATCH_INSERT>(G, W, d_descs, d_chunk_start, ndesc, total_chunks, stream);
+      return launch_batch_op<BATCH_INSERT>(G, W, d_descs, d_chunk_start, ndesc, total_chunks, counters, stream);
     case BATCH_COUNT:
-      return launch_batch_op<BATCH_COUNT>(G, W, d_descs, d_chunk_start, ndesc, total_chunks, stream);
+      return launch_batch_op<BATCH_COUNT>(G, W, d_descs, d_chunk_start, ndesc, total_chunks, counters, stream);
     case BATCH_RETRIEVE:
-      return launch_batch_op<BATCH_RETRIEVE>(G, W, d_descs, d_chunk_start, ndesc, total_chunks, stream);
+      return launch_batch_op<BATCH_RETRIEVE>(G, W, d_descs, d_chunk_start, ndesc, total_chunks, counters, stream);
     case BATCH_ERASE:
-      return launch_batch_op<BATCH_ERASE>(G, W, d_descs, d_chunk_start, ndesc, total_chunks, stream);
+      return launch_batch_op<BATCH_ERASE>(G, W, d_descs, d_chunk_start, ndesc, total_chunks, counters, stream);
   }
   return fail(HC_E_ARG, "unknown batched operation %u", op);
 }
 
 hc_err launch_batch_mixed(uint32_t op, const BatchDesc* d_descs, const uint64_t* d_chunk_start, uint32_t ndesc,
-                          uint64_t total_chunks, hipStream_t stream) {
+                          uint64_t total_chunks, unsigned long long* counters, hipStream_t stream) {
   if (ndesc == 0 || total_chunks == 0) return HC_OK;
   switch (op) {
     case BATCH_INSERT:
-      return launch_persistent(k_batch_mixed<BATCH_INSERT>, d_descs, d_chunk_start, ndesc, total_chunks, stream);
+      return launch_persistent(k_batch_mixed<BATCH_INSERT>, d_descs, d_chunk_start, ndesc, total_chunks, counters,
+                               stream);
     case BATCH_COUNT:
-      return launch_persistent(k_batch_mixed<BATCH_COUNT>, d_descs, d_chunk_start, ndesc, total_chunks, stream);
+      return launch_persistent(k_batch_mixed<BATCH_COUNT>, d_descs, d_chunk_start, ndesc, total_chunks, counters,
+                               stream);
     case BATCH_RETRIEVE:
-      return launch_persistent(k_batch_mixed<BATCH_RETRIEVE>, d_descs, d_chunk_start, ndesc, total_chunks, stream);
+      return launch_persistent(k_batch_mixed<BATCH_RETRIEVE>, d_descs, d_chunk_start, ndesc, total_chunks, counters,
+                               stream);
     case BATCH_ERASE:
-      return launch_persistent(k_batch_mixed<BATCH_ERASE>, d_descs, d_chunk_start, ndesc, total_chunks, stream);
+      return launch_persistent(k_batch_mixed<BATCH_ERASE>, d_descs, d_chunk_start, ndesc, total_chunks, counters,
+                               stream);
   }
   return fail(HC_E_ARG, "unknown batched operation %u", op);
 }

@@ -32,12 +32,17 @@ constexpr uint32_t MIXED_COUNT = 11;
 uint32_t mixed_variant(uint32_t G, uint32_t W);
 
 // One persistent launch over descs[0..ndesc) (device arrays, all of operation
-// kind `op`, group size G and window W) on `stream`.
+// kind `op`, group size G and window W) on `stream`.  counters: the launch's pair of
+// work counters (zero at the start, reset by the launch's last wavefront), or NULL
+// for a pair from the device's launch-slot ring.
 hc_err launch_batch(uint32_t op, uint32_t G, uint32_t W, const BatchDesc* d_descs, const uint64_t* d_chunk_start,
-                    uint32_t ndesc, uint64_t total_chunks, hipStream_t stream);
+                    uint32_t ndesc, uint64_t total_chunks, unsigned long long* counters, hipStream_t stream);
 // The same over descriptors of several (G, W) pairs of the mixed-launch set.
 hc_err launch_batch_mixed(uint32_t op, const BatchDesc* d_descs, const uint64_t* d_chunk_start, uint32_t ndesc,
-                          uint64_t total_chunks, hipStream_t stream);
+                          uint64_t total_chunks, unsigned long long* counters, hipStream_t stream);
+
+// Words between the counter pairs of consecutive launches of a plan (one 128-byte line each).
+constexpr uint32_t PLAN_COUNTER_STRIDE = 16;
 
 struct PlanLaunch {
   uint32_t op, G, W;           // G = W = 0: a mixed launch (each descriptor's own pair)
@@ -57,8 +62,10 @@ struct PlanHost {
 // Validate and lay out `ops` (tables on device `dev`); no device work.
 hc_err build_plan(const hc_batch_op* ops, uint32_t count, int dev, PlanHost* out);
 
-// Enqueue a plan whose descriptors and chunk starts are in device memory.
+// Enqueue a plan whose descriptors and chunk starts are in device memory.  counters:
+// PLAN_COUNTER_STRIDE words per launch owned by the plan (zeroed once), or NULL for
+// pairs from the launch-slot ring.
 hc_err launch_plan(const std::vector<PlanLaunch>& launches, const BatchDesc* d_descs, const uint64_t* d_cs,
-                   hipStream_t stream);
+                   unsigned long long* counters, hipStream_t stream);
 
 }  // namespace hc

@@ -56,10 +56,15 @@ __device__ __forceinline__ uint64_t make_slot(uint32_t k, uint32_t v) {
 }
 __device__ __forceinline__ bool reserved_key(uint32_t k) { return k == KEY_EMPTY || k == KEY_TOMB; }
 
+// Words of the table's counter block (TableView::size points at word 0).
+constexpr int CTR_SIZE = 0;        // live entries (wrapping add of +/- deltas)
+constexpr int CTR_POOL = 1;        // bucket list tables: pool words handed out
+constexpr int CTR_CAS_FAILS = 2;   // claim CASes of inserts that found the slot changed
+
 // Kernel-side view of a table (passed by value).
 struct TableView {
   uint64_t* slots;
-  unsigned long long* size;  // live entries (wrapping add of +/- deltas)
+  unsigned long long* size;  // the counter block: size[CTR_SIZE], size[CTR_POOL], size[CTR_CAS_FAILS]
   uint32_t P;                // windows, 1 <= P <= 2^31
   uint32_t pmask;            // P - 1 when P is a power of two, else 0
   uint32_t pow2;             // 1 if P is a power of two

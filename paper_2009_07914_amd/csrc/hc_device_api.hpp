@@ -32,7 +32,8 @@ __device__ __forceinline__ uint8_t insert(const TableView& t, uint32_t key, uint
   op.begin(0);
   while (!op.step()) {
   }
-  if (op.added) atomicAdd(t.size, (unsigned long long)op.added);
+  if (op.added) atomicAdd(t.size + CTR_SIZE, (unsigned long long)op.added);
+  if (op.fails) atomicAdd(t.size + CTR_CAS_FAILS, (unsigned long long)op.fails);
   return op.ln.g.bcast(st, 0);  // written by the group's first lane
 }
 

@@ -808,7 +808,7 @@ __global__ __launch_bounds__(GB) void k_long_round(TableView t, WorkCtl ctl, con
 
 // Round state of every handed-over entry; round 0 lists all of them.
 __global__ __launch_bounds__(256) void k_long_init(LongState ls, uint32_t budget) {
-  const uint64_t L = *ls.nlong;
+  const uint64_t L = *ls.nlong < ls.cap ? *ls.nlong : ls.cap;
   const uint64_t stride = (uint64_t)gridDim.x * 256;
   for (uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x; e < L; e += stride) {
     ls.base[e] = budget;
@@ -822,7 +822,7 @@ __global__ __launch_bounds__(256) void k_long_init(LongState ls, uint32_t budget
 // counts[i] of the handed-over queries, once their offsets hold the full counts.
 __global__ __launch_bounds__(256) void k_long_counts_out(LongState ls, const uint64_t* __restrict__ offsets,
                                                          uint32_t* __restrict__ counts) {
-  const uint64_t L = *ls.nlong;
+  const uint64_t L = *ls.nlong < ls.cap ? *ls.nlong : ls.cap;
   const uint64_t stride = (uint64_t)gridDim.x * 256;
   for (uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x; e < L; e += stride) {
     const uint64_t i = ls.entries[e];
@@ -1036,6 +1036,8 @@ hc_err launch_zero_u64(unsigned long long* p, uint32_t count, hipStream_t s) {
   return check_launch("zero");
 }
 
+uint64_t long_capacity(uint64_t n) { return n < walk_capacity(n) ? n : walk_capacity(n); }
+
 uint64_t long_workspace_bytes(uint64_t n, int mode) {
   return 256 + align256((mode == 0 ? 8 : 16) * n) + align256(8 * n) + 4 * align256(4 * n) + 256;
 }
@@ -1043,6 +1045,7 @@ uint64_t long_workspace_bytes(uint64_t n, int mode) {
 LongState long_layout(void* ws, uint64_t n, int mode) {
   char* p = (char*)ws;
   LongState ls;
+  ls.cap = n;
   ls.nlong = (const unsigned long long*)p;
   ls.nopen = (unsigned long long*)p + 1;  // QROUNDS_MAX + 1 words after the entry count
   p += 256;

@@ -27,7 +27,8 @@ hc_err launch_bl_grouped(const TableView& t, const BucketView& b, uint32_t G, ui
 // Queries handed over by the count (mode 0) or write (mode 1) pass after `budget`
 // windows, and the state of the rounds that finish them, all in one workspace.
 struct LongState {
-  const unsigned long long* nlong;  // entries handed over (word 0 of the workspace)
+  uint64_t cap;                     // entries the workspace holds
+  const unsigned long long* nlong;  // hand-over attempts (word 0 of the workspace; entries: min(*nlong, cap))
   unsigned long long* nopen;        // open entries at the start of each round
   uint64_t* entries;                // mode 0: query index; mode 1: (query index, values written)
   uint64_t* base;                   // next window of the entry's sequence
@@ -35,8 +36,11 @@ struct LongState {
   uint32_t* done;                   // segments of the current round finished
   uint32_t* lists[2];               // open entries of the current and the next round
 };
-uint64_t long_workspace_bytes(uint64_t n, int mode);
-LongState long_layout(void* ws, uint64_t n, int mode);
+// Entries of the hand-over list for n queries: long queries are rare; past this many,
+// groups walk on by themselves.
+uint64_t long_capacity(uint64_t n);
+uint64_t long_workspace_bytes(uint64_t cap, int mode);
+LongState long_layout(void* ws, uint64_t cap, int mode);
 hc_err launch_long_queries(const TableView& t, uint32_t W, int mode, const uint32_t* keys, const LongState& ls,
                            uint64_t n, uint32_t budget, uint64_t* offsets, uint32_t* counts, uint32_t* out,
                            hipStream_t s);

@@ -31,6 +31,9 @@ struct hc_batch_s {
   std::vector<hc::PlanLaunch> launches;  // in phase order
   hc::BatchDesc* d_descs = nullptr;
   uint64_t* d_chunk_start = nullptr;
+  // work counters of the plan's own launches (not the shared launch-slot ring), so a
+  // captured graph never shares counters with launches made outside it
+  unsigned long long* d_counters = nullptr;
 };
 
 struct hc_table_s {
@@ -38,12 +41,12 @@ struct hc_table_s {
   uint32_t kind, scheme, window, group;
   uint64_t P, C, seed;
   uint64_t* slots;
-  unsigned long long* d_size;
-  uint64_t* d_tiles;      // prefix-sum workspace (tile sums)
-  uint64_t tiles_cap;     // entries allocated in d_tiles
-  void* d_ws;             // workspace of the multi-value passes (long-query lists, grouped insert)
-  uint64_t ws_bytes;
+  unsigned long long* d_size;  // counter block: size, bucket pool, failed claim CASes
   bool owns_slots;        // false: caller-owned slot array (hc_create_in)
+  // grouped and bucket list inserts of one table run one after another: each waits on the
+  // device for the event recorded after the previous one, whatever stream it is issued on
+  hipEvent_t order_ev = nullptr;
+  bool order_pending = false;
   // bucket list tables (kind HC_BUCKET_LIST)
   uint64_t* d_cum = nullptr;       // cumulative bucket sizes of the ramp
   uint32_t bl_m = 0, bl_smax = 0;
@@ -63,7 +66,10 @@ __global__ __launch_bounds__(BLOCK) void k_fill_empty(ulonglong2* __restrict__ s
   const uint64_t stride = (uint64_t)gridDim.x * BLOCK;
   const ulonglong2 z = {0ull, 0ull};
   for (uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x; i < pairs; i += stride) slots[i] = z;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *size = 0ull;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    size[CTR_SIZE] = 0ull;
+    size[CTR_CAS_FAILS] = 0ull;
+  }
 }
 
 // ---- exclusive prefix sum, in place, n counts -> n+1 offsets --------------------
@@ -187,23 +193,27 @@ hc_err exclusive_scan_inplace(uint64_t* a, uint64_t n, uint64_t* tiles, hipStrea
   return HC_OK;
 }
 
-// Grow the table's workspace to at least `bytes` (synchronises the device when it grows).
-static hc_err ensure_ws(hc_table_s* t, uint64_t bytes) {
-  if (t->ws_bytes >= bytes) return HC_OK;
-  if (t->d_ws) {
-    const hipError_t e = hipDeviceSynchronize();
-    if (e != hipSuccess) return fail(HC_E_DEVICE, "workspace: synchronise: %s", hipGetErrorString(e));
-    (void)hipFree(t->d_ws);
-    t->d_ws = nullptr;
-    t->ws_bytes = 0;
+// Ordered inserts (grouped, bucket list): wait for the table's previous one, on the device.
+static hc_err order_begin(hc_table_s* t, hipStream_t s) {
+  if (t->order_ev == nullptr) {
+    const hipError_t e = hipEventCreateWithFlags(&t->order_ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      t->order_ev = nullptr;
+      return hip_fail(e, "ordering event");
+    }
   }
-  const hipError_t e = hipMalloc(&t->d_ws, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    t->d_ws = nullptr;
-    return fail(HC_E_NOMEM, "hipMalloc of %llu workspace bytes failed", (unsigned long long)bytes);
+  if (t->order_pending) {
+    const hipError_t e = hipStreamWaitEvent(s, t->order_ev, 0);
+    if (e != hipSuccess) return hip_fail(e, "ordering wait");
   }
-  t->ws_bytes = bytes;
+  return HC_OK;
+}
+
+static hc_err order_end(hc_table_s* t, hipStream_t s, hc_err r) {
+  if (r != HC_OK) return r;
+  const hipError_t e = hipEventRecord(t->order_ev, s);
+  if (e != hipSuccess) return hip_fail(e, "ordering record");
+  t->order_pending = true;
   return HC_OK;
 }
 
@@ -425,15 +435,50 @@ hc_err build_plan(const hc_batch_op* ops, uint32_t count, int dev, PlanHost* out
 }
 
 hc_err launch_plan(const std::vector<PlanLaunch>& launches, const BatchDesc* d_descs, const uint64_t* d_cs,
-                   hipStream_t stream) {
-  for (const auto& L : launches) {
+                   unsigned long long* counters, hipStream_t stream) {
+  for (size_t j = 0; j < launches.size(); ++j) {
+    const PlanLaunch& L = launches[j];
+    unsigned long long* c = counters ? counters + j * PLAN_COUNTER_STRIDE : nullptr;
     hc_err r = L.G == 0 ? launch_batch_mixed(L.op, d_descs + L.first_desc, d_cs + L.cs_offset, L.ndesc,
-                                             L.total_chunks, stream)
+                                             L.total_chunks, c, stream)
                         : launch_batch(L.op, L.G, L.W, d_descs + L.first_desc, d_cs + L.cs_offset, L.ndesc,
-                                       L.total_chunks, stream);
+                                       L.total_chunks, c, stream);
     if (r != HC_OK) return r;
   }
   return HC_OK;
+}
+
+}  // namespace hc
+
+namespace hc {
+
+// Workspace of a count pass: the scan's tile sums, then the long-query state (multi-value
+// tables, `cap` hand-over entries).
+static uint64_t count_values_ws_bytes(uint64_t n, uint64_t cap) {
+  const uint64_t tiles = (8 * scan_tiles_needed(n) + 255) & ~255ull;
+  return tiles + (cap ? long_workspace_bytes(cap, 0) : 0);
+}
+
+// Count pass and exclusive scan of hc_count_values in the workspace `ws` (count_values_ws_bytes).
+static hc_err count_values_in(hc_table_s* t, const uint32_t* d_keys, uint64_t n, uint32_t* d_counts,
+                              uint64_t* d_offsets, uint32_t g, void* ws, uint64_t cap, hipStream_t s) {
+  hc_err r = HC_OK;
+  uint64_t* tiles = static_cast<uint64_t*>(ws);
+  void* lws = static_cast<char*>(ws) + ((8 * scan_tiles_needed(n) + 255) & ~255ull);
+  if (n > 0 && t->kind == HC_BUCKET_LIST) {  // the count sits in the key's slot
+    if ((r = launch_bl_count(view_of(t), g, t->window, d_keys, n, d_counts, d_offsets, s)) != HC_OK) return r;
+  } else if (n > 0) {
+    // queries still open after LONG_BUDGET windows are finished by block-wide segment rounds
+    const LongState ls = long_layout(lws, cap, 0);
+    if ((r = launch_zero_u64((unsigned long long*)ls.nlong, 1, s)) != HC_OK) return r;
+    if ((r = launch_count_multi(view_of(t), g, t->window, d_keys, n, d_counts, d_offsets, nullptr, LONG_BUDGET,
+                                ls.entries, (unsigned long long*)ls.nlong, cap, s)) != HC_OK)
+      return r;
+    if ((r = launch_long_queries(view_of(t), t->window, 0, d_keys, ls, n, LONG_BUDGET, d_offsets, d_counts, nullptr,
+                                 s)) != HC_OK)
+      return r;
+  }
+  return exclusive_scan_inplace(d_offsets, n, tiles, s);
 }
 
 }  // namespace hc
@@ -664,8 +709,7 @@ hc_err hc_destroy(hc_table t) {
   hipError_t e = hipDeviceSynchronize();
   if (t->slots && t->owns_slots) (void)hipFree(t->slots);
   if (t->d_size) (void)hipFree(t->d_size);
-  if (t->d_tiles) (void)hipFree(t->d_tiles);
-  if (t->d_ws) (void)hipFree(t->d_ws);
+  if (t->order_ev) (void)hipEventDestroy(t->order_ev);
   for (void* q : {(void*)t->d_cum, (void*)t->d_pool, (void*)t->d_last, (void*)t->d_meta})
     if (q) (void)hipFree(q);
   delete t;
@@ -715,9 +759,12 @@ hc_err hc_insert(hc_table t, const uint32_t* d_keys, const uint32_t* d_values, u
   if ((r = set_device(t)) != HC_OK) return r;
   if (t->kind == HC_BUCKET_LIST) {
     hipStream_t s = (hipStream_t)stream;
+    CallWs ws(s);
+    if ((r = ws.get(bl_insert_workspace(n))) != HC_OK) return r;
+    if ((r = order_begin(t, s)) != HC_OK) return r;
     if ((r = next_bucket_batch(t, s)) != HC_OK) return r;
-    if ((r = ensure_ws(t, bl_insert_workspace(n))) != HC_OK) return r;
-    return launch_bl_insert(view_of(t), bview_of(t), g, t->window, d_keys, d_values, n, d_status, t->d_ws, s);
+    return order_end(t, s, launch_bl_insert(view_of(t), bview_of(t), g, t->window, d_keys, d_values, n, d_status,
+                                            ws.p, s));
   }
   return launch_insert(view_of(t), (int)t->kind, g, t->window, d_keys, d_values, n, d_status, (hipStream_t)stream);
 }
@@ -740,7 +787,7 @@ hc_err hc_retrieve(hc_table t, const uint32_t* d_keys, uint64_t n, uint32_t* d_v
     return launch_set(SET_CONTAINS, view_of(t), g, t->window, d_keys, n, d_found_out, (hipStream_t)stream);
   if (t->kind == HC_MULTI_VALUE)
     return launch_count_multi(view_of(t), g, t->window, d_keys, n, d_values_out, nullptr, d_found_out, 0xFFFFFFFFu,
-                              nullptr, nullptr, (hipStream_t)stream);
+                              nullptr, nullptr, 0, (hipStream_t)stream);
   return launch_retrieve(view_of(t), g, t->window, d_keys, n, d_values_out, d_found_out, (hipStream_t)stream);
 }
 
@@ -773,38 +820,10 @@ hc_err hc_count_values(hc_table t, const uint32_t* d_keys, uint64_t n, uint32_t*
   if (n > 0 && d_keys == nullptr) return fail(HC_E_ARG, "keys is NULL");
   if ((r = set_device(t)) != HC_OK) return r;
   hipStream_t s = (hipStream_t)stream;
-  const uint64_t ntiles = (n + SCAN_TILE - 1) / SCAN_TILE;
-  const uint64_t need = ntiles + 1;
-  if (t->tiles_cap < need) {
-    if (t->d_tiles) {
-      hipError_t e = hipStreamSynchronize(s);
-      if (e != hipSuccess) return hip_fail(e, "count_values: synchronise");
-      (void)hipFree(t->d_tiles);
-      t->d_tiles = nullptr;
-      t->tiles_cap = 0;
-    }
-    hipError_t e = hipMalloc((void**)&t->d_tiles, need * sizeof(uint64_t));
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(HC_E_NOMEM, "hipMalloc of %llu scan tiles failed", (unsigned long long)need);
-    }
-    t->tiles_cap = need;
-  }
-  if (n > 0 && t->kind == HC_BUCKET_LIST) {  // the count sits in the key's slot
-    if ((r = launch_bl_count(view_of(t), g, t->window, d_keys, n, d_counts, d_offsets, s)) != HC_OK) return r;
-  } else if (n > 0) {
-    // queries still open after LONG_BUDGET windows are finished by block-wide segment rounds
-    if ((r = ensure_ws(t, long_workspace_bytes(n, 0))) != HC_OK) return r;
-    const LongState ls = long_layout(t->d_ws, n, 0);
-    if ((r = launch_zero_u64((unsigned long long*)ls.nlong, 1, s)) != HC_OK) return r;
-    if ((r = launch_count_multi(view_of(t), g, t->window, d_keys, n, d_counts, d_offsets, nullptr, LONG_BUDGET,
-                                ls.entries, (unsigned long long*)ls.nlong, s)) != HC_OK)
-      return r;
-    if ((r = launch_long_queries(view_of(t), t->window, 0, d_keys, ls, n, LONG_BUDGET, d_offsets, d_counts, nullptr,
-                                 s)) != HC_OK)
-      return r;
-  }
-  if ((r = exclusive_scan_inplace(d_offsets, n, t->d_tiles, s)) != HC_OK) return r;
+  CallWs ws(s);
+  const uint64_t cap = t->kind == HC_MULTI_VALUE ? long_capacity(n) : 0;
+  if ((r = ws.get(count_values_ws_bytes(n, cap))) != HC_OK) return r;
+  if ((r = count_values_in(t, d_keys, n, d_counts, d_offsets, g, ws.p, cap, s)) != HC_OK) return r;
   if (h_total) {
     hipError_t e = hipMemcpyAsync(h_total, d_offsets + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -827,15 +846,17 @@ hc_err hc_retrieve_all(hc_table t, const uint32_t* d_keys, uint64_t n, const uin
   if (d_keys == nullptr || d_offsets == nullptr) return fail(HC_E_ARG, "keys or offsets is NULL");
   if ((r = set_device(t)) != HC_OK) return r;
   hipStream_t s = (hipStream_t)stream;
+  CallWs ws(s);
   if (t->kind == HC_BUCKET_LIST) {
-    if ((r = ensure_ws(t, bl_write_workspace(n))) != HC_OK) return r;
-    return launch_bl_write(view_of(t), bview_of(t), g, t->window, d_keys, n, d_offsets, d_values_out, t->d_ws, s);
+    if ((r = ws.get(bl_write_workspace(n))) != HC_OK) return r;
+    return launch_bl_write(view_of(t), bview_of(t), g, t->window, d_keys, n, d_offsets, d_values_out, ws.p, s);
   }
-  if ((r = ensure_ws(t, long_workspace_bytes(n, 1))) != HC_OK) return r;
-  const LongState ls = long_layout(t->d_ws, n, 1);
+  const uint64_t cap = long_capacity(n);
+  if ((r = ws.get(long_workspace_bytes(cap, 1))) != HC_OK) return r;
+  const LongState ls = long_layout(ws.p, cap, 1);
   if ((r = launch_zero_u64((unsigned long long*)ls.nlong, 1, s)) != HC_OK) return r;
   if ((r = launch_write_multi(view_of(t), g, t->window, d_keys, n, d_offsets, d_values_out, LONG_BUDGET, ls.entries,
-                              (unsigned long long*)ls.nlong, s)) != HC_OK)
+                              (unsigned long long*)ls.nlong, cap, s)) != HC_OK)
     return r;
   // the write rounds only read the offsets
   return launch_long_queries(view_of(t), t->window, 1, d_keys, ls, n, LONG_BUDGET, const_cast<uint64_t*>(d_offsets),
@@ -858,15 +879,19 @@ hc_err hc_insert_grouped(hc_table t, const uint32_t* d_keys, const uint32_t* d_v
   }
   if (n > 0xFFFFFFFFull) return fail(HC_E_ARG, "grouped insert takes at most 2^32-1 pairs");
   if ((r = set_device(t)) != HC_OK) return r;
+  hipStream_t s = (hipStream_t)stream;
+  CallWs ws(s);
   if (t->kind == HC_BUCKET_LIST) {
-    hipStream_t s = (hipStream_t)stream;
+    if ((r = ws.get(bl_grouped_workspace_bytes(n))) != HC_OK) return r;
+    if ((r = order_begin(t, s)) != HC_OK) return r;
     if ((r = next_bucket_batch(t, s)) != HC_OK) return r;
-    if ((r = ensure_ws(t, bl_grouped_workspace_bytes(n))) != HC_OK) return r;
-    return launch_bl_grouped(view_of(t), bview_of(t), t->group, t->window, d_keys, d_values, n, t->d_ws, s);
+    return order_end(t, s, launch_bl_grouped(view_of(t), bview_of(t), t->group, t->window, d_keys, d_values, n,
+                                             ws.p, s));
   }
-  if ((r = ensure_ws(t, grouped_workspace_bytes(n))) != HC_OK) return r;
-  return launch_grouped_insert(view_of(t), (int)t->kind, t->group, t->window, d_keys, d_values, n, t->d_ws,
-                               (hipStream_t)stream);
+  if ((r = ws.get(grouped_workspace_bytes(n))) != HC_OK) return r;
+  if ((r = order_begin(t, s)) != HC_OK) return r;
+  return order_end(t, s, launch_grouped_insert(view_of(t), (int)t->kind, t->group, t->window, d_keys, d_values, n,
+                                               ws.p, s));
 }
 
 static hc_err wide_call(hc_table t, int op, const uint64_t* keys, const uint64_t* values, uint64_t n,
@@ -950,21 +975,18 @@ hc_err hc_stats(hc_table t, hc_table_stats* h_out, void* stream) {
   if ((r = not_set(t, "hc_stats")) != HC_OK) return r;
   if (h_out == nullptr) return fail(HC_E_ARG, "out is NULL");
   static_assert(HC_PROBE_BUCKETS == STATS_BUCKETS, "histogram width");
-  static_assert(sizeof(hc_table_stats) == (5 + STATS_BUCKETS) * sizeof(uint64_t), "stats layout");
+  static_assert(sizeof(hc_table_stats) == (6 + STATS_BUCKETS) * sizeof(uint64_t), "stats layout");
   if ((r = set_device(t)) != HC_OK) return r;
   hipStream_t s = (hipStream_t)stream;
-  unsigned long long* d = nullptr;
-  hipError_t e = hipMalloc((void**)&d, sizeof(hc_table_stats));
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(HC_E_NOMEM, "hipMalloc of the statistics failed");
-  }
-  r = launch_zero_u64(d, 5 + STATS_BUCKETS, s);
-  if (r == HC_OK) r = launch_stats(view_of(t), t->window, d, s);
-  if (e == hipSuccess && r == HC_OK) e = hipMemcpyAsync(h_out, d, sizeof(hc_table_stats), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess && r == HC_OK) e = hipStreamSynchronize(s);
-  (void)hipFree(d);
-  if (r != HC_OK) return r;
+  CallWs ws(s);
+  if ((r = ws.get(sizeof(hc_table_stats))) != HC_OK) return r;
+  unsigned long long* d = static_cast<unsigned long long*>(ws.p);
+  if ((r = launch_zero_u64(d, 5 + STATS_BUCKETS, s)) != HC_OK) return r;
+  if ((r = launch_stats(view_of(t), t->window, d, s)) != HC_OK) return r;
+  hipError_t e = hipMemcpyAsync(h_out, d, (5 + STATS_BUCKETS) * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&h_out->cas_fails, t->d_size + CTR_CAS_FAILS, sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "hc_stats");
   return HC_OK;
 }
@@ -1007,20 +1029,26 @@ hc_err hc_batch_create(hc_batch* out, const hc_batch_op* ops, uint32_t count) {
   b->phases = plan.phases;
   b->launches = plan.launches;
   if (!plan.descs.empty()) {
+    const size_t cbytes = plan.launches.size() * PLAN_COUNTER_STRIDE * sizeof(unsigned long long);
     hipError_t e1 = hipMalloc((void**)&b->d_descs, plan.descs.size() * sizeof(BatchDesc));
     hipError_t e2 = e1 == hipSuccess ? hipMalloc((void**)&b->d_chunk_start, plan.cs.size() * sizeof(uint64_t)) : e1;
-    if (e1 != hipSuccess || e2 != hipSuccess) {
+    hipError_t e3 = e2 == hipSuccess ? hipMalloc((void**)&b->d_counters, cbytes) : e2;
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
       (void)hipGetLastError();
       if (b->d_descs) (void)hipFree(b->d_descs);
+      if (b->d_chunk_start) (void)hipFree(b->d_chunk_start);
       delete b;
       return fail(HC_E_NOMEM, "hipMalloc of batch descriptors failed");
     }
     hipError_t e = hipMemcpy(b->d_descs, plan.descs.data(), plan.descs.size() * sizeof(BatchDesc), hipMemcpyHostToDevice);
     if (e == hipSuccess)
       e = hipMemcpy(b->d_chunk_start, plan.cs.data(), plan.cs.size() * sizeof(uint64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemsetAsync(b->d_counters, 0, cbytes, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) {
       (void)hipFree(b->d_descs);
       (void)hipFree(b->d_chunk_start);
+      (void)hipFree(b->d_counters);
       delete b;
       return hip_fail(e, "batch descriptor upload");
     }
@@ -1037,7 +1065,7 @@ hc_err hc_batch_launch(hc_batch b, void* stream) {
     const hipError_t e = hipSetDevice(b->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   }
-  return launch_plan(b->launches, b->d_descs, b->d_chunk_start, (hipStream_t)stream);
+  return launch_plan(b->launches, b->d_descs, b->d_chunk_start, b->d_counters, (hipStream_t)stream);
 }
 
 hc_err hc_batch_info(hc_batch b, uint32_t* h_phases, uint32_t* h_launches) {
@@ -1051,6 +1079,7 @@ hc_err hc_batch_destroy(hc_batch b) {
   if (b == nullptr) return HC_OK;
   if (b->d_descs) (void)hipFree(b->d_descs);
   if (b->d_chunk_start) (void)hipFree(b->d_chunk_start);
+  if (b->d_counters) (void)hipFree(b->d_counters);
   delete b;
   return HC_OK;
 }

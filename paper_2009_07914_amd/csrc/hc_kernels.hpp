@@ -354,6 +354,7 @@ struct InsertUnique {
   Seq s{};
   bool cand = false;
   long long added = 0;
+  uint32_t fails = 0;  // failed claim CASes (Sec. IV-B2: the collisions an insert pays for)
 
   __device__ __forceinline__ void load(uint64_t op) {
     k_nx = keys[op];
@@ -379,6 +380,7 @@ struct InsertUnique {
     const uint64_t r = atomicCAS((unsigned long long*)&t.slots[idx], (unsigned long long)expect,
                                  (unsigned long long)make_slot(k, v));
     if (r == expect) { ++added; return 1; }
+    ++fails;
     if (slot_key(r) == k) { update(idx); return 2; }
     return 3;
   }
@@ -430,7 +432,10 @@ struct InsertUnique {
     ln.advance(t, s, lbase);
     return false;
   }
-  __device__ __forceinline__ void end() { wave_add_to(t.size, added); }
+  __device__ __forceinline__ void end() {
+    wave_add_to(t.size + CTR_SIZE, added);
+    wave_add_to(t.size + CTR_CAS_FAILS, fails);
+  }
 };
 
 template <int G, int W, int KIND>
@@ -461,6 +466,7 @@ struct InsertMulti {
   uint32_t k = 0, v = 0, lbase = 0, k_nx = 0, v_nx = 0;
   Seq s{};
   long long added = 0;
+  uint32_t fails = 0;  // failed claim CASes
 
   __device__ __forceinline__ void load(uint64_t op) {
     k_nx = keys[op];
@@ -492,7 +498,7 @@ struct InsertMulti {
         reuse &= reuse - 1;
         const uint64_t res = atomicCAS((unsigned long long*)&t.slots[win.first + j], (unsigned long long)expect,
                                        (unsigned long long)make_slot(k, v));
-        if (res == expect) { ok = 1; ++added; }
+        if (res == expect) { ok = 1; ++added; } else { ++fails; }
       }
       if (g.bcast(ok, r)) return done(ST_OK);
       b_reuse = g.bits(reuse != 0);
@@ -501,7 +507,10 @@ struct InsertMulti {
     ln.advance(t, s, lbase);
     return false;
   }
-  __device__ __forceinline__ void end() { wave_add_to(t.size, added); }
+  __device__ __forceinline__ void end() {
+    wave_add_to(t.size + CTR_SIZE, added);
+    wave_add_to(t.size + CTR_CAS_FAILS, fails);
+  }
 };
 
 template <int G, int W>
@@ -694,6 +703,7 @@ struct CountMulti {
   uint32_t budget = 0xFFFFFFFFu;              // windows before handing the query over
   uint64_t* __restrict__ long_list = nullptr;  // handed-over queries
   unsigned long long* long_n = nullptr;
+  uint64_t long_cap = 0;                       // entries the list holds; past them groups walk on
   uint64_t i = 0;
   uint32_t k = 0, lbase = 0, cnt = 0, k_nx = 0;
   Seq s{};
@@ -738,11 +748,17 @@ struct CountMulti {
     cnt += g.sum(popcount(win.match));
     if (g.bits(win.empty != 0) || ln.exhausted(t, lbase)) return done();
     if (lbase + L::WPS >= budget) {  // long: continued by the block-wide kernel from window `budget`
-      if (g.glane == 0) {
-        long_list[atomicAdd(long_n, 1ull)] = i;
-        offsets[i] = cnt;
+      unsigned long long j = 0;
+      if (g.glane == 0) j = atomicAdd(long_n, 1ull);
+      j = g.bcast64(j, 0);
+      if (j < long_cap) {
+        if (g.glane == 0) {
+          long_list[j] = i;
+          offsets[i] = cnt;
+        }
+        return true;
       }
-      return true;
+      budget = 0xFFFFFFFFu;  // the list is full: this group walks on by itself
     }
     ln.advance(t, s, lbase);
     return false;
@@ -754,7 +770,8 @@ template <int G, int W>
 __global__ __launch_bounds__(BLOCK) void k_count_multi(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys, uint64_t n,
                                                        uint32_t* __restrict__ counts, uint64_t* __restrict__ offsets,
                                                        uint8_t* __restrict__ found_out, uint32_t budget,
-                                                       uint64_t* __restrict__ long_list, unsigned long long* long_n) {
+                                                       uint64_t* __restrict__ long_list, unsigned long long* long_n,
+                                                       uint64_t long_cap) {
   using C = CountMulti<G, W>;
   __shared__ OutRing<C::RING> rings[BLOCK / 64];
   C op;
@@ -766,6 +783,7 @@ __global__ __launch_bounds__(BLOCK) void k_count_multi(TableView t, WorkCtl ctl,
   op.budget = budget;
   op.long_list = long_list;
   op.long_n = long_n;
+  op.long_cap = long_cap;
   drive_staged<G, C::RING>(n, ctl, op, rings[threadIdx.x >> 6]);
 }
 
@@ -785,6 +803,7 @@ struct WriteMulti {
   uint32_t budget = 0xFFFFFFFFu;
   uint64_t* __restrict__ long_list = nullptr;  // (query, values written) pairs
   unsigned long long* long_n = nullptr;
+  uint64_t long_cap = 0;                       // entries the list holds; past them groups walk on
   uint64_t i = 0, base = 0, limit = 0, written = 0, base_nx = 0, end_nx = 0;
   uint32_t k = 0, lbase = 0, k_nx = 0;
   Seq s{};
@@ -821,12 +840,17 @@ struct WriteMulti {
     written += total;
     if (written >= limit || g.bits(win.empty != 0) || ln.exhausted(t, lbase)) return true;
     if (lbase + L::WPS >= budget) {
-      if (g.glane == 0) {
-        const unsigned long long j = atomicAdd(long_n, 1ull);
-        long_list[2 * j] = i;
-        long_list[2 * j + 1] = written;
+      unsigned long long j = 0;
+      if (g.glane == 0) j = atomicAdd(long_n, 1ull);
+      j = g.bcast64(j, 0);
+      if (j < long_cap) {
+        if (g.glane == 0) {
+          long_list[2 * j] = i;
+          long_list[2 * j + 1] = written;
+        }
+        return true;
       }
-      return true;
+      budget = 0xFFFFFFFFu;  // the list is full: this group walks on by itself
     }
     ln.advance(t, s, lbase);
     return false;
@@ -838,7 +862,8 @@ template <int G, int W>
 __global__ __launch_bounds__(BLOCK) void k_write_multi(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys, uint64_t n,
                                                        const uint64_t* __restrict__ offsets,
                                                        uint32_t* __restrict__ out, uint32_t budget,
-                                                       uint64_t* __restrict__ long_list, unsigned long long* long_n) {
+                                                       uint64_t* __restrict__ long_list, unsigned long long* long_n,
+                                                       uint64_t long_cap) {
   WriteMulti<G, W> op;
   op.t = t;
   op.keys = keys;
@@ -847,6 +872,7 @@ __global__ __launch_bounds__(BLOCK) void k_write_multi(TableView t, WorkCtl ctl,
   op.budget = budget;
   op.long_list = long_list;
   op.long_n = long_n;
+  op.long_cap = long_cap;
   drive<G>(n, ctl, op);
 }
 

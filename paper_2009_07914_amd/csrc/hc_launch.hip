@@ -97,6 +97,49 @@ hc_err ensure_ring(int dev) {
   return HC_OK;
 }
 
+// Workspace pools, one per device, created on first use.
+static hipMemPool_t g_pools[64];
+static std::mutex g_pool_mu;
+
+hc_err ws_alloc(void** out, uint64_t bytes, hipStream_t s) {
+  *out = nullptr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return fail(HC_E_DEVICE, "hipGetDevice failed");
+  hipMemPool_t pool = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    if (g_pools[dev] == nullptr) {
+      hipMemPoolProps props = {};
+      props.allocType = hipMemAllocationTypePinned;
+      props.handleTypes = hipMemHandleTypeNone;
+      props.location.type = hipMemLocationTypeDevice;
+      props.location.id = dev;
+      hipError_t e = hipMemPoolCreate(&pool, &props);
+      if (e != hipSuccess) return hip_fail(e, "workspace pool: hipMemPoolCreate");
+      uint64_t keep = ~0ull;  // keep freed blocks for the next call
+      e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+      if (e != hipSuccess) {
+        (void)hipMemPoolDestroy(pool);
+        return hip_fail(e, "workspace pool: release threshold");
+      }
+      g_pools[dev] = pool;
+    }
+    pool = g_pools[dev];
+  }
+  if (bytes == 0) bytes = 256;
+  const hipError_t e = hipMallocFromPoolAsync(out, bytes, pool, s);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *out = nullptr;
+    return fail(HC_E_NOMEM, "workspace of %llu bytes: %s", (unsigned long long)bytes, hipGetErrorString(e));
+  }
+  return HC_OK;
+}
+
+void ws_release(void* p, hipStream_t s) {
+  if (p != nullptr && hipFreeAsync(p, s) != hipSuccess) (void)hipGetLastError();
+}
+
 WorkCtl work_for(uint64_t n, int G, unsigned grid) {
   int dev = 0;
   (void)hipGetDevice(&dev);

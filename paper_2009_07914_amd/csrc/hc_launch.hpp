@@ -18,6 +18,28 @@ const char* last_error_text();
 // Allocate the device's launch-slot ring (once per device; synchronises the first time).
 hc_err ensure_ring(int dev);
 
+// Per-call device workspace.  Each call that needs scratch memory takes its own
+// block from a library-owned memory pool of the current device, ordered on the
+// call's stream, and gives it back on the same stream when its last kernel is
+// enqueued; calls on different streams therefore never share a workspace, and
+// no call synchronises the device to grow or release one.  The pool keeps freed
+// blocks for reuse instead of returning them to the system.
+hc_err ws_alloc(void** out, uint64_t bytes, hipStream_t s);
+void ws_release(void* p, hipStream_t s);
+
+// A workspace held for the duration of one call (released on every return path).
+struct CallWs {
+  void* p = nullptr;
+  hipStream_t s = nullptr;
+  explicit CallWs(hipStream_t stream) : s(stream) {}
+  CallWs(const CallWs&) = delete;
+  CallWs& operator=(const CallWs&) = delete;
+  hc_err get(uint64_t bytes) { return ws_alloc(&p, bytes, s); }
+  ~CallWs() {
+    if (p) ws_release(p, s);
+  }
+};
+
 // Number of compute units of the current device (cached per device).
 int device_cu_count();
 
@@ -75,17 +97,21 @@ inline hc_err dispatch_gw(uint32_t G, uint32_t W, F&& f) {
 // Launchers, one translation unit each.
 hc_err launch_insert(const TableView& t, int kind, uint32_t G, uint32_t W, const uint32_t* keys,
                      const uint32_t* values, uint64_t n, uint8_t* status, hipStream_t stream);
+// Counting insert with the equal keys of each tile combined in LDS first (hc_k_count.hip).
+hc_err launch_count_insert(const TableView& t, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n,
+                           uint8_t* status, hipStream_t stream);
 hc_err launch_retrieve(const TableView& t, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n,
                        uint32_t* values_out, uint8_t* found_out, hipStream_t stream);
 hc_err launch_erase(const TableView& t, int kind, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n,
                     uint8_t* status, hipStream_t stream);
 // budget: windows a group scans before handing the query to the long-query kernel
-// (appending it to long_list); 0xFFFFFFFF: never.
+// (appending it to long_list, which holds long_cap entries; once it is full, groups
+// walk on by themselves); 0xFFFFFFFF: never.
 hc_err launch_count_multi(const TableView& t, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n,
                           uint32_t* counts, uint64_t* offsets, uint8_t* found_out, uint32_t budget,
-                          uint64_t* long_list, unsigned long long* long_n, hipStream_t stream);
+                          uint64_t* long_list, unsigned long long* long_n, uint64_t long_cap, hipStream_t stream);
 hc_err launch_write_multi(const TableView& t, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n,
                           const uint64_t* offsets, uint32_t* out, uint32_t budget, uint64_t* long_list,
-                          unsigned long long* long_n, hipStream_t stream);
+                          unsigned long long* long_n, uint64_t long_cap, hipStream_t stream);
 
 }  // namespace hc

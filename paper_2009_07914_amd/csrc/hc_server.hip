@@ -3,19 +3,28 @@
 // Not in the paper; built from its bulk operations (Sec. IV-B3/B4/B5) and its
 // concurrency rules (Sec. IV-D).  A worker thread owns the device side:
 //   * admission: requests are taken in arrival order while the device staging
-//     ring (the admission budget) has room for their inputs and outputs;
+//     ring (the admission budget, at most half the HBM free when the server is
+//     created) has room for their inputs and outputs;
 //   * coalescing: everything admitted at one moment becomes one launch group, a
 //     batched plan whose phases keep each table's operations in arrival order;
+//     same-kind writes of one group to one table run in one launch (one epoch):
+//     where they touch the same key, the outcome is one of the arrival orders of
+//     those writes (Sec. IV-D: concurrent same-kind operations are valid but
+//     order-dependent);
 //   * overlap: a group's input copies, kernels and output copies go to one of
 //     several streams in rotation, so the copies of one group overlap the
-//     kernels of its neighbours; kernels of consecutive groups are ordered by an
-//     event, which keeps every table's operations in arrival order across groups;
-//   * completion: a group is done when the event after its output copies fires;
-//     a request's latency is that moment minus its submission.
+//     kernels of its neighbours; a group's kernels wait (on the device) only for
+//     the unfinished earlier groups that touch one of its tables, so groups on
+//     disjoint tables also run their kernels side by side, while every table's
+//     operations keep their arrival order across groups;
+//   * completion: a group is done when the event after its output copies fires
+//     (groups may finish out of order); a request's latency is that moment minus
+//     its submission.  Staging memory is given back in admission order.
 // In serial mode every request is its own group and starts only when the previous
 // one has completed: the plain one-request-at-a-time path, for comparison.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -24,6 +33,7 @@
 #include <mutex>
 #include <new>
 #include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "hc.h"
@@ -55,7 +65,9 @@ struct Slot {  // per in-flight launch group
 struct Group {
   std::vector<uint64_t> tickets;
   uint64_t ring_end = 0;
+  uint64_t seq = 0;    // launch order
   int slot = -1;
+  bool done = false;   // its requests are complete (it may still hold staging memory)
 };
 
 constexpr uint64_t ALIGN = 256;
@@ -72,7 +84,8 @@ struct hc_server_s {
   std::vector<hipStream_t> streams;
   std::vector<Slot> slots;
   uint32_t next_stream = 0;
-  hipEvent_t last_kernel = nullptr;
+  uint64_t next_seq = 0;
+  std::unordered_map<const void*, uint64_t> table_last;  // table -> seq of the last group touching it
 
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -98,6 +111,7 @@ struct hc_server_s {
   // Reserve `bytes` contiguous ring bytes; returns the offset or UINT64_MAX if full.
   uint64_t ring_alloc(uint64_t bytes) {
     const uint64_t size = p.staging_bytes;
+    if (head == tail) head = tail = 0;  // empty: start at offset 0, so any request up to `size` fits
     uint64_t h = head;
     const uint64_t pos = h % size;
     if (pos + bytes > size) h += size - pos;  // do not wrap inside an allocation
@@ -117,13 +131,14 @@ static hc_err server_fail(hc_server_s* s, hc_err e, const char* what, hipError_t
   return e;
 }
 
-// Retire completed groups in order.  Called with the lock held.
+// Complete the groups whose work has finished, in any order; give staging memory back
+// over the prefix of finished groups (admission order).  Called with the lock held.
 bool hc_server_s::retire() {
   bool any = false;
-  while (!inflight.empty()) {
-    Group& g = inflight.front();
+  for (Group& g : inflight) {
+    if (g.done) continue;
     const hipError_t e = hipEventQuery(slots[g.slot].done);
-    if (e == hipErrorNotReady) break;
+    if (e == hipErrorNotReady) continue;
     if (e != hipSuccess) {
       server_fail(this, HC_E_DEVICE, "launch group", e);
       break;
@@ -136,10 +151,13 @@ bool hc_server_s::retire() {
       ops_done += r->r.n;
       ++completed;
     }
-    tail = g.ring_end;
+    g.done = true;
     slots[g.slot].busy = false;
-    inflight.pop_front();
     any = true;
+  }
+  while (!inflight.empty() && inflight.front().done) {
+    tail = inflight.front().ring_end;
+    inflight.pop_front();
   }
   if (any) cv_done.notify_all();
   return any;
@@ -185,7 +203,22 @@ bool hc_server_s::launch_group() {
   g.tickets = take;
   g.ring_end = head;
   g.slot = slot;
+  g.seq = next_seq++;
   hipStream_t st = streams[next_stream++ % streams.size()];
+  // per-table order: the kernels wait for the unfinished earlier groups that share a table
+  std::vector<hipEvent_t> waits;
+  for (uint64_t tk : take) {
+    const void* tab = reqs[tk]->r.table;
+    auto it = table_last.find(tab);
+    if (it != table_last.end()) {
+      for (const Group& e : inflight)
+        if (e.seq == it->second && !e.done) {
+          const hipEvent_t ev = slots[e.slot].kernel_done;
+          if (std::find(waits.begin(), waits.end(), ev) == waits.end()) waits.push_back(ev);
+        }
+    }
+    table_last[tab] = g.seq;
+  }
   ++launching;
   mu.unlock();
 
@@ -236,8 +269,9 @@ bool hc_server_s::launch_group() {
     if (he == hipSuccess)
       he = hipMemcpyAsync(sl.d_cs, sl.h_cs, plan.cs.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st);
   }
-  if (he == hipSuccess && err == HC_OK && last_kernel) he = hipStreamWaitEvent(st, last_kernel, 0);
-  if (he == hipSuccess && err == HC_OK) err = hc::launch_plan(plan.launches, sl.d_descs, sl.d_cs, st);
+  for (size_t j = 0; j < waits.size() && he == hipSuccess && err == HC_OK; ++j)
+    he = hipStreamWaitEvent(st, waits[j], 0);
+  if (he == hipSuccess && err == HC_OK) err = hc::launch_plan(plan.launches, sl.d_descs, sl.d_cs, nullptr, st);
   if (he == hipSuccess && err == HC_OK) he = hipEventRecord(sl.kernel_done, st);
   for (size_t j = 0; j < outs.size() && he == hipSuccess && err == HC_OK; ++j)
     he = hipMemcpyAsync(outs[j].dst, outs[j].src, outs[j].bytes, hipMemcpyDeviceToHost, st);
@@ -250,7 +284,6 @@ bool hc_server_s::launch_group() {
     error = err;
     error_msg = hc_last_error();
   }
-  last_kernel = sl.kernel_done;
   ++groups;
   inflight.push_back(std::move(g));
   --launching;
@@ -314,7 +347,20 @@ hc_err hc_server_create(hc_server* out, const hc_server_params* params) {
     delete s;
     return fail(HC_E_DEVICE, "hipGetDevice failed");
   }
-  hipError_t e = hipMalloc((void**)&s->d_staging, p.staging_bytes);
+  size_t free_b = 0, total_b = 0;
+  hipError_t e = hipMemGetInfo(&free_b, &total_b);
+  if (e != hipSuccess) {
+    delete s;
+    return hc::hip_fail(e, "hipMemGetInfo");
+  }
+  if (p.staging_bytes > free_b / 2) {  // the admission budget takes at most half the free HBM
+    if (free_b / 2 < (1u << 20)) {
+      delete s;
+      return fail(HC_E_NOMEM, "%llu bytes of HBM free: too little for a staging ring", (unsigned long long)free_b);
+    }
+    s->p.staging_bytes = p.staging_bytes = (free_b / 2) & ~(uint64_t)(ALIGN - 1);
+  }
+  e = hipMalloc((void**)&s->d_staging, p.staging_bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     delete s;
@@ -435,6 +481,7 @@ hc_err hc_server_stats(hc_server s, hc_server_counts* h_out) {
   h_out->launch_groups = s->groups;
   h_out->ops_completed = s->ops_done;
   h_out->staging_in_use = s->head - s->tail;
+  h_out->staging_bytes = s->p.staging_bytes;
   return HC_OK;
 }
 

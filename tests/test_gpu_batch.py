@@ -233,3 +233,112 @@ def test_every_mixed_pair_in_one_launch(hc, kind):
         torch.cuda.synchronize()
         check()
     b.close()
+
+
+def test_graph_replay_beside_eager_launches(hc):
+    """A captured plan keeps its own work counters: after more eager launches than the device's
+    launch-slot ring holds, replays of the graph on one stream run beside eager launches on another
+    and both stay exact."""
+    t1 = hc.Table("single", 1 << 17, scheme="double", window=16, group=4)
+    t2 = hc.Table("single", 1 << 16, scheme="linear", window=8, group=2)
+    w1 = gen.single_value_workload(t1.capacity, 0.9, 401)
+    w2 = gen.single_value_workload(t2.capacity, 0.8, 402)
+    k1, v1, q1 = d(w1["keys"]), d(w1["values"]), d(w1["queries"])
+    st = torch.empty(k1.numel(), dtype=torch.uint8, device="cuda")
+    vo = torch.empty(q1.numel(), dtype=torch.uint32, device="cuda")
+    fo = torch.empty(q1.numel(), dtype=torch.uint8, device="cuda")
+    b = hc.Batch([(hc.hc_batch_op(t1, hc.OP_INSERT, k1, v1, flags=st), [k1, v1, st]),
+                  (hc.hc_batch_op(t1, hc.OP_RETRIEVE, q1, values_out=vo, flags=fo), [q1, vo, fo])])
+    b.capture()
+    k2, v2, q2 = d(w2["keys"]), d(w2["values"]), d(w2["queries"])
+    t2.insert(k2, v2)
+    small = q2[:64]
+    for j in range(1100):  # wrap the launch-slot ring
+        hc.hc_retrieve(t2.handle, small, None, None, 0)
+    torch.cuda.synchronize()
+    o1 = oracle.OracleTable(oracle.SINGLE, t1.capacity)
+    st_o = o1.insert(w1["keys"], w1["values"])
+    vv1, ff1 = o1.retrieve(w1["queries"])
+    o2 = oracle.OracleTable(oracle.SINGLE, t2.capacity)
+    o2.insert(w2["keys"], w2["values"])
+    vv2, ff2 = o2.retrieve(w2["queries"])
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for rep in range(4):
+        t1.clear(stream=s1)
+        b.replay(s1)
+        outs = []
+        for j in range(300):
+            v = torch.empty(q2.numel(), dtype=torch.uint32, device="cuda")
+            f = torch.empty(q2.numel(), dtype=torch.uint8, device="cuda")
+            if j % 100 == 0:
+                hc.hc_retrieve(t2.handle, q2, v, f, 0, s2)
+                outs.append((v, f))
+            else:
+                hc.hc_retrieve(t2.handle, small, None, None, 0, s2)
+        torch.cuda.synchronize()
+        assert np.array_equal(h(st), st_o)
+        assert np.array_equal(h(vo), vv1) and np.array_equal(h(fo), ff1)
+        for v, f in outs:
+            assert np.array_equal(h(v), vv2) and np.array_equal(h(f), ff2)
+    b.close()
+
+
+def test_full_size_256_tables(hc):
+    """The 256-table workload at its full size (capacities log-uniform in [2^10, 2^24], loads in
+    [0.6, 0.95], about 4.4e8 slots): tuned layouts, one batched plan launched and its graph replayed;
+    every found flag, value and status against the inputs (keys are distinct, so a present query
+    returns the value inserted with its key), sizes exact, and the smallest tables against the oracle."""
+    from paper_2009_07914_amd import autotune
+    spec = gen.batched_tables_spec(256, 10, 24, 0.6, 0.95, 16, gen.SEED_BASE + 3)
+    tabs, data, ops = [], [], []
+    for sp in spec:
+        cfg = autotune.choose(sp["capacity"], sp["load"])
+        t = hc.Table("single", sp["capacity"], scheme=cfg["scheme"], window=cfg["window"],
+                     group=cfg["group_insert"], seed=sp["seed"])
+        w = gen.single_value_workload(sp["capacity"], sp["load"], sp["seed"])
+        k, v, q = d(w["keys"]), d(w["values"]), d(w["queries"])
+        st = torch.empty(k.numel(), dtype=torch.uint8, device="cuda")
+        vo = torch.empty(q.numel(), dtype=torch.uint32, device="cuda")
+        fo = torch.empty(q.numel(), dtype=torch.uint8, device="cuda")
+        ops.append((hc.hc_batch_op(t, hc.OP_INSERT, k, v, flags=st, group=cfg["group_insert"]), [k, v, st]))
+        data.append((t, w, st, vo, fo, [q]))
+        tabs.append((t, cfg))
+    ops += [(hc.hc_batch_op(t, hc.OP_RETRIEVE, x[5][0], values_out=x[3], flags=x[4], group=cfg["group_query"]),
+             [x[5][0], x[3], x[4]]) for (t, cfg), x in zip(tabs, data)]
+    b = hc.Batch(ops)
+    assert sum(x[1]["n"] for x in data) > 3e8
+
+    def check():
+        for t, w, st, vo, fo, _ in data:
+            assert (h(st) == hc.S_OK).all()
+            f, v = h(fo), h(vo)
+            present = w["query_src"] < w["n"]
+            assert np.array_equal(f.astype(bool), present)
+            assert np.array_equal(v[present], w["values"][w["query_src"][present].astype(np.int64)])
+            assert (v[~present] == 0).all()
+            assert t.size() == w["n"]
+
+    b.launch()
+    torch.cuda.synchronize()
+    check()
+    b.capture()
+    for rep in range(2):
+        for t, _ in tabs:
+            t.clear()
+        for _, _, st, vo, fo, _ in data:
+            st.fill_(77)
+            vo.view(torch.int32).fill_(12345)
+            fo.fill_(77)
+        b.replay()
+        torch.cuda.synchronize()
+        check()
+    small = sorted(range(len(data)), key=lambda j: data[j][0].capacity)[:8]
+    for j in small:
+        t, w, st, vo, fo, _ = data[j]
+        orc = oracle.OracleTable(oracle.SINGLE, t.capacity)
+        assert np.array_equal(h(st), orc.insert(w["keys"], w["values"]))
+        vv, ff = orc.retrieve(w["queries"])
+        assert np.array_equal(h(vo), vv) and np.array_equal(h(fo), ff)
+        check_layout(t, oracle.SINGLE)
+    b.close()

@@ -261,3 +261,53 @@ def test_grouped_many_rounds_against_grouping(hc, window):
         lo, hi = np.searchsorted(sk, q[i], "left"), np.searchsorted(sk, q[i], "right")
         assert np.array_equal(np.sort(vals[off[i]:off[i + 1]]), sv[lo:hi])
     check_layout(t, oracle.MULTI)
+
+
+@pytest.mark.parametrize("group", [1, 4, 64])
+def test_counting_statuses_per_key(hc, group):
+    """Counting inserts combine equal keys of a tile before the table: per key, exactly one occurrence
+    of a new key reports OK and the rest DUPLICATE, every occurrence of a present key DUPLICATE;
+    reserved keys INVALID_KEY; a ragged batch spanning many tiles; then an over-full batch where
+    each key either fits (counted exactly) or reports FULL at every occurrence."""
+    t = hc.Table("counting", 1 << 16, scheme="double", window=16, group=group)
+    orc = oracle.OracleTable(oracle.COUNT, t.capacity)
+    first = gen.multi_value_zipf_workload(50001, 1 << 10, 1.1, 71)["keys"]
+    t.insert(d(first), None)
+    orc.insert(first)
+    w = gen.multi_value_zipf_workload(100003, 1 << 12, 1.1, 72)
+    keys = w["keys"].copy()
+    keys[::997] = 0
+    keys[5::1499] = 0xFFFFFFFF
+    st = h(t.insert(d(keys), None, status=True))
+    st_o = orc.insert(keys)
+    assert np.array_equal(st == hc.S_INVALID_KEY, st_o == oracle.ST_INVALID_KEY)
+    present_before = set(first.tolist())
+    for k in np.unique(keys[(keys != 0) & (keys != 0xFFFFFFFF)])[:400]:
+        s = st[keys == k]
+        if int(k) in present_before:
+            assert (s == hc.S_DUPLICATE).all()
+        else:
+            assert (s == hc.S_OK).sum() == 1 and (s == hc.S_DUPLICATE).sum() == s.size - 1
+    assert (st == hc.S_OK).sum() == (st_o == oracle.ST_OK).sum()
+    v, f = t.retrieve(d(w["queries"]))
+    vo, fo = orc.retrieve(w["queries"])
+    assert np.array_equal(h(v), vo) and np.array_equal(h(f), fo) and t.size() == orc.size()
+    check_layout(t, oracle.COUNT)
+    # over-full: 3000 distinct keys (1-5 copies each, shuffled) into 1024 slots
+    t2 = hc.Table("counting", 1024, scheme="linear", window=16, group=group)
+    ks = gen.keys(73, 1, 3000)
+    mult = 1 + (np.arange(3000) % 5)
+    k2 = np.repeat(ks, mult)
+    k2 = k2[gen.permutation(74, k2.size).astype(np.int64)]
+    st2 = h(t2.insert(d(k2), None, status=True))
+    assert t2.size() == 1024
+    v2, f2 = t2.retrieve(d(ks))
+    v2, f2 = h(v2), h(f2).astype(bool)
+    assert f2.sum() == 1024 and np.array_equal(v2[f2], mult[f2].astype(np.uint32))
+    for i, k in enumerate(ks[:500]):
+        s = st2[k2 == k]
+        if f2[i]:
+            assert (s == hc.S_OK).sum() == 1 and (s == hc.S_DUPLICATE).sum() == s.size - 1
+        else:
+            assert (s == hc.S_FULL).all()
+    check_layout(t2, oracle.COUNT)

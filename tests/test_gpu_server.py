@@ -147,3 +147,169 @@ def test_server_argument_errors(hc):
     t = srv.submit(sv, hc.OP_RETRIEVE, torch.zeros(0, dtype=torch.uint32))
     assert srv.query(t)[0]
     srv.close()
+
+
+def _wait_all(srv, tickets, seconds=60.0):
+    """Poll until every ticket is done (fails instead of blocking forever)."""
+    import time
+    end = time.time() + seconds
+    while time.time() < end:
+        if all(srv.query(t)[0] for t in tickets):
+            return
+        time.sleep(0.001)
+    raise AssertionError("requests did not complete")
+
+
+def test_conflicting_writes_allowed_set(hc):
+    """Requests admitted together may write the same keys of one table (Sec. IV-D: concurrent
+    same-kind writes are valid but order-dependent).  Whatever the grouping: a key's value after the
+    inserts is one of the values written to it; of the inserts of a key absent before, exactly one
+    reports OK and the rest DUPLICATE (all DUPLICATE for a present key); of the erases of a present
+    key exactly one reports OK; counting tables count exactly; later retrieves see those results."""
+    rng = np.random.default_rng(21)
+    capA, capB = 1 << 14, 1 << 13
+    A = hc.Table("single", capA, scheme="double", window=16, group=4, seed=5)
+    B = hc.Table("counting", capB, scheme="linear", window=16, group=4, seed=6)
+    U = gen.keys(600, 1, 6000)
+    pre = U[:2000]
+    pre_v = gen.values(601, pre.size)
+    A.insert(torch.from_numpy(pre).cuda(), torch.from_numpy(pre_v).cuda())
+    B.insert(torch.from_numpy(pre).cuda(), None)
+    torch.cuda.synchronize()
+    srv = hc.Server(staging_bytes=64 << 20)
+    reqs = []  # (table, kind, keys, values, out tensors)
+    def submit(tab, op, keys, vals=None, want_vals=False):
+        k = _pinned(keys)
+        fl = torch.empty(keys.size, dtype=torch.uint8, pin_memory=True)
+        vo = torch.empty(keys.size, dtype=torch.uint32, pin_memory=True) if want_vals else None
+        v = None if vals is None else _pinned(vals)
+        tk = srv.submit(tab, op, k, v, values_out=vo, flags=fl, group=[1, 4, 16][len(reqs) % 3])
+        reqs.append((tab, op, keys, vals, vo, fl, tk))
+    for j in range(8):  # overlapping inserts (random subsets of U, so keys repeat across requests)
+        keys = U[rng.choice(U.size, 1500, replace=False)]
+        submit(A, hc.OP_INSERT, keys, gen.values(610 + j, keys.size))
+        submit(B, hc.OP_INSERT, U[rng.choice(U.size, 1200, replace=False)])
+    submit(A, hc.OP_RETRIEVE, U, want_vals=True)
+    for j in range(4):  # overlapping erases
+        submit(A, hc.OP_ERASE, U[rng.choice(U.size, 2500, replace=False)])
+    submit(A, hc.OP_RETRIEVE, U, want_vals=True)
+    submit(B, hc.OP_RETRIEVE, U, want_vals=True)
+    _wait_all(srv, [r[6] for r in reqs])
+    srv.close()
+    ins_A = [r for r in reqs if r[0] is A and r[1] == hc.OP_INSERT]
+    ins_B = [r for r in reqs if r[0] is B and r[1] == hc.OP_INSERT]
+    er_A = [r for r in reqs if r[0] is A and r[1] == hc.OP_ERASE]
+    ret_A = [r for r in reqs if r[0] is A and r[1] == hc.OP_RETRIEVE]
+    pre_set = set(pre.tolist())
+    written, ins_st = {}, {}
+    for _, _, keys, vals, _, fl, _ in ins_A:
+        for k, v, s in zip(keys.tolist(), vals.tolist(), fl.numpy().tolist()):
+            written.setdefault(k, set()).add(v)
+            ins_st.setdefault(k, []).append(s)
+    # a written key holds one of the values written to it; an untouched one its prefilled value
+    allowed = {int(k): {int(v)} for k, v in zip(pre, pre_v)}
+    allowed.update(written)
+    for k, sts in ins_st.items():
+        ok = sum(s == hc.S_OK for s in sts)
+        assert ok == (0 if k in pre_set else 1) and sum(s == hc.S_DUPLICATE for s in sts) == len(sts) - ok
+    present = set(allowed)
+    v1, f1 = ret_A[0][4].numpy(), ret_A[0][5].numpy()
+    for i, k in enumerate(U.tolist()):
+        assert bool(f1[i]) == (k in present)
+        if f1[i]:
+            assert int(v1[i]) in allowed[k]
+    er_st = {}
+    for _, _, keys, _, _, fl, _ in er_A:
+        for k, s in zip(keys.tolist(), fl.numpy().tolist()):
+            er_st.setdefault(k, []).append(s)
+    for k, sts in er_st.items():
+        ok = sum(s == hc.S_OK for s in sts)
+        assert ok == (1 if k in present else 0) and sum(s == hc.S_NOT_FOUND for s in sts) == len(sts) - ok
+    v2, f2 = ret_A[1][4].numpy(), ret_A[1][5].numpy()
+    for i, k in enumerate(U.tolist()):
+        assert bool(f2[i]) == (k in present and k not in er_st)
+        if f2[i]:
+            assert v2[i] == v1[i]  # no write in between: the epoch's value stays
+    # counting: exact counts, one OK per key new to the table
+    orc = oracle.OracleTable(oracle.COUNT, capB)
+    orc.insert(pre)
+    cst = {}
+    for _, _, keys, _, _, fl, _ in ins_B:
+        orc.insert(keys)
+        for k, s in zip(keys.tolist(), fl.numpy().tolist()):
+            cst.setdefault(k, []).append(s)
+    for k, sts in cst.items():
+        assert sum(s == hc.S_OK for s in sts) == (0 if k in pre_set else 1)
+    vb, fb = [r for r in reqs if r[0] is B and r[1] == hc.OP_RETRIEVE][0][4:6]
+    vo, fo = orc.retrieve(U)
+    assert np.array_equal(vb.numpy(), vo) and np.array_equal(fb.numpy(), fo)
+    assert A.size() == len(present - set(er_st)) and B.size() == orc.size()
+
+
+def test_ring_reuses_space_after_draining(hc):
+    """An idle staging ring starts again at offset 0: a request of almost the whole ring is admitted
+    after a smaller one left the ring's head in the middle."""
+    t = hc.Table("single", 1 << 18, scheme="double", window=16, group=4)
+    keys = gen.keys(620, 1, 200000)
+    t.insert(torch.from_numpy(keys).cuda(), torch.from_numpy(gen.values(621, keys.size)).cuda())
+    torch.cuda.synchronize()
+    srv = hc.Server(staging_bytes=1 << 20)
+    outs = []
+    for n in (60000, 110000, 30000, 115000):  # 9 bytes of staging per retrieved key
+        k = _pinned(keys[:n])
+        vo = torch.empty(n, dtype=torch.uint32, pin_memory=True)
+        fl = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+        tk = srv.submit(t, hc.OP_RETRIEVE, k, values_out=vo, flags=fl)
+        _wait_all(srv, [tk], 30.0)
+        outs.append((n, vo, fl))
+    assert srv.stats()["staging_in_use"] == 0
+    srv.close()
+    vals = gen.values(621, keys.size)
+    for n, vo, fl in outs:
+        assert fl.numpy().all() and np.array_equal(vo.numpy(), vals[:n])
+
+
+def test_groups_on_disjoint_tables_overlap(hc):
+    """Two launch groups on different tables: the second does not wait for the first on the device,
+    so a small request on table B completes while a long one on table A (absent keys in a linear
+    probing table at load 0.99: hundreds of windows per query) is still running; both results equal
+    the serial server's."""
+    A = hc.Table("single", 1 << 22, scheme="linear", window=16, group=4, seed=9)
+    B = hc.Table("single", 1 << 12, scheme="double", window=16, group=4, seed=10)
+    ka = gen.keys(630, 1, int(0.99 * A.capacity))
+    A.insert(torch.from_numpy(ka).cuda(), torch.from_numpy(gen.values(631, ka.size)).cuda())
+    kb = gen.keys(632, 1, 2000)
+    B.insert(torch.from_numpy(kb).cuda(), torch.from_numpy(gen.values(633, kb.size)).cuda())
+    torch.cuda.synchronize()
+    qa = gen.keys(630, ka.size + 1, 1 << 22)  # absent from A
+    qb = kb[:64]
+
+    def run(serial):
+        srv = hc.Server(staging_bytes=256 << 20, max_group_requests=1, serial=serial)
+        ra = (torch.empty(qa.size, dtype=torch.uint32, pin_memory=True),
+              torch.empty(qa.size, dtype=torch.uint8, pin_memory=True))
+        rb = (torch.empty(qb.size, dtype=torch.uint32, pin_memory=True),
+              torch.empty(qb.size, dtype=torch.uint8, pin_memory=True))
+        ta = srv.submit(A, hc.OP_RETRIEVE, _pinned(qa), values_out=ra[0], flags=ra[1])
+        tb = srv.submit(B, hc.OP_RETRIEVE, _pinned(qb), values_out=rb[0], flags=rb[1])
+        _wait_all(srv, [tb])
+        a_done_first = srv.query(ta)[0]
+        _wait_all(srv, [ta])
+        lat = (srv.query(ta)[1], srv.query(tb)[1])
+        srv.close()
+        return ra, rb, a_done_first, lat
+
+    ra, rb, a_first, lat = run(False)
+    sa, sb, _, _ = run(True)
+    assert not a_first and lat[1] < lat[0], (a_first, lat)
+    assert np.array_equal(ra[1].numpy(), sa[1].numpy()) and not ra[1].numpy().any()
+    assert np.array_equal(rb[0].numpy(), sb[0].numpy()) and rb[1].numpy().all()
+    assert np.array_equal(rb[0].numpy(), gen.values(633, kb.size)[:64])
+
+
+def test_staging_budget_bounded_by_free_memory(hc):
+    free, _ = torch.cuda.mem_get_info()
+    srv = hc.Server(staging_bytes=1 << 60)
+    st = srv.stats()
+    srv.close()
+    assert (1 << 20) <= st["staging_bytes"] <= free // 2 + (1 << 20)
