@@ -1,6 +1,6 @@
 // Device-side API: the bulk operations' per-element state machines, callable one
-// element at a time from user kernels (the paper's device-sided table operations,
-// used to fuse table work into a producer kernel, Sec. IV-A and Sec. VI).
+// element at a time from user kernels (the paper's device-sided interface, Sec. IV-A;
+// its use case fuses k-mer generation with multi-value inserts in one kernel, Sec. V-C).
 //
 // A table's device view comes from hc_device_view() (C ABI).  Every function is
 // called by a group: the G lanes of an aligned G-lane tile of the wavefront
@@ -16,13 +16,16 @@
 namespace hc {
 namespace dev {
 
-// Single-value (KIND_SINGLE: insert or update to `value`) or counting
-// (KIND_COUNT: count += 1) insert of `key`.  Returns the per-element status
-// (ST_OK new key, ST_DUPLICATE present, ST_FULL, ST_INVALID_KEY).
+// Insert of `key` into a single-value (KIND_SINGLE: insert, or update to `value`),
+// counting (KIND_COUNT: count += 1) or multi-value table (KIND_MULTI: store (key, value)
+// as one more pair at the first reusable position of its sequence, Sec. IV-B3).
+// Returns the per-element status (ST_OK new key / stored pair, ST_DUPLICATE present,
+// ST_FULL, ST_INVALID_KEY).
 template <int G, int W, int KIND = KIND_SINGLE>
 __device__ __forceinline__ uint8_t insert(const TableView& t, uint32_t key, uint32_t value = 0) {
-  static_assert(KIND == KIND_SINGLE || KIND == KIND_COUNT, "single-value or counting tables");
-  InsertUnique<G, W, KIND> op;
+  static_assert(KIND == KIND_SINGLE || KIND == KIND_COUNT || KIND == KIND_MULTI, "table kind");
+  using Op = std::conditional_t<KIND == KIND_MULTI, InsertMulti<G, W>, InsertUnique<G, W, KIND>>;
+  Op op;
   uint8_t st = ST_OK;
   op.t = t;
   op.keys = &key;
@@ -72,6 +75,39 @@ __device__ __forceinline__ uint8_t erase(const TableView& t, uint32_t key) {
   }
   if (op.added) atomicAdd(t.size, (unsigned long long)op.added);
   return op.ln.g.bcast(st, 0);
+}
+
+// Calls f(value, j) once for each value stored under `key`, j = 0, 1, ..., count - 1 in
+// the order of the key's slots along its window sequence (for a multi-value table every
+// pair of the key, Sec. IV-B4; for single-value and counting tables the one value or
+// count), the group's lanes calling f in parallel for the matches they hold.  Returns
+// the number of values (the same in every lane of the group).  The walk ends at the
+// first window holding an empty slot, as retrieval does: no copy of a key lies beyond
+// it.  This is the one-pass alternative to hc_count_values + hc_retrieve_all for a
+// caller that consumes the values in place (e.g. writes them at j past its own offset).
+template <int G, int W, typename F>
+__device__ __forceinline__ uint32_t for_each(const TableView& t, uint32_t key, F&& f) {
+  using L = Lane<G, W>;
+  constexpr int SPL = L::SPL;
+  if (reserved_key(key)) return 0;
+  L ln;
+  Seq s{};
+  uint32_t lbase = 0;
+  ln.start(t, key, s, lbase);
+  uint32_t n = 0;
+  for (;;) {
+    Window<SPL> win;
+    load_step<G, W>(t, ln, s, lbase, key, win);
+    const uint32_t c = popcount(win.match);
+    uint32_t j = n + ln.g.exclusive_scan(c);
+#pragma unroll
+    for (int q = 0; q < SPL; ++q)
+      if ((win.match >> q) & 1) f(slot_value(win.word[q]), j++);
+    n += ln.g.sum(c);
+    if (ln.g.bits(win.empty != 0) || ln.exhausted(t, lbase)) break;
+    ln.advance(t, s, lbase);
+  }
+  return n;
 }
 
 // Calls f(key, value) once for every stored pair, one thread per slot (value is

@@ -1,7 +1,10 @@
 // User kernels built on the device-side API (test support): a fused k-mer
 // counter (DNA read -> 2-bit k-mer codes -> counting-table inserts in one
-// kernel, the producer-kernel fusion the device API exists for), group lookups,
-// group inserts with statuses, and a for_all export of every stored pair.
+// kernel, the producer-kernel fusion the device API exists for), a fused k-mer
+// index (the same codes inserted with their read positions into a multi-value
+// table from one kernel, the shape of the paper's Sec. V-C database build), group
+// lookups, group inserts with statuses, a per-key for_each collection of values
+// and a for_all export of every stored pair.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -22,6 +25,35 @@ __global__ __launch_bounds__(BLK) void k_count_kmers(hc::TableView t, const uint
     uint32_t code = 0;
     for (uint32_t j = 0; j < k; ++j) code = (code << 2) | seq[i + j];
     hc::dev::insert<G, W, hc::KIND_COUNT>(t, code + 1u);  // groups of a wavefront may diverge here
+  }
+}
+
+// (k-mer code + 1, position) pairs into a multi-value table.
+template <int W>
+__global__ __launch_bounds__(BLK) void k_index_kmers(hc::TableView t, const uint8_t* __restrict__ seq,
+                                                     uint64_t positions, uint32_t k, uint8_t* __restrict__ status) {
+  const uint64_t groups = (uint64_t)gridDim.x * (BLK / G);
+  for (uint64_t i = (uint64_t)blockIdx.x * (BLK / G) + threadIdx.x / G; i < positions; i += groups) {
+    uint32_t code = 0;
+    for (uint32_t j = 0; j < k; ++j) code = (code << 2) | seq[i + j];
+    const uint8_t st = hc::dev::insert<G, W, hc::KIND_MULTI>(t, code + 1u, (uint32_t)i);
+    if (threadIdx.x % G == 0) status[i] = st;
+  }
+}
+
+// Every value of keys[i] written to out[offsets[i] + j] by for_each (at most
+// offsets[i+1] - offsets[i] of them); counts[i] = the number for_each reports.
+template <int W>
+__global__ __launch_bounds__(BLK) void k_collect(hc::TableView t, const uint32_t* __restrict__ keys, uint64_t n,
+                                                 const uint64_t* __restrict__ offsets, uint32_t* __restrict__ out,
+                                                 uint32_t* __restrict__ counts) {
+  const uint64_t groups = (uint64_t)gridDim.x * (BLK / G);
+  for (uint64_t i = (uint64_t)blockIdx.x * (BLK / G) + threadIdx.x / G; i < n; i += groups) {
+    const uint64_t base = offsets[i], room = offsets[i + 1] - offsets[i];
+    const uint32_t c = hc::dev::for_each<G, W>(t, keys[i], [&](uint32_t v, uint32_t j) {
+      if (j < room) out[base + j] = v;
+    });
+    if (threadIdx.x % G == 0) counts[i] = c;
   }
 }
 
@@ -78,6 +110,25 @@ int devapi_count_kmers(const void* view, uint32_t window, const uint8_t* d_seq, 
   const uint64_t positions = len - k + 1;
   hipLaunchKernelGGL(k_count_kmers<16>, dim3(grid_of(positions)), dim3(BLK), 0, (hipStream_t)stream, t, d_seq,
                      positions, k);
+  return hipGetLastError() == hipSuccess ? 0 : 2;
+}
+
+int devapi_index_kmers(const void* view, uint32_t window, const uint8_t* d_seq, uint64_t len, uint32_t k,
+                       uint8_t* d_status, void* stream) {
+  if (window != 16 || k == 0 || k > 15 || len < k) return 1;
+  const hc::TableView t = *static_cast<const hc::TableView*>(view);
+  const uint64_t positions = len - k + 1;
+  hipLaunchKernelGGL(k_index_kmers<16>, dim3(grid_of(positions)), dim3(BLK), 0, (hipStream_t)stream, t, d_seq,
+                     positions, k, d_status);
+  return hipGetLastError() == hipSuccess ? 0 : 2;
+}
+
+int devapi_collect(const void* view, uint32_t window, const uint32_t* d_keys, uint64_t n, const uint64_t* d_offsets,
+                   uint32_t* d_out, uint32_t* d_counts, void* stream) {
+  if (window != 16) return 1;
+  const hc::TableView t = *static_cast<const hc::TableView*>(view);
+  hipLaunchKernelGGL(k_collect<16>, dim3(grid_of(n)), dim3(BLK), 0, (hipStream_t)stream, t, d_keys, n, d_offsets,
+                     d_out, d_counts);
   return hipGetLastError() == hipSuccess ? 0 : 2;
 }
 

@@ -2,7 +2,9 @@
 
 The kernels live in tests/devapi/devapi_kernels.hip (built by __graft_entry__.build()): a fused
 k-mer counter that turns a DNA read into 2-bit k-mer codes and counts them in a counting table
-from inside one kernel, group lookups, group inserts and a for_all export.
+from inside one kernel, a fused k-mer index that inserts (k-mer, position) pairs into a
+multi-value table from one kernel (the paper's device-sided database build, Sec. V-C), group
+lookups, group inserts, a per-key for_each collection of values and a for_all export.
 """
 import ctypes
 import os
@@ -31,6 +33,8 @@ def dev():
     lib.devapi_lookup.argtypes = [P, ctypes.c_uint32, P, ctypes.c_uint64, P, P, P]
     lib.devapi_insert.argtypes = [P, ctypes.c_uint32, P, P, ctypes.c_uint64, P, P]
     lib.devapi_export.argtypes = [P, ctypes.c_uint32, P, P, P, P]
+    lib.devapi_index_kmers.argtypes = [P, ctypes.c_uint32, P, ctypes.c_uint64, ctypes.c_uint32, P, P]
+    lib.devapi_collect.argtypes = [P, ctypes.c_uint32, P, ctypes.c_uint64, P, P, P, P]
     return lib
 
 
@@ -94,3 +98,71 @@ def test_device_insert_lookup_export(hc, dev):
     vo2, fo2 = orc.retrieve(ek[order])
     assert np.all(fo2 == 1) and np.array_equal(vo2, ev[order])
     check_layout(t, oracle.SINGLE)
+
+
+def _kmer_codes(seq, k):
+    w = np.lib.stride_tricks.sliding_window_view(seq.astype(np.uint64), k)
+    return (w * (4 ** np.arange(k - 1, -1, -1, dtype=np.uint64))).sum(axis=1).astype(np.uint32)
+
+
+@pytest.mark.parametrize("k", [4, 9, 15])
+def test_fused_kmer_index_multi_value(hc, dev, k):
+    """One kernel turns a read into k-mer codes and inserts (code + 1, position) into a multi-value
+    table through dev::insert; a second user kernel collects every k-mer's positions with
+    dev::for_each.  Both against the oracle's multimap (segments compared sorted)."""
+    n = 150000
+    seq = (gen.values(500 + k, n) & 3).astype(np.uint8)
+    t = hc.Table("multi", 1 << 18, scheme="double", window=16, group=4)
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    dseq = d(seq)
+    st = torch.empty(n - k + 1, dtype=torch.uint8, device="cuda")
+    assert dev.devapi_index_kmers(_view(hc, dev, t), 16, dseq.data_ptr(), n, k, st.data_ptr(), s) == 0
+    torch.cuda.synchronize()
+    keys = _kmer_codes(seq, k) + 1
+    pos = np.arange(keys.size, dtype=np.uint32)
+    orc = oracle.OracleTable(oracle.MULTI, t.capacity)
+    assert np.array_equal(h(st), orc.insert(keys, pos))
+    assert t.size() == orc.size() == keys.size
+    check_layout(t, oracle.MULTI)
+    q = np.concatenate([np.unique(keys), np.array([0, 0xFFFFFFFF], np.uint32),
+                        np.setdiff1d(np.arange(1, 4 ** min(k, 12) + 1, 97, dtype=np.uint32), keys)[:500]])
+    co, oo = orc.count_values(q)
+    _, vo = orc.retrieve_all(q, oo)
+    seg = np.repeat(np.arange(q.size), co.astype(np.int64))
+    # bulk two-pass retrieval of the same table
+    counts, offsets, total = t.count_values(d(q))
+    assert np.array_equal(h(counts), co) and np.array_equal(h(offsets), oo)
+    _, vals = t.retrieve_all(d(q))
+    vals = h(vals)
+    assert np.array_equal(vals[np.lexsort((vals, seg))], vo)
+    # one-pass for_each into the same segments
+    out = torch.zeros(max(int(oo[-1]), 1), dtype=torch.uint32, device="cuda")
+    cnt = torch.empty(q.size, dtype=torch.uint32, device="cuda")
+    dq, doff = d(q), d(oo)
+    assert dev.devapi_collect(_view(hc, dev, t), 16, dq.data_ptr(), q.size, doff.data_ptr(), out.data_ptr(),
+                              cnt.data_ptr(), s) == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(h(cnt), co)
+    o = h(out)[: int(oo[-1])]
+    assert np.array_equal(o[np.lexsort((o, seg))], vo)
+
+
+def test_for_each_single_value(hc, dev):
+    """for_each on a single-value table yields the key's one value (count 1) or nothing."""
+    w = gen.single_value_workload(1 << 15, 0.9, 23)
+    t = hc.Table("single", 1 << 15, scheme="linear", window=16, group=4)
+    t.insert(d(w["keys"]), d(w["values"]))
+    orc = oracle.OracleTable(oracle.SINGLE, t.capacity)
+    orc.insert(w["keys"], w["values"])
+    q = w["queries"]
+    vo, fo = orc.retrieve(q)
+    offsets = np.arange(q.size + 1, dtype=np.uint64)
+    out = torch.zeros(q.size, dtype=torch.uint32, device="cuda")
+    cnt = torch.empty(q.size, dtype=torch.uint32, device="cuda")
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    dq, doff = d(q), d(offsets)
+    assert dev.devapi_collect(_view(hc, dev, t), 16, dq.data_ptr(), q.size, doff.data_ptr(), out.data_ptr(),
+                              cnt.data_ptr(), s) == 0
+    torch.cuda.synchronize()
+    assert np.array_equal(h(cnt), fo.astype(np.uint32))
+    assert np.array_equal(h(out)[fo == 1], vo[fo == 1])
