@@ -90,6 +90,33 @@ def _traffic(kernel: str, workload: str):
     return rec.get("bytes_per_launch")
 
 
+def _host_cpus():
+    """(model name, logical CPUs of the host, CPUs this process may use): the affinity mask, further
+    limited by a cgroup CPU quota where one is set."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0))
+    try:
+        quota, period = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if quota != "max":
+            usable = max(1, min(usable, int(int(quota) // int(period))))
+    except (OSError, ValueError):
+        pass
+    return model, os.cpu_count() or 1, usable
+
+
+def _measured_frac(traffic_bytes, ms):
+    if not traffic_bytes:
+        return None
+    return round(traffic_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+
+
 def _cpu_baseline(w, log2n: int):
     """The oracle as it stands, single thread, on a bounded sample of the same workload."""
     import numpy as np
@@ -105,7 +132,9 @@ def _cpu_baseline(w, log2n: int):
     t.retrieve(q)
     t2 = time.perf_counter()
     ops = keys.size + q.size
+    model, nproc, usable = _host_cpus()
     return {"value": round(ops / (t2 - t0) / 1e9, 6), "unit": "G ops/s", "cores": 1, "kind": "oracle",
+            "cpu_model": model, "nproc": nproc, "cpus_usable": usable,
             "sample": f"first 2^{log2n} keys inserted, then 2^{log2n + 1} queries (50/50 present/absent) "
                       f"of the same workload; insert {keys.size / (t1 - t0) / 1e6:.2f} M/s, "
                       f"retrieve {q.size / (t2 - t1) / 1e6:.2f} M/s, {t2 - t0:.1f} s"}
@@ -120,7 +149,7 @@ def _cpu_multicore(w, log2n: int):
     import numpy as np
     import oracle
 
-    threads = max(1, min(len(os.sched_getaffinity(0)), 16))
+    model, nproc, threads = _host_cpus()  # every CPU this process may use
     m = 1 << log2n
     keys, vals = w["keys"][:m], w["values"][:m]
     q = np.concatenate([keys, w["absent"][:m]])
@@ -142,6 +171,7 @@ def _cpu_multicore(w, log2n: int):
     tr = phase(lambda j: tables[j].retrieve(parts[j][2]))
     ops = keys.size + q.size
     return {"value": round(ops / (ti + tr) / 1e9, 6), "unit": "G ops/s", "threads": threads,
+            "cpu_model": model, "nproc": nproc,
             "kind": "oracle sharded by key hash, one table per thread",
             "sample": f"the single-core sample; insert {keys.size / ti / 1e6:.2f} M/s, "
                       f"retrieve {q.size / tr / 1e6:.2f} M/s"}
@@ -265,6 +295,11 @@ def main():
         "retrieve_ms": {"mean": round(ret_avg, 4), "p50": round(pct(ret_ms, 50), 4), "p99": round(pct(ret_ms, 99), 4)},
         "insert_hbm_frac": round(ins_gbs / HBM_PEAK_GBS, 4),
         "retrieve_hbm_frac": round(ret_gbs / HBM_PEAK_GBS, 4),
+        # counter-measured DRAM bytes (FETCH_SIZE + WRITE_SIZE of the committed counter runs, when they
+        # describe the current kernels) over the same kernel times: the model charges a whole 128-byte
+        # line written back per claim, the memory system writes back the dirty 64-byte half
+        "insert_hbm_frac_measured": _measured_frac(_traffic(KERNEL_NAMES["insert"], workload), ins_avg),
+        "retrieve_hbm_frac_measured": _measured_frac(_traffic(KERNEL_NAMES["retrieve"], workload), ret_avg),
         "roofline": {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": round(dom_gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
                      "traffic": tr},

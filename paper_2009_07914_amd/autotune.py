@@ -11,9 +11,10 @@ measured table ships with the package as ``tuning.json``.
 Each grid point is measured on enough elements (``elements``, spread over up to
 ``max_tables`` tables) that the launches run at steady throughput: with a few
 million elements a launch is dominated by its start and its slowest groups, and
-the winners there lose in large mixed batches.  Every (g, W) pair the tuner may
-pick belongs to the batched launcher's mixed-launch set, so tables tuned to
-different pairs still share one launch per phase and operation kind.
+the winners there lose in large mixed batches.  The candidates cover the three
+outer probing schemes and every group size with g <= W and at most 8 slots per
+lane; the (g, W) pairs of the batched launcher's mixed-launch set let tables tuned
+to different pairs share one launch per phase and operation kind.
 """
 from __future__ import annotations
 
@@ -47,10 +48,15 @@ def choose(capacity: int, load: float) -> dict:
     return {k: best[k] for k in ("scheme", "window", "group_insert", "group_query")}
 
 
-def tune(log2_capacities=(10, 13, 16, 19, 22, 24), loads=(0.6, 0.8, 0.95), schemes=("linear", "double"),
-         windows=(8, 16, 32), groups=(1, 2, 4, 8, 16), elements=1 << 25, max_tables=1024, reps=3,
+def tune(log2_capacities=(10, 13, 16, 19, 22, 24), loads=(0.6, 0.8, 0.95), schemes=("linear", "quadratic", "double"),
+         windows=(8, 16, 32, 64), groups=(1, 2, 4, 8, 16, 32, 64), elements=1 << 25, max_tables=1024, reps=3,
          out_path=TUNING_PATH, log=print):
-    """Measure every candidate on the current GPU and write the winners to `out_path`."""
+    """Measure every candidate on the current GPU and write the winners to `out_path`.
+
+    Candidates: every scheme x W x g with g <= W and at most 8 slots per lane (the register budget of
+    the probing kernels), which includes the wide groups g = 32, 64 on W = 32, 64.  A pair outside the
+    batched launcher's mixed-launch set still runs correctly but takes a launch of its own in a batch
+    of differently tuned tables."""
     import torch
 
     import gen

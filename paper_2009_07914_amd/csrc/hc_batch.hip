@@ -14,8 +14,11 @@
 
 namespace hc {
 
+// Per-wavefront LDS ring of the batched retrieve's outputs (see drive_range_staged).
+using BatchRing = OutRing<128, uint32_t>;
+
 template <uint32_t OP, int G, int W>
-__device__ __forceinline__ void run_chunk(const BatchDesc& d, uint64_t begin, uint64_t end) {
+__device__ __forceinline__ void run_chunk(const BatchDesc& d, uint64_t begin, uint64_t end, BatchRing* ring) {
   if constexpr (OP == BATCH_INSERT) {
     InsertUnique<G, W, KIND_SINGLE> op;
     op.t = d.t;
@@ -36,7 +39,7 @@ __device__ __forceinline__ void run_chunk(const BatchDesc& d, uint64_t begin, ui
     op.keys = d.keys;
     op.values_out = d.values_out;
     op.found_out = d.flags;
-    drive_range<G>(begin, end, op);
+    drive_range_staged<G, Retrieve<G, W>::RING>(begin, end, op, *ring);
   } else {
     Erase<G, W, KIND_SINGLE> op;
     op.t = d.t;
@@ -90,8 +93,10 @@ template <uint32_t OP, int G, int W>
 __global__ __launch_bounds__(BLOCK) void k_batch(const BatchDesc* __restrict__ descs,
                                                  const uint64_t* __restrict__ chunk_start, uint32_t ndesc,
                                                  WorkCtl ctl) {
+  __shared__ BatchRing rings[OP == BATCH_RETRIEVE ? BLOCK / 64 : 1];
+  BatchRing* ring = &rings[OP == BATCH_RETRIEVE ? (threadIdx.x >> 6) : 0];
   take_chunks(descs, chunk_start, ndesc, ctl,
-              [](const BatchDesc& d, uint64_t begin, uint64_t end) { run_chunk<OP, G, W>(d, begin, end); });
+              [ring](const BatchDesc& d, uint64_t begin, uint64_t end) { run_chunk<OP, G, W>(d, begin, end, ring); });
 }
 
 // Mixed launch: each chunk runs with its descriptor's (G, W) pair, so tables
@@ -102,19 +107,21 @@ template <uint32_t OP>
 __global__ __launch_bounds__(BLOCK) void k_batch_mixed(const BatchDesc* __restrict__ descs,
                                                        const uint64_t* __restrict__ chunk_start, uint32_t ndesc,
                                                        WorkCtl ctl) {
-  take_chunks(descs, chunk_start, ndesc, ctl, [](const BatchDesc& d, uint64_t begin, uint64_t end) {
+  __shared__ BatchRing rings[OP == BATCH_RETRIEVE ? BLOCK / 64 : 1];
+  BatchRing* ring = &rings[OP == BATCH_RETRIEVE ? (threadIdx.x >> 6) : 0];
+  take_chunks(descs, chunk_start, ndesc, ctl, [ring](const BatchDesc& d, uint64_t begin, uint64_t end) {
     switch (d.variant) {
-      case 0: run_chunk<OP, 1, 8>(d, begin, end); break;
-      case 1: run_chunk<OP, 2, 8>(d, begin, end); break;
-      case 2: run_chunk<OP, 4, 8>(d, begin, end); break;
-      case 3: run_chunk<OP, 8, 8>(d, begin, end); break;
-      case 4: run_chunk<OP, 2, 16>(d, begin, end); break;
-      case 5: run_chunk<OP, 4, 16>(d, begin, end); break;
-      case 6: run_chunk<OP, 8, 16>(d, begin, end); break;
-      case 7: run_chunk<OP, 16, 16>(d, begin, end); break;
-      case 8: run_chunk<OP, 4, 32>(d, begin, end); break;
-      case 9: run_chunk<OP, 8, 32>(d, begin, end); break;
-      case 10: run_chunk<OP, 16, 32>(d, begin, end); break;
+      case 0: run_chunk<OP, 1, 8>(d, begin, end, ring); break;
+      case 1: run_chunk<OP, 2, 8>(d, begin, end, ring); break;
+      case 2: run_chunk<OP, 4, 8>(d, begin, end, ring); break;
+      case 3: run_chunk<OP, 8, 8>(d, begin, end, ring); break;
+      case 4: run_chunk<OP, 2, 16>(d, begin, end, ring); break;
+      case 5: run_chunk<OP, 4, 16>(d, begin, end, ring); break;
+      case 6: run_chunk<OP, 8, 16>(d, begin, end, ring); break;
+      case 7: run_chunk<OP, 16, 16>(d, begin, end, ring); break;
+      case 8: run_chunk<OP, 4, 32>(d, begin, end, ring); break;
+      case 9: run_chunk<OP, 8, 32>(d, begin, end, ring); break;
+      case 10: run_chunk<OP, 16, 32>(d, begin, end, ring); break;
       default: break;  // the planner puts no other pair into a mixed launch
     }
   });

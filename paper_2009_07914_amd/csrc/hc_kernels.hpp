@@ -336,6 +336,81 @@ __device__ __forceinline__ void drive_staged(uint64_t n, const WorkCtl& ctl, Op&
   }
 }
 
+// drive_range() with the outputs staged as in drive_staged(): the elements of the
+// chunk [begin, end) are numbered in hand-out order from 0, results go to the
+// wavefront's LDS ring, and every 64 consecutive finished results leave as whole
+// lines; the ring is empty again when the call returns.
+template <int G, int RB, typename Op, typename V>
+__device__ __forceinline__ void drive_range_staged(uint64_t begin, uint64_t end, Op& op, OutRing<RB, V>& ring) {
+  static_assert(RB % 64 == 0 && RB >= 128, "ring of whole 64-entry blocks, at least two");
+  const GroupCtx<G>& g = op.ln.g;
+  uint64_t pos = begin;  // next element to hand out (wavefront-uniform)
+  uint64_t hcount = 0;   // elements handed out
+  uint64_t flushed = 0;  // ring entries below this are written back (multiple of 64)
+#pragma unroll
+  for (int j = 0; j < RB / 64; ++j) ring.done[j * 64 + g.lane] = 0;
+  auto write_back = [&](bool only_full) -> bool {
+    const uint64_t e = flushed + g.lane;
+    const uint32_t r = (uint32_t)(e % RB);
+    const bool handed = e < hcount;
+    const uint8_t st = handed ? ring.done[r] : (uint8_t)0;
+    if (only_full && (flushed + 64 > hcount || __ballot(st != 0) != ~0ull)) return false;
+    if (st == 1) op.write_out(ring.idx[r], ring.val[r], ring.found[r]);
+    if (handed) ring.done[r] = 0;
+    flushed += 64;
+    op.flushed = flushed;
+    return true;
+  };
+  auto reserve = [&](bool want_group, uint64_t& seq_out) -> uint64_t {
+    const uint64_t want = __ballot(want_group && g.glane == 0);
+    if (want == 0) return ~0ull;
+    const uint32_t cnt = (uint32_t)__popcll(want);
+    const uint32_t rank = (uint32_t)__popcll(want & ((1ull << g.lane) - 1ull));
+    while (hcount + cnt > flushed + RB) write_back(false);
+    const uint64_t idx = pos + rank;
+    pos += cnt;
+    if ((want >> g.lane) & 1ull) {
+      const uint32_t r = (uint32_t)((hcount + rank) % RB);
+      ring.idx[r] = idx;
+      ring.done[r] = idx < end ? 0 : 2;
+    }
+    seq_out = g.bcast64(hcount + rank, 0);
+    hcount += cnt;
+    return g.bcast64(idx, 0);
+  };
+  op.ring_val = ring.val;
+  op.ring_found = ring.found;
+  op.ring_done = ring.done;
+  op.flushed = 0;
+  uint64_t seq_next = 0;
+  uint64_t i_next = reserve(true, seq_next);
+  bool has_next = i_next < end;
+  if (has_next) op.load(i_next);
+  bool active = false;
+  for (;;) {
+    const bool start = !active && has_next;
+    if (start) {
+      op.seq = seq_next;
+      op.begin(i_next);
+      active = true;
+    }
+    uint64_t sq = 0;
+    const uint64_t r = reserve(start, sq);
+    if (start) {
+      i_next = r;
+      seq_next = sq;
+      has_next = r < end;
+      if (has_next) op.load(r);
+    }
+    if (__ballot(active) == 0) break;
+    if (active && op.step()) active = false;
+    while (write_back(true)) {
+    }
+  }
+  while (flushed < hcount) write_back(false);
+  op.end();
+}
+
 // ------------------------------------------------------------------------------
 // Single-value and counting insert (Sec. IV-B2 steps 1-7; Sec. IV-B3).
 // ------------------------------------------------------------------------------
