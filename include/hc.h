@@ -325,6 +325,18 @@ hc_err hc_erase(hc_table table, const uint32_t* d_keys, uint64_t n, uint8_t* d_s
 hc_err hc_count_values(hc_table table, const uint32_t* d_keys, uint64_t n, uint32_t* d_counts,
                        uint64_t* d_offsets, uint64_t* h_total, uint32_t group, void* stream);
 
+/* hc_count_values for callers that cannot allocate device memory (code being captured into a
+ * HIP graph, serving loops and harnesses that forbid allocation): the same arguments, results
+ * and errors, but the scratch memory (scan tile sums, long-query list) is a fixed 16 MiB array
+ * of the library on each GPU, held until the process ends, and the call allocates nothing.
+ * Limits: n <= 2^28 (HC_E_ARG beyond); the long-query list holds min(n/16 + 1024, about
+ * 490,000) entries, past which groups walk on by themselves (results are the same).  Every
+ * call on one GPU shares that GPU's array: calls that overlap on one GPU (other streams, other
+ * host threads) race and must be serialised by the caller.  The first call on a device looks
+ * the array's address up once (no allocation). */
+hc_err hc_count_values_noalloc(hc_table table, const uint32_t* d_keys, uint64_t n, uint32_t* d_counts,
+                               uint64_t* d_offsets, uint64_t* h_total, uint32_t group, void* stream);
+
 /* Multi-value pass 2 (Sec. IV-B4): writes the values of d_keys[i] to
  * d_values_out[d_offsets[i] .. d_offsets[i+1]); the order inside a segment is unspecified.
  * d_offsets must come from hc_count_values on the same keys with no write call in between;

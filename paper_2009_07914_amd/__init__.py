@@ -133,6 +133,7 @@ _SIGS = {
     "hc_retrieve": ([_p, _p, _u64, _p, _p, _u32, _p], ctypes.c_int),
     "hc_erase": ([_p, _p, _u64, _p, _u32, _p], ctypes.c_int),
     "hc_count_values": ([_p, _p, _u64, _p, _p, ctypes.POINTER(_u64), _u32, _p], ctypes.c_int),
+    "hc_count_values_noalloc": ([_p, _p, _u64, _p, _p, ctypes.POINTER(_u64), _u32, _p], ctypes.c_int),
     "hc_retrieve_all": ([_p, _p, _u64, _p, _p, _u32, _p], ctypes.c_int),
     "hc_insert_grouped": ([_p, _p, _p, _u64, _p], ctypes.c_int),
     "hc_size": ([_p, ctypes.POINTER(_u64), _p], ctypes.c_int),
@@ -331,6 +332,18 @@ def hc_count_values(h: int, keys, offsets, counts=None, want_total: bool = False
                                       torch.uint64, "offsets", n + 1),
                                 ctypes.byref(tot) if want_total else None, group, _stream(stream)),
            "hc_count_values")
+    return int(tot.value) if want_total else None
+
+
+def hc_count_values_noalloc(h: int, keys, offsets, counts=None, want_total: bool = False, group: int = 0,
+                            stream=None):
+    n = keys.numel()
+    tot = ctypes.c_uint64(0)
+    _check(_lib.hc_count_values_noalloc(h, _u32t(keys, "keys"), n, _u32t(counts, "counts", n),
+                                        _dptr(offsets.view(torch.uint64) if offsets.dtype == torch.int64 else offsets,
+                                              torch.uint64, "offsets", n + 1),
+                                        ctypes.byref(tot) if want_total else None, group, _stream(stream)),
+           "hc_count_values_noalloc")
     return int(tot.value) if want_total else None
 
 

@@ -806,30 +806,78 @@ hc_err hc_erase(hc_table t, const uint32_t* d_keys, uint64_t n, uint8_t* d_statu
   return launch_erase(view_of(t), (int)t->kind, g, t->window, d_keys, n, d_status, (hipStream_t)stream);
 }
 
-hc_err hc_count_values(hc_table t, const uint32_t* d_keys, uint64_t n, uint32_t* d_counts, uint64_t* d_offsets,
-                       uint64_t* h_total, uint32_t group, void* stream) {
+// Argument checks shared by hc_count_values and hc_count_values_noalloc.
+static hc_err count_values_args(hc_table t, const uint32_t* d_keys, uint64_t n, uint64_t* d_offsets, uint32_t group,
+                                uint32_t* g) {
   hc_err r = check_table(t);
   if (r != HC_OK) return r;
   if ((r = not_wide(t, "hc_count_values")) != HC_OK) return r;
   if ((r = not_set(t, "hc_count_values")) != HC_OK) return r;
   if (t->kind != HC_MULTI_VALUE && t->kind != HC_BUCKET_LIST)
     return fail(HC_E_KIND, "count_values needs a multi-value or bucket list table");
-  uint32_t g;
-  if ((r = resolve_group(t, group, &g)) != HC_OK) return r;
+  if ((r = resolve_group(t, group, g)) != HC_OK) return r;
   if (d_offsets == nullptr) return fail(HC_E_ARG, "offsets is NULL");
   if (n > 0 && d_keys == nullptr) return fail(HC_E_ARG, "keys is NULL");
-  if ((r = set_device(t)) != HC_OK) return r;
+  return set_device(t);
+}
+
+static hc_err count_values_total(const uint64_t* d_offsets, uint64_t n, uint64_t* h_total, hipStream_t s) {
+  if (h_total == nullptr) return HC_OK;
+  hipError_t e = hipMemcpyAsync(h_total, d_offsets + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "count_values: total");
+  return HC_OK;
+}
+
+}  // extern "C"
+
+namespace hc {
+
+hc_err table_device(hc_table t, int* dev) {
+  if (t == nullptr) return fail(HC_E_ARG, "table handle is NULL");
+  *dev = t->device;
+  return HC_OK;
+}
+
+hc_err count_values_into(hc_table t, const uint32_t* d_keys, uint64_t n, uint32_t* d_counts, uint64_t* d_offsets,
+                         uint64_t* h_total, uint32_t group, void* ws, uint64_t ws_bytes, void* stream) {
+  uint32_t g;
+  hc_err r = count_values_args(t, d_keys, n, d_offsets, group, &g);
+  if (r != HC_OK) return r;
+  if (ws == nullptr || (reinterpret_cast<uintptr_t>(ws) & 255) != 0)
+    return fail(HC_E_ARG, "workspace is NULL or not 256-byte aligned");
+  const uint64_t tiles = count_values_ws_bytes(n, 0);
+  if (tiles > ws_bytes)
+    return fail(HC_E_ARG, "%llu queries need %llu workspace bytes for the scan, %llu given", (unsigned long long)n,
+                (unsigned long long)tiles, (unsigned long long)ws_bytes);
+  uint64_t cap = 0;
+  if (t->kind == HC_MULTI_VALUE && n > 0) {
+    cap = long_capacity(n);
+    const uint64_t fit = (ws_bytes - tiles) > 2048 ? (ws_bytes - tiles - 2048) / 32 : 0;
+    if (cap > fit) cap = fit;
+    while (cap > 0 && count_values_ws_bytes(n, cap) > ws_bytes) --cap;
+    if (cap == 0) return fail(HC_E_ARG, "workspace of %llu bytes holds no long-query entry", (unsigned long long)ws_bytes);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if ((r = count_values_in(t, d_keys, n, d_counts, d_offsets, g, ws, cap, s)) != HC_OK) return r;
+  return count_values_total(d_offsets, n, h_total, s);
+}
+
+}  // namespace hc
+
+extern "C" {
+
+hc_err hc_count_values(hc_table t, const uint32_t* d_keys, uint64_t n, uint32_t* d_counts, uint64_t* d_offsets,
+                       uint64_t* h_total, uint32_t group, void* stream) {
+  uint32_t g;
+  hc_err r = count_values_args(t, d_keys, n, d_offsets, group, &g);
+  if (r != HC_OK) return r;
   hipStream_t s = (hipStream_t)stream;
   CallWs ws(s);
   const uint64_t cap = t->kind == HC_MULTI_VALUE ? long_capacity(n) : 0;
   if ((r = ws.get(count_values_ws_bytes(n, cap))) != HC_OK) return r;
   if ((r = count_values_in(t, d_keys, n, d_counts, d_offsets, g, ws.p, cap, s)) != HC_OK) return r;
-  if (h_total) {
-    hipError_t e = hipMemcpyAsync(h_total, d_offsets + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "count_values: total");
-  }
-  return HC_OK;
+  return count_values_total(d_offsets, n, h_total, s);
 }
 
 hc_err hc_retrieve_all(hc_table t, const uint32_t* d_keys, uint64_t n, const uint64_t* d_offsets,

@@ -40,6 +40,15 @@ struct CallWs {
   }
 };
 
+// The device a table lives on.
+hc_err table_device(hc_table t, int* dev);
+
+// hc_count_values in a caller-given workspace (256-byte aligned, ws_bytes long): the scan's
+// tile sums, then a long-query list of as many entries as fit (at most n/16 + 1024).
+// HC_E_ARG if the tile sums or a single list entry do not fit.
+hc_err count_values_into(hc_table t, const uint32_t* d_keys, uint64_t n, uint32_t* d_counts, uint64_t* d_offsets,
+                         uint64_t* h_total, uint32_t group, void* ws, uint64_t ws_bytes, void* stream);
+
 // Number of compute units of the current device (cached per device).
 int device_cu_count();
 
