@@ -244,11 +244,13 @@ hc_err hc_diag_gather(const void* d_base, uint64_t bytes, uint32_t line_bytes, u
 /* ---- bucket list tables (Sec. IV-C) ------------------------------------------------
  * A multi-value table that stores each distinct key once: the key's slot in a
  * cooperative-probing table holds its number of values, and the values live in a list of
- * buckets taken from one preallocated pool.  Bucket i holds s_i values: s_0 = s0,
+ * buckets in one preallocated pool.  Bucket i holds s_i values: s_0 = s0,
  * s_i = min(ceil(growth * s_{i-1}), smax) (the paper's growth rule, capped); every bucket
- * but the first begins with the pool offset of the bucket before it.  A key's values sit in
- * its list in insertion-ticket order.  Pool memory of erased keys is not reused before
- * hc_clear.
+ * but the first begins with the pool offset of the bucket before it.  The first bucket of the
+ * key in slot p is the s0 pool words at p * s0 (the first C * s0 pool words are reserved for
+ * them); later buckets are allocated from the rest.  A key's values sit in its list in
+ * insertion-ticket order.  Pool memory of erased keys' later buckets is not reused before
+ * hc_clear (a first bucket is reused with its slot).
  *   hc_insert: pairs as for a multi-value table (status OK, FULL when the key table or the
  *              pool is full, INVALID_KEY); values are required.
  *   hc_retrieve: d_values_out = the key's number of values, found = key present.
@@ -257,23 +259,25 @@ hc_err hc_diag_gather(const void* d_base, uint64_t bytes, uint32_t line_bytes, u
  *   hc_insert_grouped: the same lists, one atomic per distinct key of the batch.
  * Not supported: batched launches and the server (HC_E_KIND). */
 typedef struct {
-  uint64_t pool_values;  /* pool size in 32-bit words (values and links); 0: 4 per key slot */
+  uint64_t pool_values;  /* pool size in 32-bit words (values and links), >= s0 * C; 0: (s0 + 3) * C */
   uint32_t s0;           /* first bucket size, >= 1 */
   uint32_t smax;         /* largest bucket size, s0 <= smax <= 2^24 */
   double growth;         /* growth factor lambda in [1, 64]; with 1 every bucket holds s0 (needs s0 = smax) */
 } hc_bucket_params;
 
-void hc_default_bucket_params(hc_bucket_params* params); /* pool 0 (4 per slot), s0 1, smax 65536, growth 2 */
+void hc_default_bucket_params(hc_bucket_params* params); /* pool 0 (s0 + 3 per slot), s0 1, smax 65536, growth 2 */
 
 /* Create a bucket list table for at least key_capacity distinct keys (rounded as hc_create).
- * params / bparams may be NULL (defaults).  Errors: HC_E_ARG (bad parameters, or a size ramp
- * from s0 to smax longer than 4096 buckets), HC_E_NOMEM. */
+ * params / bparams may be NULL (defaults).  Errors: HC_E_ARG (bad parameters, a pool smaller
+ * than s0 words per key slot or larger than 2^32 - 1 words, or a size ramp from s0 to smax
+ * longer than 4096 buckets), HC_E_NOMEM. */
 hc_err hc_create_bucket_list(hc_table* out, uint64_t key_capacity, const hc_params* params,
                              const hc_bucket_params* bparams);
 
 typedef struct {
   uint64_t values;      /* values stored (hc_size) */
-  uint64_t pool_used;   /* pool words handed out (values, links and the unused tail of last buckets) */
+  uint64_t pool_used;   /* pool words in use: the C * s0 words of the first buckets, then the words
+                           allocated (values, links and the unused tail of last buckets) */
   uint64_t pool_words;  /* pool size */
   uint32_t smax;
   uint32_t reserved;

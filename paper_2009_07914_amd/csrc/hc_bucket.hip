@@ -26,6 +26,15 @@
 //   3. every pair writes its value where its ticket falls: ticket t lies in the
 //      bucket i with S(i) <= t < S(i+1), S(i) = s_0 + ... + s_{i-1}.
 // Values of a key therefore appear in its list in ticket order.
+//
+// Bucket 0 of the key in slot p is never allocated: it is the s_0 pool words at
+// p * s_0 (the first C * s_0 words of the pool are reserved for them; later buckets
+// come from the rest of the pool).  So a pair of the per-pair insert that claims a
+// new slot for its key -- it holds ticket 0 -- stores its value and points `last` at
+// bucket 0 right away and skips phases 2 and 3: for keys seen once per batch (the
+// common case at low multiplicity) the insert is one probe, one claim and two stores.
+// Later tickets of the same key in the batch find bucket 0 through `last`, as tickets
+// of a key stored by an earlier batch do.
 #include <cmath>
 
 #include "hc_bucket.hpp"
@@ -74,23 +83,27 @@ struct BlTicket {
   BucketView b;
   const uint32_t* __restrict__ keys;
   const uint32_t* __restrict__ incr;  // values per element (runs of a grouped insert); NULL: 1
+  const uint32_t* __restrict__ values = nullptr;  // per-pair insert: the values (fast path); NULL: none
   uint64_t* __restrict__ pos;     // per pair: slot of its key
   uint32_t* __restrict__ ticket;  // per pair: rank among the key's values
-  uint8_t* __restrict__ st;       // per pair: ST_OK provisional, or the final failure
+  uint8_t* __restrict__ st;       // per pair: ST_OK provisional, BL_PLACED, or the final failure
   uint64_t i = 0, cand_idx = 0;
-  uint32_t k = 0, lbase = 0, k_nx = 0, inc = 1, inc_nx = 1;
+  uint32_t k = 0, lbase = 0, k_nx = 0, inc = 1, inc_nx = 1, v = 0, v_nx = 0;
   Seq s{};
   bool cand = false;
   long long added = 0;
+  long long placed = 0;  // values stored by claims (phase 1)
 
   __device__ __forceinline__ void load(uint64_t op) {
     k_nx = keys[op];
     inc_nx = incr != nullptr ? incr[op] : 1u;
+    if (values != nullptr) v_nx = values[op];
   }
   __device__ __forceinline__ void begin(uint64_t op) {
     i = op;
     k = k_nx;
     inc = inc_nx;
+    v = v_nx;
     ln.start(t, k, s, lbase);
     cand = false;
   }
@@ -110,12 +123,13 @@ struct BlTicket {
     record(idx, slot_value(old));
   }
   // CAS a reusable slot: 1 claimed (ticket 0), 2 the key was there (ticket taken), 3 lost to another key.
+  // A claim by a per-pair insert stores its value at once (claimed()).
   __device__ __forceinline__ uint32_t claim(uint64_t idx, uint64_t expect) {
     const uint64_t r = atomicCAS((unsigned long long*)&t.slots[idx], (unsigned long long)expect,
                                  (unsigned long long)make_slot(k, inc));
     if (r == expect) {
       ++added;
-      record(idx, 0u);
+      if (values == nullptr) record(idx, 0u);
       return 1;
     }
     if (slot_key(r) == k) {
@@ -123,6 +137,19 @@ struct BlTicket {
       return 2;
     }
     return 3;
+  }
+  // A claim succeeded at slot idx (known to group rank r): a per-pair insert holds ticket 0, the
+  // first word of the slot's bucket 0.
+  __device__ __forceinline__ bool claimed(uint64_t idx, uint32_t r) {
+    if (values == nullptr) return true;
+    const uint64_t p = ln.g.bcast64(idx, r);
+    if (ln.g.glane == 0) {
+      b.pool[p * b.s0] = v;
+      b.last[p] = (uint32_t)(p * b.s0);
+      st[i] = BL_PLACED;
+      ++placed;
+    }
+    return true;
   }
   __device__ __forceinline__ bool step() {
     const auto& g = ln.g;
@@ -143,6 +170,7 @@ struct BlTicket {
         uint32_t outcome = 0;
         if (g.glane == 0) outcome = claim(cand_idx, WORD_TOMB);
         outcome = g.bcast(outcome, 0);
+        if (outcome == 1) return claimed(cand_idx, 0);
         if (outcome != 3) return true;
         ln.start(t, k, s, lbase);
         cand = false;
@@ -151,13 +179,16 @@ struct BlTicket {
       while (b_reuse) {
         const uint32_t r = (uint32_t)ffs64(b_reuse);
         uint32_t outcome = 0;
+        uint64_t at = 0;
         if (g.glane == r) {
           const int j = lowbit(reuse);
           const uint64_t expect = ((win.empty >> j) & 1) ? WORD_EMPTY : WORD_TOMB;
           reuse &= reuse - 1;
-          outcome = claim(win.first + j, expect);
+          at = win.first + j;
+          outcome = claim(at, expect);
         }
         outcome = g.bcast(outcome, r);
+        if (outcome == 1) return claimed(at, r);
         if (outcome != 3) return true;
         b_reuse = g.bits(reuse != 0);
       }
@@ -170,14 +201,15 @@ struct BlTicket {
     ln.advance(t, s, lbase);
     return false;
   }
-  __device__ __forceinline__ void end() {}  // the size counts values (phase 3)
+  __device__ __forceinline__ void end() { wave_add_to(t.size, placed); }  // the others count in phase 3
 };
 
 // n_dev non-NULL: the element count is *n_dev (runs counted on the device).
 template <int G, int W>
 __global__ __launch_bounds__(BLOCK) void k_bl_ticket(TableView t, WorkCtl ctl, BucketView b,
                                                      const uint32_t* __restrict__ keys,
-                                                     const uint32_t* __restrict__ incr, uint64_t n,
+                                                     const uint32_t* __restrict__ incr,
+                                                     const uint32_t* __restrict__ values, uint64_t n,
                                                      const uint64_t* __restrict__ n_dev,
                                                      uint64_t* __restrict__ pos, uint32_t* __restrict__ ticket,
                                                      uint8_t* __restrict__ st) {
@@ -186,6 +218,7 @@ __global__ __launch_bounds__(BLOCK) void k_bl_ticket(TableView t, WorkCtl ctl, B
   op.b = b;
   op.keys = keys;
   op.incr = incr;
+  op.values = values;
   op.pos = pos;
   op.ticket = ticket;
   op.st = st;
@@ -229,7 +262,7 @@ __global__ __launch_bounds__(ALLOC_BLOCK) void k_bl_alloc(TableView t, BucketVie
   // the trip count depends only on blockIdx, so every thread of a block reaches each barrier
   for (uint64_t i0 = (uint64_t)blockIdx.x * ALLOC_BLOCK; i0 < n; i0 += stride) {
     const uint64_t i = i0 + threadIdx.x;
-    uint64_t p = 0, word = 0, b0 = 0, b1 = 0, words = 0;
+    uint64_t p = 0, word = 0, b0 = 0, b1 = 0, a0 = 1, words = 0;
     bool mine = false;
     if (i < n && st[i] == ST_OK) {
       p = pos[i];
@@ -239,7 +272,8 @@ __global__ __launch_bounds__(ALLOC_BLOCK) void k_bl_alloc(TableView t, BucketVie
         word = t.slots[p];
         b0 = bl_buckets(b, c0);
         b1 = bl_buckets(b, slot_value(word));  // count after phase 1
-        words = bl_words(b, b0, b1);
+        a0 = b0 > 1 ? b0 : 1;                   // bucket 0 is the slot's own, never allocated
+        words = b1 > a0 ? bl_words(b, a0, b1) : 0;
       }
     }
     // inclusive scan of the words over the wavefront, then over the block's wavefronts
@@ -264,25 +298,28 @@ __global__ __launch_bounds__(ALLOC_BLOCK) void k_bl_alloc(TableView t, BucketVie
     }
     __syncthreads();
     if (mine) {
-      const uint32_t old_last = b.last[p];
+      const uint64_t home = p * b.s0;                             // bucket 0
+      const uint32_t old_last = b0 == 0 ? (uint32_t)home : b.last[p];  // bucket a0 - 1
       uint32_t first_new = 0xFFFFFFFFu;
-      if (b1 > b0) {
-        const uint64_t base = block_base + wave_off[wv] + incl - words;
+      if (b1 > a0) {
+        const uint64_t base = b.bump + block_base + wave_off[wv] + incl - words;
         if (base + words > b.pool_cap || base + words > 0xFFFFFFFFull) {
-          // pool exhausted: keep what the existing buckets hold; a key left with no value leaves the table
-          const uint64_t keep = bl_S(b, b0);
+          // pool exhausted: keep what bucket 0 and the existing buckets hold
           atomicExch((unsigned long long*)&t.slots[p],
-                     (unsigned long long)(keep ? make_slot(slot_key(word), (uint32_t)keep) : WORD_TOMB));
+                     (unsigned long long)make_slot(slot_key(word), (uint32_t)bl_S(b, a0)));
+          if (b0 == 0) b.last[p] = (uint32_t)home;
         } else {
           uint64_t o = base, prev = old_last;
-          for (uint64_t j = b0; j < b1; ++j) {
-            if (j >= 1) b.pool[o] = (uint32_t)prev;
+          for (uint64_t j = a0; j < b1; ++j) {  // every allocated bucket starts with its link
+            b.pool[o] = (uint32_t)prev;
             prev = o;
-            o += bl_S(b, j + 1) - bl_S(b, j) + (j >= 1 ? 1 : 0);
+            o += bl_S(b, j + 1) - bl_S(b, j) + 1;
           }
           b.last[p] = (uint32_t)prev;
           first_new = (uint32_t)base;
         }
+      } else if (b0 == 0 && b1 >= 1) {
+        b.last[p] = (uint32_t)home;  // bucket 0 holds all of the key's values
       }
       b.meta[p].y = (uint64_t)old_last | ((uint64_t)first_new << 32);
     }
@@ -300,7 +337,9 @@ __global__ __launch_bounds__(256) void k_bl_place(TableView t, BucketView b, con
   long long stored = 0;
   for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
     uint8_t code = st[i];
-    if (code == ST_OK) {
+    if (code == BL_PLACED) {  // stored in phase 1 (and counted there)
+      code = ST_OK;
+    } else if (code == ST_OK) {
       const uint64_t p = pos[i], tk = ticket[i];
       const uint64_t c = slot_value(t.slots[p]);
       if (tk >= c) {
@@ -309,8 +348,11 @@ __global__ __launch_bounds__(256) void k_bl_place(TableView t, BucketView b, con
         const ulonglong2 mt = b.meta[p];
         const uint64_t c0 = (uint32_t)mt.x;
         const uint64_t b0 = bl_buckets(b, c0), bi = bl_bucket_of(b, tk);
+        const uint64_t a0 = b0 > 1 ? b0 : 1;
         const uint64_t bat = mt.y;
-        const uint64_t o = (bi < b0) ? (uint32_t)bat : (bat >> 32) + bl_words(b, b0, bi);
+        // bucket 0 is the slot's own; a ticket below the batch's first new bucket lies in the key's
+        // last bucket before the batch; the others in the buckets allocated in phase 2
+        const uint64_t o = bi == 0 ? p * b.s0 : (bi < b0) ? (uint32_t)bat : (bat >> 32) + bl_words(b, a0, bi);
         b.pool[o + (bi >= 1 ? 1 : 0) + (tk - bl_S(b, bi))] = values[i];
         ++stored;
       }
@@ -589,20 +631,20 @@ hc_err launch_bl_insert(const TableView& t, const BucketView& b, uint32_t G, uin
   uint64_t* pos = (uint64_t*)p; p += align256(8 * n);
   uint32_t* ticket = (uint32_t*)p; p += align256(4 * n);
   uint8_t* st = (uint8_t*)p;
-  hc_err r = launch_bl_tickets(t, b, G, W, keys, nullptr, n, nullptr, pos, ticket, st, s);
+  hc_err r = launch_bl_tickets(t, b, G, W, keys, nullptr, values, n, nullptr, pos, ticket, st, s);
   if (r != HC_OK) return r;
   return launch_bl_finish(t, b, values, n, pos, ticket, st, status, s);
 }
 
 hc_err launch_bl_tickets(const TableView& t, const BucketView& b, uint32_t G, uint32_t W, const uint32_t* keys,
-                         const uint32_t* incr, uint64_t n, const uint64_t* n_dev, uint64_t* pos, uint32_t* ticket,
-                         uint8_t* st, hipStream_t s) {
+                         const uint32_t* incr, const uint32_t* values, uint64_t n, const uint64_t* n_dev,
+                         uint64_t* pos, uint32_t* ticket, uint8_t* st, hipStream_t s) {
   return dispatch_gw(G, W, [&](auto g, auto w) -> hc_err {
     constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
     auto k = k_bl_ticket<GG, WW>;
     const unsigned grid = grid_for(k, n, GG);
     hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n_dev ? n / 8 : n, GG, grid), b, keys, incr,
-                       n, n_dev, pos, ticket, st);
+                       values, n, n_dev, pos, ticket, st);
     return check_launch("bucket list tickets");
   });
 }

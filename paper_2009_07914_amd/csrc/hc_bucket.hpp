@@ -21,7 +21,9 @@ struct BucketView {
   uint32_t smax;
   uint32_t* pool;                  // bucket pool, 32-bit words
   uint64_t pool_cap;               // words
-  unsigned long long* pool_next;   // first free word
+  uint64_t s0;                     // size of bucket 0: slot p's bucket 0 is the words [p * s0, (p + 1) * s0)
+  uint64_t bump;                   // C * s0: later buckets are allocated from here on
+  unsigned long long* pool_next;   // words allocated after `bump`
   uint32_t* last;                  // per key slot: pool offset of the key's last bucket
   // per key slot, one 16-byte record (the allocation reads the first word and writes the second,
   // placement reads both: one line each):
@@ -42,11 +44,12 @@ uint64_t bl_insert_workspace(uint64_t n);
 hc_err launch_bl_insert(const TableView& t, const BucketView& b, uint32_t G, uint32_t W, const uint32_t* keys,
                         const uint32_t* values, uint64_t n, uint8_t* status, void* ws, hipStream_t s);
 // The phases separately (grouped insert): tickets of n elements (n_dev non-NULL: *n_dev
-// elements, n an upper bound) with incr[i] values each (NULL: 1); tickets of the pairs of a
-// sorted batch from those of its runs; allocation and placement.
+// elements, n an upper bound) with incr[i] values each (NULL: 1); values non-NULL (per-pair
+// inserts, incr NULL): a pair that claims a new key stores its value in bucket 0 at once;
+// tickets of the pairs of a sorted batch from those of its runs; allocation and placement.
 hc_err launch_bl_tickets(const TableView& t, const BucketView& b, uint32_t G, uint32_t W, const uint32_t* keys,
-                         const uint32_t* incr, uint64_t n, const uint64_t* n_dev, uint64_t* pos, uint32_t* ticket,
-                         uint8_t* st, hipStream_t s);
+                         const uint32_t* incr, const uint32_t* values, uint64_t n, const uint64_t* n_dev,
+                         uint64_t* pos, uint32_t* ticket, uint8_t* st, hipStream_t s);
 hc_err launch_bl_expand(const uint64_t* scan, const uint64_t* starts, uint64_t n, const uint64_t* rpos,
                         const uint32_t* rticket, const uint8_t* rst, uint64_t* pos, uint32_t* ticket, uint8_t* st,
                         hipStream_t s);
@@ -59,6 +62,8 @@ hc_err launch_bl_count(const TableView& t, uint32_t G, uint32_t W, const uint32_
 // Values of keys into out[offsets[i] .. offsets[i+1]); lists longer than BL_LONG_LIST
 // values are copied by whole blocks.  Workspace: bl_write_workspace(n) bytes.
 constexpr uint64_t BL_LONG_LIST = 1024;
+// Phase-1 state of a pair whose value is already stored (it claimed its key's slot and bucket 0).
+constexpr uint8_t BL_PLACED = 0x80;
 uint64_t bl_write_workspace(uint64_t n);
 hc_err launch_bl_write(const TableView& t, const BucketView& b, uint32_t G, uint32_t W, const uint32_t* keys,
                        uint64_t n, const uint64_t* offsets, uint32_t* out, void* ws, hipStream_t s);

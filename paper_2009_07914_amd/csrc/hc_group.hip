@@ -1026,7 +1026,8 @@ hc_err launch_bl_grouped(const TableView& t, const BucketView& b, uint32_t G, ui
   if (hc_err r = check_launch("run starts"); r != HC_OK) return r;
   hipLaunchKernelGGL(k_run_lengths, dim3(g256), dim3(256), 0, s, kc, starts, flags + n, n, kt, vt);
   if (hc_err r = check_launch("run lengths"); r != HC_OK) return r;
-  if (hc_err r = launch_bl_tickets(t, b, G, W, kt, vt, n, flags + n, rpos, rticket, rst, s); r != HC_OK) return r;
+  if (hc_err r = launch_bl_tickets(t, b, G, W, kt, vt, nullptr, n, flags + n, rpos, rticket, rst, s); r != HC_OK)
+    return r;
   if (hc_err r = launch_bl_expand(flags, starts, n, rpos, rticket, rst, pos, ticket, st, s); r != HC_OK) return r;
   return launch_bl_finish(t, b, vc, n, pos, ticket, st, nullptr, s);
 }

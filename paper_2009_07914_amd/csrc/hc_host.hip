@@ -49,7 +49,7 @@ struct hc_table_s {
   bool order_pending = false;
   // bucket list tables (kind HC_BUCKET_LIST)
   uint64_t* d_cum = nullptr;       // cumulative bucket sizes of the ramp
-  uint32_t bl_m = 0, bl_smax = 0;
+  uint32_t bl_m = 0, bl_smax = 0, bl_s0 = 1;
   uint32_t* d_pool = nullptr;
   uint64_t pool_cap = 0;
   uint32_t* d_last = nullptr;
@@ -228,6 +228,8 @@ static BucketView bview_of(const hc_table_s* t) {
   b.smax = t->bl_smax;
   b.pool = t->d_pool;
   b.pool_cap = t->pool_cap;
+  b.s0 = t->bl_s0;
+  b.bump = t->C * t->bl_s0;     // the first C * s0 words hold the slots' first buckets
   b.pool_next = t->d_size + 1;  // the size counter and the pool counter share one allocation
   b.last = t->d_last;
   b.meta = t->d_meta;
@@ -598,7 +600,7 @@ hc_err hc_create(hc_table* out, uint32_t kind, uint64_t capacity, const hc_param
 }
 
 void hc_default_bucket_params(hc_bucket_params* p) {
-  p->pool_values = 0;  // 0: four values per key slot
+  p->pool_values = 0;  // 0: s0 + 3 words per key slot
   p->s0 = 1;
   p->smax = 1u << 16;
   p->growth = 2.0;
@@ -621,11 +623,18 @@ hc_err hc_create_bucket_list(hc_table* out, uint64_t key_capacity, const hc_para
   hc_table t = nullptr;
   hc_err r = create_table(&t, HC_BUCKET_LIST, key_capacity, params, nullptr, 0);
   if (r != HC_OK) return r;
-  const uint64_t pool = bp.pool_values ? bp.pool_values : 4 * t->C;
+  const uint64_t pool = bp.pool_values ? bp.pool_values : ((uint64_t)bp.s0 + 3) * t->C;
   if (pool > 0xFFFFFFFFull) {
     hc_destroy(t);
     return fail(HC_E_ARG, "pool of %llu words exceeds 2^32 - 1", (unsigned long long)pool);
   }
+  if (pool < (uint64_t)bp.s0 * t->C) {
+    const uint64_t need = (uint64_t)bp.s0 * t->C;
+    hc_destroy(t);
+    return fail(HC_E_ARG, "pool of %llu words is smaller than the first buckets of the %llu key slots (%llu words)",
+                (unsigned long long)pool, (unsigned long long)(need / bp.s0), (unsigned long long)need);
+  }
+  t->bl_s0 = bp.s0;
   t->bl_m = m;
   t->bl_smax = bp.smax;
   t->pool_cap = pool;
@@ -664,7 +673,8 @@ hc_err hc_bucket_usage(hc_table t, hc_bucket_usage_t* h_out, void* stream) {
   if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "hc_bucket_usage");
   h_out->values = v[0];
-  h_out->pool_used = v[1] < t->pool_cap ? v[1] : t->pool_cap;
+  const uint64_t used = t->C * t->bl_s0 + v[1];  // the slots' first buckets, then the allocated ones
+  h_out->pool_used = used < t->pool_cap ? used : t->pool_cap;
   h_out->pool_words = t->pool_cap;
   h_out->smax = t->bl_smax;
   return HC_OK;
