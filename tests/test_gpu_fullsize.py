@@ -33,15 +33,21 @@ def test_single_value_2e28_load_0_9_double_w16_g4(hc):
     assert np.array_equal(v[present], w["values"][w["query_src"][present].astype(np.int64)])
     assert not v[~present].any()
     # erase a tenth of the keys, then query again: erased keys are gone, absent ones still absent,
-    # and every other present key is still found (each present key is queried exactly once)
+    # and every other present key is still found with its value (each present key is queried once)
     er = w["erase"]
     assert np.all(h(t.erase(d(er), status=True, group=4)) == hc.S_OK)
     assert t.size() == n - er.size
     _, fe = t.retrieve(d(er), group=4)
     assert not h(fe).any()
-    _, f = t.retrieve(q, group=4)
-    f = h(f).astype(bool)
-    assert not f[~present].any() and int(f.sum()) == n - er.size
+    v, f = t.retrieve(q, group=4)
+    f, v = h(f).astype(bool), h(v)
+    erased = np.isin(w["keys"], er)  # per present key
+    src = w["query_src"]
+    live = present.copy()
+    live[present] = ~erased[src[present].astype(np.int64)]
+    assert np.array_equal(f, live) and int(f.sum()) == n - er.size
+    assert np.array_equal(v[live], w["values"][src[live].astype(np.int64)])
+    assert not v[~live].any()
 
 
 def test_multi_value_and_counting_2e26_zipf_into_2e27(hc):
@@ -57,6 +63,14 @@ def test_multi_value_and_counting_2e26_zipf_into_2e27(hc):
     ct = hc.Table("counting", 1 << 27, scheme="double", window=16, group=4)
     hc.hc_insert_grouped(ct.handle, keys, None)
     assert ct.size() == u.size
+    cv, cf = ct.retrieve(q)
+    assert np.array_equal(h(cv).astype(np.int64), expect) and np.array_equal(h(cf).astype(bool), hit)
+    # the per-element counting insert (equal keys of each tile combined): the same counts, one OK
+    # status per distinct key and DUPLICATE for every other occurrence
+    ct.clear()
+    st = h(ct.insert(keys, None, status=True, group=4))
+    assert ct.size() == u.size
+    assert int((st == hc.S_OK).sum()) == u.size and int((st == hc.S_DUPLICATE).sum()) == n - u.size
     cv, cf = ct.retrieve(q)
     assert np.array_equal(h(cv).astype(np.int64), expect) and np.array_equal(h(cf).astype(bool), hit)
     ct.close()
