@@ -1049,9 +1049,12 @@ def bench_sweep(args):
 
 def bench_serving(args):
     """16 resident single-value tables (2^20..2^28 slots) prefilled to half of a 0.9-load key universe;
-    requests of log-uniform size in [1, 2^max] (30% insert of fresh keys, 60% retrieve with 10% absent
-    keys, 10% erase of prefilled keys) arrive as a Poisson process.  The serial per-request path is
-    measured first; the server then takes the same stream at 50%, 80% and 95% of that path's rate."""
+    requests of log-uniform size in [1, 2^max] (30% insert, 60% retrieve with 10% absent keys, 10% erase of
+    prefilled keys) arrive as a Poisson process.  Uniform keys: inserts take fresh keys of the universe.
+    Zipf keys (--zipf): inserts and retrieves draw Zipf(1.1) keys of the universe, so inserts update hot
+    keys (upserts) and requests admitted together write the same keys; every insert writes the value
+    fixed by its key, so results agree whichever write of an epoch wins.  The serial per-request path
+    is measured first; the server then takes the same stream at 50%, 80% and 95% of that path's rate."""
     import threading
 
     import numpy as np
@@ -1075,28 +1078,41 @@ def bench_serving(args):
     zipf_pool = {}
     reqs = []
     nxt_ins, nxt_er = list(pre), [0] * len(caps)
+
+    def zipf_keys(t, n):
+        """Zipf(1.1) over the table's universe (its first min(|U|, 2^22) keys, skipping the erase range):
+        a wrapped slice of a per-table pool of 2^21 inverse-CDF draws."""
+        if t not in zipf_pool:
+            cdf = np.cumsum(gen.zipf_pmf(min(uni[t].size - pre[t] // 2, 1 << 22), 1.1))
+            u = gen.values(gen.derive_seed(seed, 200000 + t), 1 << 21).astype(np.float64) / 2.0**32
+            zipf_pool[t] = pre[t] // 2 + np.minimum(np.searchsorted(cdf, u * cdf[-1], side="right"), cdf.size - 1)
+        pool = zipf_pool[t]
+        start = int(rng.integers(pool.size))
+        return uni[t][pool[(start + np.arange(n)) % pool.size]]
+
+    def value_of(keys):  # the value an insert writes for a key (Zipf streams)
+        return ((keys.astype(np.uint64) * np.uint64(0x9E3779B1)) >> np.uint64(7)).astype(np.uint32)
+
     for r in range(args.requests):
         t = int(rng.integers(len(caps)))
         n = max(1, int(2.0 ** (args.max_log2_request * rng.random())))
         kind = rng.choice(3, p=[0.3, 0.6, 0.1])
+        if kind == 0 and args.zipf:
+            keys = zipf_keys(t, n)
+            reqs.append((t, hc.OP_INSERT, keys, value_of(keys)))
+            continue
         if kind == 0 and uni[t].size - nxt_ins[t] >= n:
             keys = uni[t][nxt_ins[t]:nxt_ins[t] + n]
             nxt_ins[t] += n
             reqs.append((t, hc.OP_INSERT, keys, gen.values(gen.derive_seed(seed, 100000 + r), n)))
             continue
-        if kind == 2 and pre[t] - nxt_er[t] >= n:
+        if kind == 2 and pre[t] // 2 - nxt_er[t] >= n:  # erases take prefilled keys no other request uses
             keys = uni[t][nxt_er[t]:nxt_er[t] + n]
             nxt_er[t] += n
             reqs.append((t, hc.OP_ERASE, keys, None))
             continue
-        if args.zipf:  # Zipf(1.1) over the table's first min(|U|, 2^22) keys: a pool of 2^21 draws per
-            if t not in zipf_pool:  # table (inverse CDF), from which each request takes a wrapped slice
-                cdf = np.cumsum(gen.zipf_pmf(min(uni[t].size, 1 << 22), 1.1))
-                u = gen.values(gen.derive_seed(seed, 200000 + t), 1 << 21).astype(np.float64) / 2.0**32
-                zipf_pool[t] = np.minimum(np.searchsorted(cdf, u * cdf[-1], side="right"), cdf.size - 1)
-            pool = zipf_pool[t]
-            start = int(rng.integers(pool.size))
-            keys = uni[t][pool[(start + np.arange(n)) % pool.size]]
+        if args.zipf:
+            keys = zipf_keys(t, n)
         else:
             keys = uni[t][rng.integers(0, uni[t].size, n)]
         m = n // 10
@@ -1120,7 +1136,8 @@ def bench_serving(args):
 
     tables = [hc.Table("single", c, scheme="double", window=16, group=4, seed=gen.derive_seed(seed, 50 + j), device=dev)
               for j, c in enumerate(caps)]
-    pre_d = [(torch.from_numpy(u[:p]).to(dev), torch.from_numpy(gen.values(gen.derive_seed(seed, 60 + j), p)).to(dev))
+    pre_d = [(torch.from_numpy(u[:p]).to(dev),
+              torch.from_numpy(value_of(u[:p]) if args.zipf else gen.values(gen.derive_seed(seed, 60 + j), p)).to(dev))
              for j, (u, p) in enumerate(zip(uni, pre))]
 
     def reset():
@@ -1161,10 +1178,16 @@ def bench_serving(args):
         r_server, out = run(False, frac * base_rate)
         res[f"serial_at_{frac}"] = r_serial
         res[f"server_at_{frac}"] = r_server
-        for (vm, fm), (vb, fb) in zip(out, base_out):  # same results alone and in the mix
+        ok_mix, ok_alone = [0] * len(caps), [0] * len(caps)
+        for (t, op, _, _, _, _), (vm, fm), (vb, fb) in zip(host, out, base_out):  # alone and in the mix
+            if op == hc.OP_INSERT and args.zipf:  # same-key inserts of one epoch: which one reports OK
+                ok_mix[t] += int((fm == hc.S_OK).sum())  # is open, how many is not
+                ok_alone[t] += int((fb == hc.S_OK).sum())
+                continue
             assert np.array_equal(fm, fb), "flags differ between the serial path and the server"
             if vm is not None:
                 assert np.array_equal(vm, vb), "values differ between the serial path and the server"
+        assert ok_mix == ok_alone, "new keys inserted differ between the serial path and the server"
     sat, _ = run(False, 0)
     res["server_saturated"] = sat
 
@@ -1179,8 +1202,9 @@ def bench_serving(args):
         "config": {"workload": "16 resident single-value tables (2^20..2^28 slots), prefilled to 45% of capacity; "
                                f"{len(host)} requests of log-uniform size in [1, 2^{args.max_log2_request}], "
                                "30% insert / 60% retrieve (10% absent keys) / 10% erase, "
-                               + ("Zipf(1.1) (over each table's first 2^22 keys)" if args.zipf else "uniform")
-                               + " retrieve keys; Poisson arrivals",
+                               + ("Zipf(1.1) insert and retrieve keys (over each table's first 2^22 keys)"
+                                  if args.zipf else "uniform keys (inserts of fresh keys)")
+                               + "; Poisson arrivals",
                    "requests": len(host), "ops": total_ops, "host_buffers": "pinned"},
         "modes": {k: fmt(v) for k, v in res.items()},
         "serial_rate_req_per_s": round(base_rate, 2),
