@@ -287,7 +287,8 @@ typedef struct {
 hc_err hc_bucket_usage(hc_table table, hc_bucket_usage_t* h_out, void* stream);
 
 /* Copy the pool (pool_words uint32) and the per-slot last-bucket offsets (C uint32) to caller
- * device memory, on the stream (for inspection). */
+ * device memory, on the stream (for inspection).  The last-bucket offset of slot p is meaningful
+ * only for a key with more than one bucket; a key with one bucket has it at p * s0. */
 hc_err hc_dump_buckets(hc_table table, uint32_t* d_pool_dst, uint32_t* d_last_dst, void* stream);
 
 /* Release the table and its device memory (synchronises the device). */

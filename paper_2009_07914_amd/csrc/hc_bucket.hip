@@ -21,20 +21,19 @@
 //   2. the pair holding that first ticket takes the buckets the key's new tickets
 //      need from the pool in one allocation (one pool atomic per wavefront),
 //      links them (previous-bucket offsets) and moves `last`; if the pool is
-//      exhausted the count is cut back to what the existing buckets hold (a key
-//      left with none becomes a tombstone);
+//      exhausted the count is cut back to what bucket 0 and the existing buckets
+//      hold;
 //   3. every pair writes its value where its ticket falls: ticket t lies in the
 //      bucket i with S(i) <= t < S(i+1), S(i) = s_0 + ... + s_{i-1}.
 // Values of a key therefore appear in its list in ticket order.
 //
 // Bucket 0 of the key in slot p is never allocated: it is the s_0 pool words at
 // p * s_0 (the first C * s_0 words of the pool are reserved for them; later buckets
-// come from the rest of the pool).  So a pair of the per-pair insert that claims a
-// new slot for its key -- it holds ticket 0 -- stores its value and points `last` at
-// bucket 0 right away and skips phases 2 and 3: for keys seen once per batch (the
-// common case at low multiplicity) the insert is one probe, one claim and two stores.
-// Later tickets of the same key in the batch find bucket 0 through `last`, as tickets
-// of a key stored by an earlier batch do.
+// come from the rest of the pool), and `last` is only read for keys with more than
+// one bucket.  So a pair of the per-pair insert that claims a new slot for its key --
+// it holds ticket 0 -- stores its value right away and skips phases 2 and 3: for keys
+// seen once per batch (the common case at low multiplicity) the insert is one probe,
+// one claim and one store.  Later tickets of the same key find bucket 0 at p * s_0.
 #include <cmath>
 
 #include "hc_bucket.hpp"
@@ -115,8 +114,9 @@ struct BlTicket {
   __device__ __forceinline__ void record(uint64_t idx, uint32_t tk) {
     pos[i] = idx;
     ticket[i] = tk;
-    st[i] = ST_OK;
-    atomicMin(&b.meta[idx].x, ((unsigned long long)(~b.epoch) << 32) | tk);  // older batches compare larger
+    const unsigned long long mine = ((unsigned long long)(~b.epoch) << 32) | tk;  // older batches compare larger
+    // a smaller stamp already there is a smaller ticket of this batch: not the key's allocator
+    st[i] = atomicMin(&b.meta[idx].x, mine) < mine ? BL_FOLLOW : ST_OK;
   }
   __device__ __forceinline__ void add_one(uint64_t idx) {  // `inc` more values (tickets old .. old + inc - 1)
     const uint64_t old = atomicAdd((unsigned long long*)&t.slots[idx], (unsigned long long)inc << 32);
@@ -144,8 +144,7 @@ struct BlTicket {
     if (values == nullptr) return true;
     const uint64_t p = ln.g.bcast64(idx, r);
     if (ln.g.glane == 0) {
-      b.pool[p * b.s0] = v;
-      b.last[p] = (uint32_t)(p * b.s0);
+      b.pool[p * b.s0] = v;  // `last` stays as it is: a key with one bucket has it at p * s0
       st[i] = BL_PLACED;
       ++placed;
     }
@@ -299,7 +298,7 @@ __global__ __launch_bounds__(ALLOC_BLOCK) void k_bl_alloc(TableView t, BucketVie
     __syncthreads();
     if (mine) {
       const uint64_t home = p * b.s0;                             // bucket 0
-      const uint32_t old_last = b0 == 0 ? (uint32_t)home : b.last[p];  // bucket a0 - 1
+      const uint32_t old_last = b0 <= 1 ? (uint32_t)home : b.last[p];  // bucket a0 - 1
       uint32_t first_new = 0xFFFFFFFFu;
       if (b1 > a0) {
         const uint64_t base = b.bump + block_base + wave_off[wv] + incl - words;
@@ -307,7 +306,7 @@ __global__ __launch_bounds__(ALLOC_BLOCK) void k_bl_alloc(TableView t, BucketVie
           // pool exhausted: keep what bucket 0 and the existing buckets hold
           atomicExch((unsigned long long*)&t.slots[p],
                      (unsigned long long)make_slot(slot_key(word), (uint32_t)bl_S(b, a0)));
-          if (b0 == 0) b.last[p] = (uint32_t)home;
+          atomicOr(t.size + CTR_BL_CUT, 1ull);  // placement must check tickets against the counts
         } else {
           uint64_t o = base, prev = old_last;
           for (uint64_t j = a0; j < b1; ++j) {  // every allocated bucket starts with its link
@@ -318,8 +317,6 @@ __global__ __launch_bounds__(ALLOC_BLOCK) void k_bl_alloc(TableView t, BucketVie
           b.last[p] = (uint32_t)prev;
           first_new = (uint32_t)base;
         }
-      } else if (b0 == 0 && b1 >= 1) {
-        b.last[p] = (uint32_t)home;  // bucket 0 holds all of the key's values
       }
       b.meta[p].y = (uint64_t)old_last | ((uint64_t)first_new << 32);
     }
@@ -335,24 +332,27 @@ __global__ __launch_bounds__(256) void k_bl_place(TableView t, BucketView b, con
                                                   uint8_t* __restrict__ status) {
   const uint64_t stride = (uint64_t)gridDim.x * 256;
   long long stored = 0;
+  // counts were only cut back (and tickets past them refused) if the allocation ran out of pool
+  const bool cut = *(volatile unsigned long long*)(t.size + CTR_BL_CUT) != 0;
   for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
     uint8_t code = st[i];
     if (code == BL_PLACED) {  // stored in phase 1 (and counted there)
       code = ST_OK;
-    } else if (code == ST_OK) {
+    } else if (code == ST_OK || code == BL_FOLLOW) {
+      code = ST_OK;
       const uint64_t p = pos[i], tk = ticket[i];
-      const uint64_t c = slot_value(t.slots[p]);
-      if (tk >= c) {
+      if (cut && tk >= slot_value(t.slots[p])) {
         code = ST_FULL;
       } else {
-        const ulonglong2 mt = b.meta[p];
-        const uint64_t c0 = (uint32_t)mt.x;
-        const uint64_t b0 = bl_buckets(b, c0), bi = bl_bucket_of(b, tk);
-        const uint64_t a0 = b0 > 1 ? b0 : 1;
-        const uint64_t bat = mt.y;
         // bucket 0 is the slot's own; a ticket below the batch's first new bucket lies in the key's
         // last bucket before the batch; the others in the buckets allocated in phase 2
-        const uint64_t o = bi == 0 ? p * b.s0 : (bi < b0) ? (uint32_t)bat : (bat >> 32) + bl_words(b, a0, bi);
+        const uint64_t bi = bl_bucket_of(b, tk);
+        uint64_t o = p * b.s0;
+        if (bi >= 1) {
+          const ulonglong2 mt = b.meta[p];
+          const uint64_t b0 = bl_buckets(b, (uint32_t)mt.x);
+          o = (bi < b0) ? (uint32_t)mt.y : (mt.y >> 32) + bl_words(b, b0 > 1 ? b0 : 1, bi);
+        }
         b.pool[o + (bi >= 1 ? 1 : 0) + (tk - bl_S(b, bi))] = values[i];
         ++stored;
       }
@@ -432,7 +432,7 @@ struct BlProbe {
         return true;
       }
       uint64_t bi = bl_bucket_of(b, c - 1);
-      uint64_t o = b.last[p];
+      uint64_t o = bi == 0 ? p * b.s0 : b.last[p];  // one bucket: at p * s0
       for (;;) {
         const uint64_t lo = bl_S(b, bi), hi = bl_S(b, bi + 1) < c ? bl_S(b, bi + 1) : c;
         const uint64_t v0 = o + (bi >= 1 ? 1 : 0);
@@ -508,7 +508,7 @@ __global__ __launch_bounds__(1024) void k_bl_write_long(BucketView b, const uint
     const uint64_t i = long_list[3 * e], p = long_list[3 * e + 1], c = long_list[3 * e + 2];
     const uint64_t base = offsets[i], limit = offsets[i + 1] - base;
     uint64_t bi = bl_bucket_of(b, c - 1);
-    uint64_t o = b.last[p];
+    uint64_t o = bi == 0 ? p * b.s0 : b.last[p];  // one bucket: at p * s0
     for (;;) {
       const uint64_t lo = bl_S(b, bi), hi = bl_S(b, bi + 1) < c ? bl_S(b, bi + 1) : c;
       const uint64_t v0 = o + (bi >= 1 ? 1 : 0);
@@ -663,6 +663,8 @@ hc_err launch_bl_finish(const TableView& t, const BucketView& b, const uint32_t*
   uint64_t ga = (n + ALLOC_BLOCK - 1) / ALLOC_BLOCK;
   const uint64_t cap = (uint64_t)device_cu_count() * 2;
   if (ga > cap) ga = cap;
+  hipLaunchKernelGGL(k_bl_zero1, dim3(1), dim3(64), 0, s, t.size + CTR_BL_CUT);
+  if (hc_err r = check_launch("bucket list flag"); r != HC_OK) return r;
   hipLaunchKernelGGL(k_bl_alloc, dim3((unsigned)(ga ? ga : 1)), dim3(ALLOC_BLOCK), 0, s, t, b, n, pos, ticket, st);
   if (hc_err r = check_launch("bucket list allocation"); r != HC_OK) return r;
   hipLaunchKernelGGL(k_bl_place, dim3(stream_grid(n)), dim3(256), 0, s, t, b, values, n, pos, ticket,

@@ -62,8 +62,14 @@ hc_err launch_bl_count(const TableView& t, uint32_t G, uint32_t W, const uint32_
 // Values of keys into out[offsets[i] .. offsets[i+1]); lists longer than BL_LONG_LIST
 // values are copied by whole blocks.  Workspace: bl_write_workspace(n) bytes.
 constexpr uint64_t BL_LONG_LIST = 1024;
-// Phase-1 state of a pair whose value is already stored (it claimed its key's slot and bucket 0).
+// Phase-1 states beside ST_OK (a candidate for allocating its key's new buckets): BL_PLACED, the
+// value is already stored (the pair claimed its key's slot and bucket 0); BL_FOLLOW, a pair of the
+// same key held a smaller ticket of the batch first, so this one only places its value.
 constexpr uint8_t BL_PLACED = 0x80;
+// Word of the table's counter block set while a bucket list insert runs once the pool ran out and
+// a key's count was cut back (placement then checks tickets against the counts).
+constexpr int CTR_BL_CUT = 3;
+constexpr uint8_t BL_FOLLOW = 0x81;
 uint64_t bl_write_workspace(uint64_t n);
 hc_err launch_bl_write(const TableView& t, const BucketView& b, uint32_t G, uint32_t W, const uint32_t* keys,
                        uint64_t n, const uint64_t* offsets, uint32_t* out, void* ws, hipStream_t s);

@@ -4,8 +4,9 @@ The bucket list table stores the same multiset as a multi-value table (each key'
 count per key), so the oracle's multi-value table is the reference: counts, offsets and each
 key's sorted values must match.  The list structure is checked on the host, independently
 of the device code: bucket sizes follow the paper's growth rule s_0, s_i = ceil(lambda s_{i-1})
-(capped), every bucket but the first links to the one before it, and walking a key's list
-from its last bucket yields exactly its values.
+(capped), bucket 0 of the key in slot p is the pool range [p s_0, (p + 1) s_0), every bucket but
+the first links to the one before it, and walking a key's list from its last bucket yields
+exactly its values.
 """
 import math
 
@@ -49,7 +50,10 @@ def _check_lists(t, orc, keys):
         p, c = by_key[k]
         assert c == int(c_o[0])
         sizes = _sizes(bp["s0"], bp["growth"], bp["smax"], c)
-        vals, o = [], int(last[p])
+        # bucket 0 is the slot's own range [p * s0, (p + 1) * s0); the last-bucket word is kept for
+        # keys with more than one bucket
+        bucket0 = p * bp["s0"]
+        vals, o = [], (bucket0 if len(sizes) == 1 else int(last[p]))
         for i in range(len(sizes) - 1, -1, -1):
             lo = sum(sizes[:i])
             nv = min(sizes[i], c - lo)
@@ -57,6 +61,8 @@ def _check_lists(t, orc, keys):
             vals.append(pool[base:base + nv])
             if i >= 1:
                 o = int(pool[o])
+                if i == 1:
+                    assert o == bucket0, f"key {k}: bucket 1 links to {o}, not to bucket 0 at {bucket0}"
         got = np.sort(np.concatenate(vals[::-1]))
         _, exp = orc.retrieve_all(np.array([k], np.uint32))
         assert np.array_equal(got, np.sort(exp)), f"values of key {k}"
