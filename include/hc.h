@@ -447,6 +447,29 @@ typedef struct hc_batch_s* hc_batch;
  * All tables must live on the current device. */
 hc_err hc_batch_create(hc_batch* out, const hc_batch_op* ops, uint32_t count);
 
+/* Flags of hc_batch_create_flags. */
+enum { HC_BATCH_ONE_LAUNCH = 1 };
+/* Longest wait of a one-launch plan for a table's previous phase, in milliseconds. */
+#define HC_BATCH_WAIT_MS 20000
+
+/* hc_batch_create with flags (0: the same plan).  HC_BATCH_ONE_LAUNCH runs every phase in
+ * ONE persistent launch instead of one launch per phase: wavefronts take the chunks of all
+ * phases from one counter in phase order, and a chunk of a table's later phase first waits,
+ * on the device, until every chunk of that table's previous phase has finished (a completion
+ * counter per table and phase, written after a device-scope release and read before a
+ * device-scope acquire).  Tables that finish early are queried while others are still being
+ * built; results are those of the phased plan.  Every operation of such a plan must use the
+ * same group size and window (HC_E_ARG otherwise).  Waiting cannot deadlock (the chunks waited
+ * for were taken earlier by running wavefronts, which never wait for later chunks); a wait
+ * still ends after HC_BATCH_WAIT_MS, and is then counted as abandoned (the results of that
+ * launch are not valid) -- a phase of one table that runs longer than that must use the
+ * phased plan.  Launch, capture and replay rules are those of hc_batch_create. */
+hc_err hc_batch_create_flags(hc_batch* out, const hc_batch_op* ops, uint32_t count, uint32_t flags);
+
+/* Number of waits of a one-launch plan abandoned so far, over all its launches (0 for
+ * other plans); synchronises the device first. */
+hc_err hc_batch_abandoned_waits(hc_batch batch, uint64_t* h_count);
+
 /* Enqueue every phase of the plan on `stream` (asynchronous; no allocation and no
  * memset, so it may be captured into a graph).  Each launch of the plan uses work
  * counters that belong to the plan (allocated by hc_batch_create and reset by the

@@ -142,6 +142,8 @@ _SIGS = {
     "hc_info": ([_p, ctypes.POINTER(HcTableInfo)], ctypes.c_int),
     "hc_dump_slots": ([_p, _p, _p], ctypes.c_int),
     "hc_batch_create": ([ctypes.POINTER(_p), ctypes.POINTER(HcBatchOp), _u32], ctypes.c_int),
+    "hc_batch_create_flags": ([ctypes.POINTER(_p), ctypes.POINTER(HcBatchOp), _u32, _u32], ctypes.c_int),
+    "hc_batch_abandoned_waits": ([_p, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
     "hc_batch_launch": ([_p, _p], ctypes.c_int),
     "hc_batch_info": ([_p, ctypes.POINTER(_u32), ctypes.POINTER(_u32)], ctypes.c_int),
     "hc_batch_destroy": ([_p], ctypes.c_int),
@@ -411,10 +413,25 @@ def hc_batch_op(table, op: int, keys, values=None, values_out=None, flags=None, 
                      _u32t(values_out, "values_out", n), _dptr(flags, torch.uint8, "flags", n), n)
 
 
+HC_BATCH_ONE_LAUNCH = 1
+
+
 def hc_batch_create(ops) -> int:
     h = ctypes.c_void_p()
     _check(_lib.hc_batch_create(ctypes.byref(h), _ops_array(ops), len(ops)), "hc_batch_create")
     return h.value
+
+
+def hc_batch_create_flags(ops, flags: int) -> int:
+    h = ctypes.c_void_p()
+    _check(_lib.hc_batch_create_flags(ctypes.byref(h), _ops_array(ops), len(ops), flags), "hc_batch_create_flags")
+    return h.value
+
+
+def hc_batch_abandoned_waits(batch: int) -> int:
+    c = ctypes.c_uint64(0)
+    _check(_lib.hc_batch_abandoned_waits(batch, ctypes.byref(c)), "hc_batch_abandoned_waits")
+    return int(c.value)
 
 
 def hc_batch_launch(batch: int, stream=None):
@@ -452,12 +469,17 @@ def hc_graph_destroy(graph: int):
 class Batch:
     """A launch plan over many tables; keeps the tensors of its operations alive."""
 
-    def __init__(self, ops_with_tensors):
-        # ops_with_tensors: list of (HcBatchOp, [tensors...])
+    def __init__(self, ops_with_tensors, one_launch: bool = False):
+        # ops_with_tensors: list of (HcBatchOp, [tensors...]); one_launch: every phase in one
+        # gated launch (HC_BATCH_ONE_LAUNCH)
         self._keep = [t for _, ts in ops_with_tensors for t in ts]
-        self.handle = hc_batch_create([o for o, _ in ops_with_tensors])
+        self.handle = hc_batch_create_flags([o for o, _ in ops_with_tensors],
+                                            HC_BATCH_ONE_LAUNCH if one_launch else 0)
         self.phases, self.launches = hc_batch_info(self.handle)
         self.graph = None
+
+    def abandoned_waits(self) -> int:
+        return hc_batch_abandoned_waits(self.handle)
 
     def launch(self, stream=None):
         hc_batch_launch(self.handle, stream)

@@ -51,12 +51,14 @@ __device__ __forceinline__ void run_chunk(const BatchDesc& d, uint64_t begin, ui
 
 // Every wavefront takes (descriptor, chunk) items from the launch's counter until
 // none is left and runs body(descriptor, first element, end) on each; the last
-// wavefront to leave resets the counters for the launch slot's next use.
+// wavefront to leave resets the counters for the launch slot's next use (and the
+// nreset words at `reset`).
 // chunk_start[d] = first global chunk of descriptor d; chunk_start[ndesc] = total.
 template <typename Body>
 __device__ __forceinline__ void take_chunks(const BatchDesc* __restrict__ descs,
                                             const uint64_t* __restrict__ chunk_start, uint32_t ndesc, WorkCtl ctl,
-                                            Body&& body) {
+                                            Body&& body, unsigned long long* reset = nullptr,
+                                            uint32_t nreset = 0) {
   const uint32_t lane = __lane_id();
   const uint64_t total = chunk_start[ndesc];
   for (;;) {
@@ -77,13 +79,17 @@ __device__ __forceinline__ void take_chunks(const BatchDesc* __restrict__ descs,
     const uint64_t end = begin + d.chunk < d.n ? begin + d.chunk : d.n;
     body(d, begin, end);
   }
+  uint32_t last = 0;
   if (lane == 0) {
     const unsigned long long waves = (unsigned long long)gridDim.x * (BLOCK / 64);
     if (atomicAdd(ctl.counters + 1, 1ull) == waves - 1) {
       atomicExch(ctl.counters, 0ull);
       atomicExch(ctl.counters + 1, 0ull);
+      last = 1;
     }
   }
+  if (nreset != 0 && __builtin_amdgcn_readfirstlane(last) != 0)
+    for (uint32_t j = lane; j < nreset; j += 64) atomicExch(reset + j, 0ull);
 }
 
 // One kernel per (operation kind, group size, window): every descriptor of a
@@ -127,6 +133,66 @@ __global__ __launch_bounds__(BLOCK) void k_batch_mixed(const BatchDesc* __restri
   });
 }
 
+// ---- one launch over every phase -------------------------------------------------------
+//
+// A plan's phases exist because a table's operations of different kinds must not
+// overlap.  Here the chunks of all phases are handed out from one counter in phase
+// order, and a chunk of a table's later phase first waits for the table's previous
+// phase: each finished chunk adds 1 to its (table, phase) completion counter after a
+// device-scope release, and the waiting wavefront spins on that counter and then
+// acquires.  Waiting cannot deadlock: every chunk waited for was taken earlier from the
+// same counter by a wavefront that is running and only waits, if at all, on chunks taken
+// earlier still, down to the first phase, which never waits.  Each wait is still bounded
+// by the device clock (a plan bug then shows as a counted abandoned wait, never a hang).
+
+__device__ __forceinline__ void gate_wait(unsigned long long* gate, uint64_t need, unsigned long long* abandoned,
+                                          uint64_t ticks) {
+  if (__lane_id() == 0) {
+    const uint64_t t0 = wall_clock64();
+    while (__hip_atomic_load(gate, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+      if (wall_clock64() - t0 > ticks) {
+        atomicAdd(abandoned, 1ull);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the previous phase's writes, from every XCD
+}
+
+__device__ __forceinline__ void gate_post(unsigned long long* gate) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this chunk's writes before it counts as done
+  if (__lane_id() == 0) atomicAdd(gate, 1ull);
+}
+
+template <int G, int W>
+__global__ __launch_bounds__(BLOCK) void k_batch_one(const BatchDesc* __restrict__ descs,
+                                                     const uint64_t* __restrict__ chunk_start, uint32_t ndesc,
+                                                     WorkCtl ctl, unsigned long long* gates, uint32_t ngates,
+                                                     unsigned long long* abandoned, uint64_t ticks) {
+  __shared__ BatchRing rings[BLOCK / 64];
+  BatchRing* ring = &rings[threadIdx.x >> 6];
+  // the last counter this wavefront saw complete: a later chunk waiting for it needs no
+  // second wait or acquire (no write of that phase remains to be seen)
+  uint32_t passed = NO_GATE;
+  take_chunks(
+      descs, chunk_start, ndesc, ctl,
+      [&](const BatchDesc& d, uint64_t begin, uint64_t end) {
+        if (d.gate_wait != NO_GATE && d.gate_wait != passed) {
+          gate_wait(gates + d.gate_wait, d.gate_need, abandoned, ticks);
+          passed = d.gate_wait;
+        }
+        switch (d.op) {
+          case BATCH_INSERT: run_chunk<BATCH_INSERT, G, W>(d, begin, end, ring); break;
+          case BATCH_COUNT: run_chunk<BATCH_COUNT, G, W>(d, begin, end, ring); break;
+          case BATCH_RETRIEVE: run_chunk<BATCH_RETRIEVE, G, W>(d, begin, end, ring); break;
+          default: run_chunk<BATCH_ERASE, G, W>(d, begin, end, ring); break;
+        }
+        if (d.gate_post != NO_GATE) gate_post(gates + d.gate_post);
+      },
+      gates, ngates);
+}
+
 uint32_t mixed_variant(uint32_t G, uint32_t W) {
   switch (W) {
     case 8: return G == 1 ? 0 : G == 2 ? 1 : G == 4 ? 2 : G == 8 ? 3 : MIXED_NONE;
@@ -136,16 +202,31 @@ uint32_t mixed_variant(uint32_t G, uint32_t W) {
   }
 }
 
-template <typename K>
+template <typename K, typename... Extra>
 static hc_err launch_persistent(K k, const BatchDesc* d_descs, const uint64_t* d_chunk_start, uint32_t ndesc,
-                                uint64_t total_chunks, unsigned long long* counters, hipStream_t stream) {
+                                uint64_t total_chunks, unsigned long long* counters, hipStream_t stream,
+                                Extra... extra) {
   const uint64_t cap = (uint64_t)device_cu_count() * (uint64_t)blocks_per_cu(reinterpret_cast<const void*>(k));
   const uint64_t need = (total_chunks + (BLOCK / 64) - 1) / (BLOCK / 64);
   const unsigned grid = (unsigned)(need < cap ? need : cap);
   WorkCtl ctl = work_for(0, 64, grid);
   if (counters != nullptr) ctl.counters = counters;
-  hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, d_descs, d_chunk_start, ndesc, ctl);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, d_descs, d_chunk_start, ndesc, ctl, extra...);
   return check_launch("batch");
+}
+
+hc_err launch_batch_one(uint32_t G, uint32_t W, const BatchDesc* d_descs, const uint64_t* d_chunk_start,
+                        uint32_t ndesc, uint64_t total_chunks, unsigned long long* counters,
+                        unsigned long long* gates, uint32_t ngates, unsigned long long* abandoned,
+                        uint64_t wait_ticks, hipStream_t stream) {
+  if (ndesc == 0 || total_chunks == 0) return HC_OK;
+  if (counters == nullptr || (ngates != 0 && gates == nullptr) || abandoned == nullptr)
+    return fail(HC_E_ARG, "a one-launch plan needs its own counters");
+  return dispatch_gw(G, W, [&](auto g, auto w) -> hc_err {
+    constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
+    return launch_persistent(k_batch_one<GG, WW>, d_descs, d_chunk_start, ndesc, total_chunks, counters, stream,
+                             gates, ngates, abandoned, wait_ticks);
+  });
 }
 
 template <uint32_t OP>

@@ -34,6 +34,8 @@ struct hc_batch_s {
   // work counters of the plan's own launches (not the shared launch-slot ring), so a
   // captured graph never shares counters with launches made outside it
   unsigned long long* d_counters = nullptr;
+  uint32_t gates = 0;       // one-launch plans: completion counters after the launch counters
+  uint64_t wait_ticks = 0;  // device clock ticks after which a completion wait is abandoned
 };
 
 struct hc_table_s {
@@ -310,19 +312,116 @@ static hc_err set_device(hc_table t) {
 
 namespace hc {
 
+struct PlanItem {
+  uint32_t phase, op, G, W;
+  uint32_t index;  // into ops
+};
+
+// Chunk size of an operation of n elements with group size G in a launch whose
+// per-wavefront share is per_wave elements: about two chunks per resident wavefront
+// over the whole launch, between one element per group and 64 elements per group of a
+// wavefront.
+static uint32_t chunk_of(uint64_t n, uint32_t G, uint64_t per_wave) {
+  const uint64_t gpw = 64 / G;
+  uint64_t ch = per_wave < gpw ? gpw : per_wave;
+  if (ch > 64 * gpw) ch = 64 * gpw;
+  return (uint32_t)(n < ch ? n : ch);
+}
+
+// Every phase in one launch (items with phases assigned, list order kept): descriptors in
+// (phase, list) order; a table's descriptors in phase p wait for the completion counter of
+// the table's latest earlier phase that has elements, and post to their own (table, phase)
+// counter if a later phase of the table waits for it.
+static hc_err build_one_launch(const hc_batch_op* ops, std::vector<PlanItem>& items, uint32_t phases,
+                               PlanHost* out) {
+  out->phases = phases;
+  if (items.empty()) return HC_OK;
+  for (const PlanItem& x : items)
+    if (x.G != items[0].G || x.W != items[0].W)
+      return fail(HC_E_ARG, "a one-launch plan needs one group size and window for every operation "
+                            "(op %u has g = %u, W = %u; op %u has g = %u, W = %u)",
+                  items[0].index, items[0].G, items[0].W, x.index, x.G, x.W);
+  std::stable_sort(items.begin(), items.end(),
+                   [](const PlanItem& a, const PlanItem& b) { return a.phase < b.phase; });
+  const uint64_t waves = (uint64_t)device_cu_count() * 32;
+  uint64_t total = 0;
+  for (const PlanItem& x : items) total += ops[x.index].n;
+  const uint64_t per_wave = (total + 2 * waves - 1) / (2 * waves);
+  // (table, phase) groups: own completion counter and the counter they wait for
+  struct Group {
+    uint32_t phase, gate, wait;
+  };
+  std::unordered_map<const hc_table_s*, Group> cur;  // each table's latest group so far
+  std::vector<uint64_t> gate_chunks;                 // chunks per counter
+  std::vector<uint8_t> gate_used;                    // a later group waits for it
+  uint64_t chunks = 0;
+  for (const PlanItem& x : items) {
+    const hc_batch_op& o = ops[x.index];
+    auto it = cur.find(o.table);
+    if (it == cur.end() || it->second.phase != x.phase) {  // a new (table, phase) group
+      const uint32_t prev = it == cur.end() ? NO_GATE : it->second.gate;
+      if (prev != NO_GATE) gate_used[prev] = 1;
+      cur[o.table] = Group{x.phase, (uint32_t)gate_chunks.size(), prev};
+      gate_chunks.push_back(0);
+      gate_used.push_back(0);
+      it = cur.find(o.table);
+    }
+    BatchDesc d;
+    d.t = view_of(o.table);
+    d.keys = o.d_keys;
+    d.values = o.d_values;
+    d.values_out = o.d_values_out;
+    d.flags = o.d_flags;
+    d.n = o.n;
+    d.chunk = chunk_of(o.n, x.G, per_wave);
+    d.op = x.op;
+    d.variant = MIXED_NONE;
+    d.pad = 0;
+    d.gate_need = 0;
+    d.gate_wait = it->second.wait;
+    d.gate_post = it->second.gate;
+    const uint64_t nch = (o.n + d.chunk - 1) / d.chunk;
+    gate_chunks[it->second.gate] += nch;
+    out->descs.push_back(d);
+    out->cs.push_back(chunks);
+    chunks += nch;
+  }
+  out->cs.push_back(chunks);
+  // counters nobody waits for are dropped; the others get compact ids
+  std::vector<uint32_t> id(gate_chunks.size(), NO_GATE);
+  uint32_t ngates = 0;
+  for (size_t g = 0; g < gate_chunks.size(); ++g)
+    if (gate_used[g]) id[g] = ngates++;
+  for (BatchDesc& d : out->descs) {
+    if (d.gate_wait != NO_GATE) {
+      d.gate_need = gate_chunks[d.gate_wait];
+      d.gate_wait = id[d.gate_wait];
+    }
+    d.gate_post = id[d.gate_post];
+  }
+  out->gates = ngates;
+  PlanLaunch L;
+  L.op = BATCH_ALL;
+  L.G = items[0].G;
+  L.W = items[0].W;
+  L.first_desc = 0;
+  L.ndesc = (uint32_t)out->descs.size();
+  L.cs_offset = 0;
+  L.total_chunks = chunks;
+  out->launches.push_back(L);
+  return HC_OK;
+}
+
 // Validate `ops`, assign phases (a table's phase advances where its operation kind
 // changes) and lay out the per-launch descriptor groups on the host.
-hc_err build_plan(const hc_batch_op* ops, uint32_t count, int dev, PlanHost* out) {
+hc_err build_plan(const hc_batch_op* ops, uint32_t count, int dev, PlanHost* out, bool one_launch) {
   out->descs.clear();
   out->cs.clear();
   out->launches.clear();
   out->phases = 0;
+  out->gates = 0;
   if (count > 0 && ops == nullptr) return fail(HC_E_ARG, "ops is NULL");
-  struct Item {
-    uint32_t phase, op, G, W;
-    uint32_t index;
-  };
-  std::vector<Item> items;
+  std::vector<PlanItem> items;
   items.reserve(count);
   std::unordered_map<const hc_table_s*, std::pair<uint32_t, uint32_t>> last;  // table -> (phase, op)
   uint32_t phases = 0;
@@ -353,11 +452,12 @@ hc_err build_plan(const hc_batch_op* ops, uint32_t count, int dev, PlanHost* out
     if (phase + 1 > phases) phases = phase + 1;
     if (o.n > 0) items.push_back({phase, bop, g, t->window, j});
   }
+  if (one_launch) return build_one_launch(ops, items, phases, out);
   // Launches: one per (phase, kind, G, W) group, list order kept inside each group.
   // Where a (phase, kind) has several pairs, those of the mixed-launch set share one
   // mixed launch (G = W = 0 below); pairs outside the set keep launches of their own.
-  auto pair_key = [](const Item& x) { return (x.G << 8) | x.W; };
-  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) {
+  auto pair_key = [](const PlanItem& x) { return (x.G << 8) | x.W; };
+  std::stable_sort(items.begin(), items.end(), [](const PlanItem& a, const PlanItem& b) {
     if (a.phase != b.phase) return a.phase < b.phase;
     return a.op < b.op;
   });
@@ -376,7 +476,7 @@ hc_err build_plan(const hc_batch_op* ops, uint32_t count, int dev, PlanHost* out
   std::vector<size_t> order(items.size());
   for (size_t q = 0; q < order.size(); ++q) order[q] = q;
   std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
-    const Item &a = items[x], &b = items[y];
+    const PlanItem &a = items[x], &b = items[y];
     if (a.phase != b.phase) return a.phase < b.phase;
     if (a.op != b.op) return a.op < b.op;
     if (mixed[x] != mixed[y]) return mixed[x] > mixed[y];
@@ -385,11 +485,11 @@ hc_err build_plan(const hc_batch_op* ops, uint32_t count, int dev, PlanHost* out
   const uint64_t waves = (uint64_t)device_cu_count() * 32;
   out->phases = phases;
   for (size_t a = 0; a < order.size();) {
-    const Item& f = items[order[a]];
+    const PlanItem& f = items[order[a]];
     const bool mix = mixed[order[a]] != 0;
     size_t e = a;
     while (e < order.size()) {
-      const Item& x = items[order[e]];
+      const PlanItem& x = items[order[e]];
       if (x.phase != f.phase || x.op != f.op || (mixed[order[e]] != 0) != mix) break;
       if (!mix && pair_key(x) != pair_key(f)) break;
       ++e;
@@ -401,18 +501,13 @@ hc_err build_plan(const hc_batch_op* ops, uint32_t count, int dev, PlanHost* out
     L.first_desc = (uint32_t)out->descs.size();
     L.ndesc = (uint32_t)(e - a);
     L.cs_offset = out->cs.size();
-    // chunk size: about two chunks per resident wavefront over the whole launch, between
-    // one element per group and 64 elements per group of a wavefront (per descriptor's G)
     uint64_t total = 0;
     for (size_t q = a; q < e; ++q) total += ops[items[order[q]].index].n;
     const uint64_t per_wave = (total + 2 * waves - 1) / (2 * waves);
     uint64_t chunks = 0;
     for (size_t q = a; q < e; ++q) {
-      const Item& x = items[order[q]];
+      const PlanItem& x = items[order[q]];
       const hc_batch_op& o = ops[x.index];
-      const uint64_t gpw = 64 / x.G;
-      uint64_t ch = per_wave < gpw ? gpw : per_wave;
-      if (ch > 64 * gpw) ch = 64 * gpw;
       BatchDesc d;
       d.t = view_of(o.table);
       d.keys = o.d_keys;
@@ -420,10 +515,12 @@ hc_err build_plan(const hc_batch_op* ops, uint32_t count, int dev, PlanHost* out
       d.values_out = o.d_values_out;
       d.flags = o.d_flags;
       d.n = o.n;
-      d.chunk = (uint32_t)(o.n < ch ? o.n : ch);
+      d.chunk = chunk_of(o.n, x.G, per_wave);
       d.op = L.op;
       d.variant = mix ? mixed_variant(x.G, x.W) : MIXED_NONE;
-      d.reserved = 0;
+      d.gate_post = d.gate_wait = NO_GATE;
+      d.pad = 0;
+      d.gate_need = 0;
       out->descs.push_back(d);
       out->cs.push_back(chunks);
       chunks += (o.n + d.chunk - 1) / d.chunk;
@@ -437,10 +534,17 @@ hc_err build_plan(const hc_batch_op* ops, uint32_t count, int dev, PlanHost* out
 }
 
 hc_err launch_plan(const std::vector<PlanLaunch>& launches, const BatchDesc* d_descs, const uint64_t* d_cs,
-                   unsigned long long* counters, hipStream_t stream) {
+                   unsigned long long* counters, hipStream_t stream, uint32_t gates, uint64_t wait_ticks) {
   for (size_t j = 0; j < launches.size(); ++j) {
     const PlanLaunch& L = launches[j];
     unsigned long long* c = counters ? counters + j * PLAN_COUNTER_STRIDE : nullptr;
+    if (L.op == BATCH_ALL) {
+      unsigned long long* extra = counters ? counters + launches.size() * PLAN_COUNTER_STRIDE : nullptr;
+      hc_err r = launch_batch_one(L.G, L.W, d_descs + L.first_desc, d_cs + L.cs_offset, L.ndesc, L.total_chunks, c,
+                                  extra ? extra + PLAN_COUNTER_STRIDE : nullptr, gates, extra, wait_ticks, stream);
+      if (r != HC_OK) return r;
+      continue;
+    }
     hc_err r = L.G == 0 ? launch_batch_mixed(L.op, d_descs + L.first_desc, d_cs + L.cs_offset, L.ndesc,
                                              L.total_chunks, c, stream)
                         : launch_batch(L.op, L.G, L.W, d_descs + L.first_desc, d_cs + L.cs_offset, L.ndesc,
@@ -1075,19 +1179,33 @@ hc_err hc_dump_slots(hc_table t, uint64_t* d_dst, void* stream) {
 
 
 hc_err hc_batch_create(hc_batch* out, const hc_batch_op* ops, uint32_t count) {
+  return hc_batch_create_flags(out, ops, count, 0);
+}
+
+hc_err hc_batch_create_flags(hc_batch* out, const hc_batch_op* ops, uint32_t count, uint32_t flags) {
   if (out == nullptr) return fail(HC_E_ARG, "out is NULL");
   *out = nullptr;
+  if ((flags & ~(uint32_t)HC_BATCH_ONE_LAUNCH) != 0) return fail(HC_E_ARG, "unknown batch flags 0x%x", flags);
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(HC_E_DEVICE, "hipGetDevice failed");
   PlanHost plan;
-  if (hc_err r = build_plan(ops, count, dev, &plan); r != HC_OK) return r;
+  if (hc_err r = build_plan(ops, count, dev, &plan, (flags & HC_BATCH_ONE_LAUNCH) != 0); r != HC_OK) return r;
+  uint64_t ticks = 0;
+  if (flags & HC_BATCH_ONE_LAUNCH) {
+    int khz = 0;
+    const hipError_t e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess || khz <= 0) return fail(HC_E_DEVICE, "device clock rate unavailable");
+    ticks = (uint64_t)khz * HC_BATCH_WAIT_MS;
+  }
   hc_batch_s* b = new (std::nothrow) hc_batch_s();
   if (!b) return fail(HC_E_NOMEM, "host allocation failed");
   b->device = dev;
   b->phases = plan.phases;
   b->launches = plan.launches;
+  b->gates = plan.gates;
+  b->wait_ticks = ticks;
   if (!plan.descs.empty()) {
-    const size_t cbytes = plan.launches.size() * PLAN_COUNTER_STRIDE * sizeof(unsigned long long);
+    const size_t cbytes = plan_counter_words(plan) * sizeof(unsigned long long);
     hipError_t e1 = hipMalloc((void**)&b->d_descs, plan.descs.size() * sizeof(BatchDesc));
     hipError_t e2 = e1 == hipSuccess ? hipMalloc((void**)&b->d_chunk_start, plan.cs.size() * sizeof(uint64_t)) : e1;
     hipError_t e3 = e2 == hipSuccess ? hipMalloc((void**)&b->d_counters, cbytes) : e2;
@@ -1123,7 +1241,28 @@ hc_err hc_batch_launch(hc_batch b, void* stream) {
     const hipError_t e = hipSetDevice(b->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   }
-  return launch_plan(b->launches, b->d_descs, b->d_chunk_start, b->d_counters, (hipStream_t)stream);
+  return launch_plan(b->launches, b->d_descs, b->d_chunk_start, b->d_counters, (hipStream_t)stream, b->gates,
+                     b->wait_ticks);
+}
+
+hc_err hc_batch_abandoned_waits(hc_batch b, uint64_t* h_count) {
+  if (b == nullptr || h_count == nullptr) return fail(HC_E_ARG, "batch or out is NULL");
+  *h_count = 0;
+  bool one = false;
+  for (const PlanLaunch& L : b->launches) one |= L.op == BATCH_ALL;
+  if (!one || b->d_counters == nullptr) return HC_OK;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(HC_E_DEVICE, "hipGetDevice failed");
+  if (cur != b->device) {
+    const hipError_t e = hipSetDevice(b->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  }
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess)
+    e = hipMemcpy(h_count, b->d_counters + b->launches.size() * PLAN_COUNTER_STRIDE, sizeof(uint64_t),
+                  hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hc_batch_abandoned_waits");
+  return HC_OK;
 }
 
 hc_err hc_batch_info(hc_batch b, uint32_t* h_phases, uint32_t* h_launches) {

@@ -284,16 +284,19 @@ def test_graph_replay_beside_eager_launches(hc):
     b.close()
 
 
-def test_full_size_256_tables(hc):
+@pytest.mark.parametrize("one_launch", [False, True])
+def test_full_size_256_tables(hc, one_launch):
     """The 256-table workload at its full size (capacities log-uniform in [2^10, 2^24], loads in
-    [0.6, 0.95], about 4.4e8 slots): tuned layouts, one batched plan launched and its graph replayed;
-    every found flag, value and status against the inputs (keys are distinct, so a present query
-    returns the value inserted with its key), sizes exact, and the smallest tables against the oracle."""
+    [0.6, 0.95], about 4.4e8 slots): tuned layouts in a phased plan, or one layout (double hashing,
+    W = 16, g = 4) in a one-launch plan; launched and its graph replayed; every found flag, value and
+    status against the inputs (keys are distinct, so a present query returns the value inserted with
+    its key), sizes exact, and the smallest tables against the oracle."""
     from paper_2009_07914_amd import autotune
     spec = gen.batched_tables_spec(256, 10, 24, 0.6, 0.95, 16, gen.SEED_BASE + 3)
     tabs, data, ops = [], [], []
     for sp in spec:
-        cfg = autotune.choose(sp["capacity"], sp["load"])
+        cfg = (dict(scheme="double", window=16, group_insert=4, group_query=4) if one_launch
+               else autotune.choose(sp["capacity"], sp["load"]))
         t = hc.Table("single", sp["capacity"], scheme=cfg["scheme"], window=cfg["window"],
                      group=cfg["group_insert"], seed=sp["seed"])
         w = gen.single_value_workload(sp["capacity"], sp["load"], sp["seed"])
@@ -306,7 +309,8 @@ def test_full_size_256_tables(hc):
         tabs.append((t, cfg))
     ops += [(hc.hc_batch_op(t, hc.OP_RETRIEVE, x[5][0], values_out=x[3], flags=x[4], group=cfg["group_query"]),
              [x[5][0], x[3], x[4]]) for (t, cfg), x in zip(tabs, data)]
-    b = hc.Batch(ops)
+    b = hc.Batch(ops, one_launch=one_launch)
+    assert b.launches == 1 or not one_launch
     assert sum(x[1]["n"] for x in data) > 3e8
 
     def check():
@@ -341,4 +345,128 @@ def test_full_size_256_tables(hc):
         vv, ff = orc.retrieve(w["queries"])
         assert np.array_equal(h(vo), vv) and np.array_equal(h(fo), ff)
         check_layout(t, oracle.SINGLE)
+    assert b.abandoned_waits() == 0
     b.close()
+
+
+def test_one_launch_phases_follow_list_order(hc):
+    """HC_BATCH_ONE_LAUNCH: the four phases of a list over two tables (with an empty operation
+    between two of them) run in one gated launch and give the oracle's list-order results; no
+    completion wait is abandoned, and graph replays give the same results."""
+    t1 = hc.Table("single", 1 << 15, scheme="double", window=16, group=4)
+    t2 = hc.Table("single", 1 << 12, scheme="quadratic", window=16, group=4)
+    k1, v1 = gen.keys(90, 1, 24000), gen.values(91, 24000)
+    k2, v2 = gen.keys(92, 1, 2500), gen.values(93, 2500)
+    er = k1[:9000]
+    k2b, v2b = gen.keys(92, 2501, 900), gen.values(94, 900)
+    q1 = np.concatenate([k1, gen.keys(90, 24001, 4000)])
+    q2 = np.concatenate([k2, k2b, gen.keys(92, 4000, 500)])
+    T = {}
+
+    def buf(name, a):
+        T[name] = d(a)
+        return T[name]
+
+    def out(name, n, dt):
+        T[name] = torch.zeros(n, dtype=dt, device="cuda")
+        return T[name]
+
+    ops = [
+        hc.hc_batch_op(t1, hc.OP_INSERT, buf("k1", k1), buf("v1", v1), flags=out("s1", k1.size, torch.uint8)),
+        hc.hc_batch_op(t2, hc.OP_INSERT, buf("k2", k2), buf("v2", v2)),
+        hc.hc_batch_op(t2, hc.OP_RETRIEVE, buf("q2a", q2), values_out=out("r2a", q2.size, torch.uint32),
+                       flags=out("f2a", q2.size, torch.uint8)),
+        hc.hc_batch_op(t1, hc.OP_RETRIEVE, buf("empty", np.zeros(0, np.uint32))),  # a phase with no chunks
+        hc.hc_batch_op(t1, hc.OP_ERASE, buf("e1", er), flags=out("se", er.size, torch.uint8)),
+        hc.hc_batch_op(t1, hc.OP_RETRIEVE, buf("q1", q1), values_out=out("r1", q1.size, torch.uint32),
+                       flags=out("f1", q1.size, torch.uint8)),
+        hc.hc_batch_op(t2, hc.OP_INSERT, buf("k2b", k2b), buf("v2b", v2b)),
+        hc.hc_batch_op(t2, hc.OP_RETRIEVE, buf("q2b", q2), values_out=out("r2b", q2.size, torch.uint32),
+                       flags=out("f2b", q2.size, torch.uint8)),
+    ]
+    b = hc.Batch([(o, list(T.values())) for o in ops], one_launch=True)
+    assert b.phases == 4 and b.launches == 1
+
+    def check():
+        o1, o2 = oracle.OracleTable(oracle.SINGLE, t1.capacity), oracle.OracleTable(oracle.SINGLE, t2.capacity)
+        assert np.array_equal(h(T["s1"]), o1.insert(k1, v1))
+        o2.insert(k2, v2)
+        vv, ff = o2.retrieve(q2)
+        assert np.array_equal(h(T["r2a"]), vv) and np.array_equal(h(T["f2a"]), ff)
+        assert np.array_equal(h(T["se"]), o1.erase(er))
+        vv, ff = o1.retrieve(q1)
+        assert np.array_equal(h(T["r1"]), vv) and np.array_equal(h(T["f1"]), ff)
+        o2.insert(k2b, v2b)
+        vv, ff = o2.retrieve(q2)
+        assert np.array_equal(h(T["r2b"]), vv) and np.array_equal(h(T["f2b"]), ff)
+        assert t1.size() == o1.size() and t2.size() == o2.size()
+
+    b.launch()
+    torch.cuda.synchronize()
+    check()
+    b.capture()
+    for _ in range(2):
+        t1.clear()
+        t2.clear()
+        for name in ("s1", "r2a", "f2a", "se", "r1", "f1", "r2b", "f2b"):
+            T[name].fill_(0x5A)
+        torch.cuda.synchronize()
+        b.replay()
+        torch.cuda.synchronize()
+        check()
+    assert b.abandoned_waits() == 0
+    check_layout(t1, oracle.SINGLE)
+    b.close()
+
+
+def test_one_launch_many_tables_build_then_query(hc):
+    """40 single-value and 8 counting tables of every probing scheme (one group size and window),
+    built then queried in one gated launch, against the oracle per table."""
+    spec = gen.batched_tables_spec(48, 10, 17, 0.6, 0.95, 16, 321)
+    tabs, ops = [], []
+    for j, sp in enumerate(spec):
+        kind = "counting" if j % 6 == 5 else "single"
+        t = hc.Table(kind, sp["capacity"], scheme=["linear", "double", "quadratic"][j % 3], window=16, group=8,
+                     seed=sp["seed"])
+        w = gen.single_value_workload(t.capacity, sp["load"], sp["seed"])
+        k, q = d(w["keys"]), d(w["queries"])
+        v = d(w["values"]) if kind == "single" else None
+        st = torch.empty(k.numel(), dtype=torch.uint8, device="cuda")
+        vo = torch.empty(q.numel(), dtype=torch.uint32, device="cuda")
+        fo = torch.empty(q.numel(), dtype=torch.uint8, device="cuda")
+        ops.append((hc.hc_batch_op(t, hc.OP_INSERT, k, v, flags=st), [k, v, st]))
+        ops.append((hc.hc_batch_op(t, hc.OP_RETRIEVE, q, values_out=vo, flags=fo), [q, vo, fo]))
+        tabs.append((t, kind, w, st, vo, fo))
+    b = hc.Batch(ops, one_launch=True)
+    assert b.phases == 2 and b.launches == 1
+    b.launch()
+    torch.cuda.synchronize()
+    assert b.abandoned_waits() == 0
+    for t, kind, w, st, vo, fo in tabs:
+        orc = oracle.OracleTable(oracle.SINGLE if kind == "single" else oracle.COUNT, t.capacity)
+        assert np.array_equal(h(st), orc.insert(w["keys"], w["values"] if kind == "single" else None))
+        vv, ff = orc.retrieve(w["queries"])
+        assert np.array_equal(h(vo), vv) and np.array_equal(h(fo), ff)
+        assert t.size() == orc.size()
+    b.close()
+
+
+def test_one_launch_argument_errors(hc):
+    t1 = hc.Table("single", 1024, window=16, group=4)
+    t2 = hc.Table("single", 1024, window=8, group=4)
+    k = torch.ones(4, dtype=torch.uint32, device="cuda")
+    with pytest.raises(hc.HcError) as e:  # two windows
+        hc.hc_batch_create_flags([hc.hc_batch_op(t1, hc.OP_RETRIEVE, k), hc.hc_batch_op(t2, hc.OP_RETRIEVE, k)],
+                                 hc.HC_BATCH_ONE_LAUNCH)
+    assert e.value.code == hc.E_ARG
+    with pytest.raises(hc.HcError) as e:  # two group sizes
+        hc.hc_batch_create_flags([hc.hc_batch_op(t1, hc.OP_RETRIEVE, k),
+                                  hc.hc_batch_op(t1, hc.OP_RETRIEVE, k, group=8)], hc.HC_BATCH_ONE_LAUNCH)
+    assert e.value.code == hc.E_ARG
+    with pytest.raises(hc.HcError) as e:
+        hc.hc_batch_create_flags([hc.hc_batch_op(t1, hc.OP_RETRIEVE, k)], 6)
+    assert e.value.code == hc.E_ARG
+    b = hc.hc_batch_create_flags([], hc.HC_BATCH_ONE_LAUNCH)
+    hc.hc_batch_launch(b)
+    assert hc.hc_batch_abandoned_waits(b) == 0
+    hc.hc_batch_destroy(b)
