@@ -673,7 +673,7 @@ def bench_bucket(args):
     """Bucket list tables (s0 = 1, growth 2) on the multi-value workloads: 2^26 pairs with keys uniform on
     1..2^26/r, and 2^26 pairs Zipf(1.1) over 2^22 keys.  Insert (per pair and grouped), count + prefix sum,
     retrieve-all of every key; storage density = 4 bytes per distinct key and per value over the table's key slots,
-    last-bucket offsets and used pool words (a multi-value table of 2^27 slots holding the same pairs has
+    per-slot records and used pool words (a multi-value table of 2^27 slots holding the same pairs has
     4 (keys + 2^26) / 2^30)."""
     import numpy as np
     import torch
@@ -741,9 +741,10 @@ def bench_bucket(args):
         check(w, q, offs, out)
         u = t.bucket_usage()
         st = t.stats()
-        # stored information (each distinct key once, each value once, 32 bits each) over the table's key slots,
-        # last-bucket offsets and used pool words
-        density = (4.0 * (int(st["live"]) + n)) / (8.0 * t.capacity + 4.0 * t.capacity + 4.0 * u["pool_used"])
+        # stored information (each distinct key once, each value once, 32 bits each) over everything the table
+        # holds: key slots (8 B), per-slot records (16 B: last-bucket offset and insert bookkeeping) and used
+        # pool words
+        density = (4.0 * (int(st["live"]) + n)) / (8.0 * t.capacity + 16.0 * t.capacity + 4.0 * u["pool_used"])
         best_ins = min(row.get("insert_ms", 1e9), row["insert_grouped_ms"])
         row.update({"count_scan_ms": round(statistics.mean(cnt), 4), "write_ms": round(statistics.mean(wr), 4),
                     "insert_gops": round(n / best_ins / 1e6, 4),

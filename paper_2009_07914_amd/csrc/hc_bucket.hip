@@ -1,7 +1,7 @@
 // Bucket list hash table (Sec. IV-C).
 //
 // Each distinct key occupies one slot of a cooperative-probing table; the
-// slot's value half counts the key's values, and per slot `last` holds the pool
+// slot's value half counts the key's values, and a per-slot record holds the pool
 // offset of the key's last bucket.  Bucket i holds s_i values, s_0 given,
 // s_i = ceil(growth * s_{i-1}) up to a cap; every bucket but the first starts
 // with the pool offset of the bucket before it, so a list is walked from its
@@ -19,8 +19,9 @@
 //      holds the stamp and the batch's bucket offsets, so phases 2 and 3 find
 //      both in one line);
 //   2. the pair holding that first ticket takes the buckets the key's new tickets
-//      need from the pool in one allocation (one pool atomic per wavefront),
-//      links them (previous-bucket offsets) and moves `last`; if the pool is
+//      need from the pool in one allocation (one pool atomic per block),
+//      links them (previous-bucket offsets) and moves the last-bucket offset in the
+//      same record; if the pool is
 //      exhausted the count is cut back to what bucket 0 and the existing buckets
 //      hold;
 //   3. every pair writes its value where its ticket falls: ticket t lies in the
@@ -29,8 +30,8 @@
 //
 // Bucket 0 of the key in slot p is never allocated: it is the s_0 pool words at
 // p * s_0 (the first C * s_0 words of the pool are reserved for them; later buckets
-// come from the rest of the pool), and `last` is only read for keys with more than
-// one bucket.  So a pair of the per-pair insert that claims a new slot for its key --
+// come from the rest of the pool), and the last-bucket offset is only read for keys
+// with more than one bucket.  So a pair of the per-pair insert that claims a new slot for its key --
 // it holds ticket 0 -- stores its value right away and skips phases 2 and 3: for keys
 // seen once per batch (the common case at low multiplicity) the insert is one probe,
 // one claim and one store.  Later tickets of the same key find bucket 0 at p * s_0.
@@ -144,7 +145,7 @@ struct BlTicket {
     if (values == nullptr) return true;
     const uint64_t p = ln.g.bcast64(idx, r);
     if (ln.g.glane == 0) {
-      b.pool[p * b.s0] = v;  // `last` stays as it is: a key with one bucket has it at p * s0
+      b.pool[p * b.s0] = v;  // a key with one bucket has it at p * s0: no record to update
       st[i] = BL_PLACED;
       ++placed;
     }
@@ -263,9 +264,12 @@ __global__ __launch_bounds__(ALLOC_BLOCK) void k_bl_alloc(TableView t, BucketVie
     const uint64_t i = i0 + threadIdx.x;
     uint64_t p = 0, word = 0, b0 = 0, b1 = 0, a0 = 1, words = 0;
     bool mine = false;
+    uint32_t rec_last = 0;
     if (i < n && st[i] == ST_OK) {
       p = pos[i];
-      const uint64_t c0 = (uint32_t)b.meta[p].x;  // first ticket of this batch = count before it
+      const ulonglong2 rec = b.meta[p];
+      const uint64_t c0 = (uint32_t)rec.x;  // first ticket of this batch = count before it
+      rec_last = (uint32_t)rec.y;
       mine = ticket[i] == c0;
       if (mine) {
         word = t.slots[p];
@@ -297,9 +301,9 @@ __global__ __launch_bounds__(ALLOC_BLOCK) void k_bl_alloc(TableView t, BucketVie
     }
     __syncthreads();
     if (mine) {
-      const uint64_t home = p * b.s0;                             // bucket 0
-      const uint32_t old_last = b0 <= 1 ? (uint32_t)home : b.last[p];  // bucket a0 - 1
-      uint32_t first_new = 0xFFFFFFFFu;
+      const uint64_t home = p * b.s0;                                // bucket 0
+      const uint32_t old_last = b0 <= 1 ? (uint32_t)home : rec_last;  // bucket a0 - 1
+      uint32_t first_new = 0xFFFFFFFFu, new_last = old_last;
       if (b1 > a0) {
         const uint64_t base = b.bump + block_base + wave_off[wv] + incl - words;
         if (base + words > b.pool_cap || base + words > 0xFFFFFFFFull) {
@@ -314,11 +318,12 @@ __global__ __launch_bounds__(ALLOC_BLOCK) void k_bl_alloc(TableView t, BucketVie
             prev = o;
             o += bl_S(b, j + 1) - bl_S(b, j) + 1;
           }
-          b.last[p] = (uint32_t)prev;
+          new_last = (uint32_t)prev;
           first_new = (uint32_t)base;
         }
       }
-      b.meta[p].y = (uint64_t)old_last | ((uint64_t)first_new << 32);
+      // placement finds the old last bucket as the link word of the first new one
+      b.meta[p].y = (uint64_t)new_last | ((uint64_t)first_new << 32);
     }
     __syncthreads();  // wave_off and block_base are rewritten by the next round
   }
@@ -345,13 +350,16 @@ __global__ __launch_bounds__(256) void k_bl_place(TableView t, BucketView b, con
         code = ST_FULL;
       } else {
         // bucket 0 is the slot's own; a ticket below the batch's first new bucket lies in the key's
-        // last bucket before the batch; the others in the buckets allocated in phase 2
+        // last bucket before the batch (the link of the first new bucket, or the record's last
+        // bucket if the batch allocated none); the others in the buckets allocated in phase 2
         const uint64_t bi = bl_bucket_of(b, tk);
         uint64_t o = p * b.s0;
         if (bi >= 1) {
           const ulonglong2 mt = b.meta[p];
           const uint64_t b0 = bl_buckets(b, (uint32_t)mt.x);
-          o = (bi < b0) ? (uint32_t)mt.y : (mt.y >> 32) + bl_words(b, b0 > 1 ? b0 : 1, bi);
+          const uint32_t first_new = (uint32_t)(mt.y >> 32);
+          if (bi >= b0) o = first_new + bl_words(b, b0 > 1 ? b0 : 1, bi);
+          else o = first_new != 0xFFFFFFFFu ? b.pool[first_new] : (uint32_t)mt.y;
         }
         b.pool[o + (bi >= 1 ? 1 : 0) + (tk - bl_S(b, bi))] = values[i];
         ++stored;
@@ -432,7 +440,7 @@ struct BlProbe {
         return true;
       }
       uint64_t bi = bl_bucket_of(b, c - 1);
-      uint64_t o = bi == 0 ? p * b.s0 : b.last[p];  // one bucket: at p * s0
+      uint64_t o = bi == 0 ? p * b.s0 : (uint32_t)b.meta[p].y;  // one bucket: at p * s0
       for (;;) {
         const uint64_t lo = bl_S(b, bi), hi = bl_S(b, bi + 1) < c ? bl_S(b, bi + 1) : c;
         const uint64_t v0 = o + (bi >= 1 ? 1 : 0);
@@ -508,7 +516,7 @@ __global__ __launch_bounds__(1024) void k_bl_write_long(BucketView b, const uint
     const uint64_t i = long_list[3 * e], p = long_list[3 * e + 1], c = long_list[3 * e + 2];
     const uint64_t base = offsets[i], limit = offsets[i + 1] - base;
     uint64_t bi = bl_bucket_of(b, c - 1);
-    uint64_t o = bi == 0 ? p * b.s0 : b.last[p];  // one bucket: at p * s0
+    uint64_t o = bi == 0 ? p * b.s0 : (uint32_t)b.meta[p].y;  // one bucket: at p * s0
     for (;;) {
       const uint64_t lo = bl_S(b, bi), hi = bl_S(b, bi + 1) < c ? bl_S(b, bi + 1) : c;
       const uint64_t v0 = o + (bi >= 1 ? 1 : 0);
@@ -594,7 +602,13 @@ __global__ __launch_bounds__(64) void k_bl_zero1(unsigned long long* p) {
 
 __global__ __launch_bounds__(256) void k_bl_reset(ulonglong2* meta, uint64_t C) {
   const uint64_t stride = (uint64_t)gridDim.x * 256;
-  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < C; i += stride) meta[i] = make_ulonglong2(~0ull, 0ull);
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < C; i += stride) meta[i].x = ~0ull;
+}
+
+__global__ __launch_bounds__(256) void k_bl_dump_last(const ulonglong2* __restrict__ meta, uint64_t C,
+                                                      uint32_t* __restrict__ dst) {
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < C; i += stride) dst[i] = (uint32_t)meta[i].y;
 }
 
 // ---- host side ----------------------------------------------------------------------------
@@ -724,6 +738,11 @@ hc_err launch_bl_erase(const TableView& t, uint32_t G, uint32_t W, const uint32_
 hc_err launch_bl_reset(const BucketView& b, uint64_t C, hipStream_t s) {
   hipLaunchKernelGGL(k_bl_reset, dim3(stream_grid(C)), dim3(256), 0, s, b.meta, C);
   return check_launch("bucket list reset");
+}
+
+hc_err launch_bl_dump_last(const BucketView& b, uint64_t C, uint32_t* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_bl_dump_last, dim3(stream_grid(C)), dim3(256), 0, s, b.meta, C, dst);
+  return check_launch("bucket list dump");
 }
 
 }  // namespace hc

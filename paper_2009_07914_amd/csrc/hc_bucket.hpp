@@ -24,11 +24,11 @@ struct BucketView {
   uint64_t s0;                     // size of bucket 0: slot p's bucket 0 is the words [p * s0, (p + 1) * s0)
   uint64_t bump;                   // C * s0: later buckets are allocated from here on
   unsigned long long* pool_next;   // words allocated after `bump`
-  uint32_t* last;                  // per key slot: pool offset of the key's last bucket
-  // per key slot, one 16-byte record (the allocation reads the first word and writes the second,
-  // placement reads both: one line each):
-  //   stamp = (~batch << 32) | first ticket of the key in that batch
-  //   batch = old last bucket (low 32) | first new bucket (high 32)
+  // per key slot, one 16-byte record (the allocation reads and writes it, placement and the
+  // list walks read it: one line each):
+  //   stamp = (~batch << 32) | first ticket of the key in the latest batch that added to it
+  //   y = pool offset of the key's last bucket (low 32; meaningful once the key has more than
+  //       one bucket) | first bucket that batch allocated (high 32, ~0 if none)
   ulonglong2* meta;
   uint32_t epoch;                  // batch number (1 ..)
 };
@@ -75,7 +75,9 @@ hc_err launch_bl_write(const TableView& t, const BucketView& b, uint32_t G, uint
                        uint64_t n, const uint64_t* offsets, uint32_t* out, void* ws, hipStream_t s);
 hc_err launch_bl_erase(const TableView& t, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n, uint8_t* status,
                        hipStream_t s);
-// stamp of every slot = ~0 (a fill kernel).
+// stamp of every slot = ~0 (a fill kernel); the last-bucket offsets stay.
 hc_err launch_bl_reset(const BucketView& b, uint64_t C, hipStream_t s);
+// Last-bucket offset of every slot (the low words of the records) into dst[0..C).
+hc_err launch_bl_dump_last(const BucketView& b, uint64_t C, uint32_t* dst, hipStream_t s);
 
 }  // namespace hc

@@ -54,7 +54,6 @@ struct hc_table_s {
   uint32_t bl_m = 0, bl_smax = 0, bl_s0 = 1;
   uint32_t* d_pool = nullptr;
   uint64_t pool_cap = 0;
-  uint32_t* d_last = nullptr;
   ulonglong2* d_meta = nullptr;  // per slot: batch stamp, batch bucket offsets
   uint32_t epoch = 0;
 };
@@ -233,7 +232,6 @@ static BucketView bview_of(const hc_table_s* t) {
   b.s0 = t->bl_s0;
   b.bump = t->C * t->bl_s0;     // the first C * s0 words hold the slots' first buckets
   b.pool_next = t->d_size + 1;  // the size counter and the pool counter share one allocation
-  b.last = t->d_last;
   b.meta = t->d_meta;
   b.epoch = t->epoch;
   return b;
@@ -744,7 +742,6 @@ hc_err hc_create_bucket_list(hc_table* out, uint64_t key_capacity, const hc_para
   t->pool_cap = pool;
   hipError_t e = hipMalloc((void**)&t->d_cum, (m + 1) * sizeof(uint64_t));
   if (e == hipSuccess) e = hipMalloc((void**)&t->d_pool, pool * sizeof(uint32_t));
-  if (e == hipSuccess) e = hipMalloc((void**)&t->d_last, t->C * sizeof(uint32_t));
   if (e == hipSuccess) e = hipMalloc((void**)&t->d_meta, t->C * sizeof(ulonglong2));
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -792,10 +789,8 @@ hc_err hc_dump_buckets(hc_table t, uint32_t* d_pool_dst, uint32_t* d_last_dst, v
   if ((r = set_device(t)) != HC_OK) return r;
   hipError_t e = hipMemcpyAsync(d_pool_dst, t->d_pool, t->pool_cap * sizeof(uint32_t), hipMemcpyDeviceToDevice,
                                 (hipStream_t)stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(d_last_dst, t->d_last, t->C * sizeof(uint32_t), hipMemcpyDeviceToDevice, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "hc_dump_buckets");
-  return HC_OK;
+  return launch_bl_dump_last(bview_of(t), t->C, d_last_dst, (hipStream_t)stream);
 }
 
 hc_err hc_create_in(hc_table* out, uint32_t kind, void* d_slots, uint64_t slot_bytes, uint64_t capacity,
@@ -824,7 +819,7 @@ hc_err hc_destroy(hc_table t) {
   if (t->slots && t->owns_slots) (void)hipFree(t->slots);
   if (t->d_size) (void)hipFree(t->d_size);
   if (t->order_ev) (void)hipEventDestroy(t->order_ev);
-  for (void* q : {(void*)t->d_cum, (void*)t->d_pool, (void*)t->d_last, (void*)t->d_meta})
+  for (void* q : {(void*)t->d_cum, (void*)t->d_pool, (void*)t->d_meta})
     if (q) (void)hipFree(q);
   delete t;
   if (e != hipSuccess) return hip_fail(e, "hc_destroy: synchronise");
