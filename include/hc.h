@@ -44,6 +44,13 @@
  *     (hipMallocFromPoolAsync / hipFreeAsync): concurrent calls never share
  *     it and no call synchronises the device for it.  Freed blocks stay in
  *     the pool for later calls.  HC_E_NOMEM if the pool cannot grow.
+ *   - Work counters: every stream that launches on a device gets its own
+ *     pair of the library's work counters (the first 1024 streams per device;
+ *     beyond that pairs are shared round-robin), so any number of calls may be
+ *     in flight on different streams.  A graph captured from library calls uses
+ *     its capturing stream's counters: replay it on that stream, not beside
+ *     other work of that stream or beside another replay of itself (batch plans
+ *     own their counters instead, see hc_batch_capture).
  *   - Errors: every call returns hc_err; hc_last_error() gives a message for
  *     the calling thread's last failure.  No C++ exception crosses the ABI.
  *     A device fault inside a kernel is not recoverable by the library.

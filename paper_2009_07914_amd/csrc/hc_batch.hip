@@ -209,7 +209,7 @@ static hc_err launch_persistent(K k, const BatchDesc* d_descs, const uint64_t* d
   const uint64_t cap = (uint64_t)device_cu_count() * (uint64_t)blocks_per_cu(reinterpret_cast<const void*>(k));
   const uint64_t need = (total_chunks + (BLOCK / 64) - 1) / (BLOCK / 64);
   const unsigned grid = (unsigned)(need < cap ? need : cap);
-  WorkCtl ctl = work_for(0, 64, grid);
+  WorkCtl ctl = work_for(0, 64, grid, stream);
   if (counters != nullptr) ctl.counters = counters;
   hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, d_descs, d_chunk_start, ndesc, ctl, extra...);
   return check_launch("batch");

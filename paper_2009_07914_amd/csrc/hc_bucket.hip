@@ -225,7 +225,9 @@ __global__ __launch_bounds__(BLOCK) void k_bl_ticket(TableView t, WorkCtl ctl, B
   drive<G>(n_dev != nullptr ? *n_dev : n, ctl, op);
 }
 
-// Pair j of a sorted batch takes the ticket of its run plus its rank in the run.
+// Pair j of a sorted batch takes the ticket of its run plus its rank in the run; the
+// pairs after the first of a run only place their values (BL_FOLLOW), so the allocation
+// pass does the key's work once.
 // scan: exclusive scan of the run-start flags (scan[j + 1] - 1 = run of j).
 __global__ __launch_bounds__(256) void k_bl_expand(const uint64_t* __restrict__ scan,
                                                    const uint64_t* __restrict__ starts, uint64_t n,
@@ -236,7 +238,8 @@ __global__ __launch_bounds__(256) void k_bl_expand(const uint64_t* __restrict__ 
   const uint64_t stride = (uint64_t)gridDim.x * 256;
   for (uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += stride) {
     const uint64_t r = scan[j + 1] - 1;
-    st[j] = rst[r];
+    const uint8_t c = rst[r];
+    st[j] = (c == ST_OK && j != starts[r]) ? BL_FOLLOW : c;
     pos[j] = rpos[r];
     ticket[j] = rticket[r] + (uint32_t)(j - starts[r]);
   }
@@ -657,7 +660,7 @@ hc_err launch_bl_tickets(const TableView& t, const BucketView& b, uint32_t G, ui
     constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
     auto k = k_bl_ticket<GG, WW>;
     const unsigned grid = grid_for(k, n, GG);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n_dev ? n / 8 : n, GG, grid), b, keys, incr,
+    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n_dev ? n / 8 : n, GG, grid, s), b, keys, incr,
                        values, n, n_dev, pos, ticket, st);
     return check_launch("bucket list tickets");
   });
@@ -692,7 +695,7 @@ hc_err launch_bl_count(const TableView& t, uint32_t G, uint32_t W, const uint32_
     constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
     auto k = k_bl_probe<GG, WW, false>;
     const unsigned grid = grid_for(k, n, GG);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid), BucketView{}, keys, n, counts,
+    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid, s), BucketView{}, keys, n, counts,
                        offsets, nullptr, nullptr, nullptr);
     return check_launch("bucket list count");
   });
@@ -711,7 +714,7 @@ hc_err launch_bl_write(const TableView& t, const BucketView& b, uint32_t G, uint
     constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
     auto k = k_bl_probe<GG, WW, true>;
     const unsigned grid = grid_for(k, n, GG);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid), b, keys, n, nullptr,
+    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid, s), b, keys, n, nullptr,
                        const_cast<uint64_t*>(offsets), out, long_n, long_list);  // the write pass only reads offsets
     return check_launch("bucket list write");
   });
@@ -719,7 +722,7 @@ hc_err launch_bl_write(const TableView& t, const BucketView& b, uint32_t G, uint
   const uint64_t cap = (uint64_t)device_cu_count() * (uint64_t)blocks_per_cu_threads(
                            reinterpret_cast<const void*>(k_bl_write_long), 1024);
   const unsigned grid = (unsigned)(cap < n ? cap : (n ? n : 1));
-  hipLaunchKernelGGL(k_bl_write_long, dim3(grid), dim3(1024), 0, s, b, offsets, out, work_for(0, 64, grid * 4), long_n,
+  hipLaunchKernelGGL(k_bl_write_long, dim3(grid), dim3(1024), 0, s, b, offsets, out, work_for(0, 64, grid * 4, s), long_n,
                      long_list);
   return check_launch("bucket list long write");
 }
@@ -730,7 +733,7 @@ hc_err launch_bl_erase(const TableView& t, uint32_t G, uint32_t W, const uint32_
     constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
     auto k = k_bl_erase<GG, WW>;
     const unsigned grid = grid_for(k, n, GG);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid), keys, n, status);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid, s), keys, n, status);
     return check_launch("bucket list erase");
   });
 }

@@ -929,7 +929,7 @@ hc_err launch_grouped_insert(const TableView& t, int kind, uint32_t G, uint32_t 
       constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
       auto k = k_insert_counts<GG, WW>;
       const unsigned grid = grid_for(k, n, GG);
-      hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n / 8, GG, grid), kt, vt, flags + n);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n / 8, GG, grid, s), kt, vt, flags + n);
       return check_launch("insert counts");
     });
   }
@@ -942,13 +942,13 @@ hc_err launch_grouped_insert(const TableView& t, int kind, uint32_t G, uint32_t 
     for (int round = 0; round < IROUNDS; ++round) {
       hipLaunchKernelGGL(k_heavy_plan<WW>, dim3(1), dim3(GB), 0, s, t, kc, starts, heavy, nheavy, hs, round == 0);
       if (hc_err r = check_launch("heavy plan"); r != HC_OK) return r;
-      WorkCtl ctl = work_for(0, 64, rgrid * (GB / 256));
+      WorkCtl ctl = work_for(0, 64, rgrid * (GB / 256), s);
       hipLaunchKernelGGL(kr, dim3(rgrid), dim3(GB), 0, s, t, ctl, kc, vc, starts, heavy, nheavy, hs);
       if (hc_err r = check_launch("heavy round"); r != HC_OK) return r;
     }
     auto k = k_claim_runs<WW>;
     const unsigned grid = block_grid(reinterpret_cast<const void*>(k), ~0ull);
-    WorkCtl ctl = work_for(0, 64, grid * (GB / 256));  // a launch slot (counters 0..2 reset by the kernel)
+    WorkCtl ctl = work_for(0, 64, grid * (GB / 256), s);  // a launch slot (counters 0..2 reset by the kernel)
     hipLaunchKernelGGL(k, dim3(grid), dim3(GB), 0, s, t, ctl, kc, vc, starts, flags + n, heavy, nheavy, hs, medium,
                        nmedium, wo);
     return check_launch("claim runs");
@@ -958,7 +958,7 @@ hc_err launch_grouped_insert(const TableView& t, int kind, uint32_t G, uint32_t 
     constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
     auto k = k_claim_small<GG, WW>;
     const unsigned grid = grid_for(k, n, GG);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n / 8, GG, grid), kc, vc, starts, flags + n, wo);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n / 8, GG, grid, s), kc, vc, starts, flags + n, wo);
     return check_launch("claim short runs");
   });
   if (r != HC_OK) return r;
@@ -973,13 +973,13 @@ hc_err launch_grouped_insert(const TableView& t, int kind, uint32_t G, uint32_t 
     const uint32_t rounds = rounds_to_cover(t.P, GB * GB_SPL / WW);
     if (rounds > (uint32_t)QROUNDS_MAX) return fail(HC_E_ARG, "sequence too long for the find rounds");
     for (uint32_t round = 0; round < rounds; ++round) {
-      WorkCtl ctl = work_for(0, 64, grid * (GB / 256));
+      WorkCtl ctl = work_for(0, 64, grid * (GB / 256), s);
       hipLaunchKernelGGL(kr, dim3(grid), dim3(GB), 0, s, t, ctl, kc, starts, wk, round);
       if (hc_err e2 = check_launch("walk round"); e2 != HC_OK) return e2;
     }
     auto kc2 = k_walk_claim<WW>;
     const unsigned cgrid = block_grid(reinterpret_cast<const void*>(kc2), ~0ull);
-    WorkCtl ctl = work_for(0, 64, cgrid * (GB / 256));
+    WorkCtl ctl = work_for(0, 64, cgrid * (GB / 256), s);
     hipLaunchKernelGGL(kc2, dim3(cgrid), dim3(GB), 0, s, t, ctl, kc, vc, starts, wk);
     return check_launch("walk claim");
   });
@@ -1075,7 +1075,7 @@ hc_err launch_long_queries(const TableView& t, uint32_t W, int mode, const uint3
       const uint32_t rounds = rounds_to_cover(t.P, GB * GB_SPL / WW);
       if (rounds > (uint32_t)QROUNDS_MAX) return fail(HC_E_ARG, "sequence too long for the long-query rounds");
       for (uint32_t round = 0; round < rounds; ++round) {
-        WorkCtl ctl = work_for(0, 64, grid * (GB / 256));
+        WorkCtl ctl = work_for(0, 64, grid * (GB / 256), s);
         hipLaunchKernelGGL(kr, dim3(grid), dim3(GB), 0, s, t, ctl, keys, ls, round, offsets, out);
         if (hc_err e = check_launch("long round"); e != HC_OK) return e;
       }

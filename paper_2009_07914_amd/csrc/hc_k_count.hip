@@ -172,7 +172,7 @@ hc_err launch_count_insert(const TableView& t, uint32_t G, uint32_t W, const uin
     const uint64_t ntiles = (n + AGG_TILE - 1) / AGG_TILE;
     const uint64_t cap = (uint64_t)device_cu_count() * (uint64_t)blocks_per_cu(reinterpret_cast<const void*>(k));
     const unsigned grid = (unsigned)(ntiles < cap ? (ntiles ? ntiles : 1) : cap);
-    WorkCtl ctl = work_for(0, GG, grid);
+    WorkCtl ctl = work_for(0, GG, grid, stream);
     hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, t, ctl, keys, n, status);
     return check_launch("counting insert");
   });

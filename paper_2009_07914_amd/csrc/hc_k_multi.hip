@@ -11,7 +11,7 @@ hc_err launch_count_multi(const TableView& t, uint32_t G, uint32_t W, const uint
     constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
     auto k = k_count_multi<GG, WW>;
     const unsigned grid = grid_for(k, n, GG);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, t, work_for(n, GG, grid), keys, n, counts, offsets,
+    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, t, work_for(n, GG, grid, stream), keys, n, counts, offsets,
                        found_out, budget, long_list, long_n, long_cap);
     return check_launch("count_values");
   });
@@ -24,7 +24,7 @@ hc_err launch_write_multi(const TableView& t, uint32_t G, uint32_t W, const uint
     constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
     auto k = k_write_multi<GG, WW>;
     const unsigned grid = grid_for(k, n, GG);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, t, work_for(n, GG, grid), keys, n, offsets, out, budget,
+    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, t, work_for(n, GG, grid, stream), keys, n, offsets, out, budget,
                        long_list, long_n, long_cap);
     return check_launch("retrieve_all");
   });

@@ -10,7 +10,7 @@ hc_err launch_retrieve(const TableView& t, uint32_t G, uint32_t W, const uint32_
     constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
     auto k = k_retrieve<GG, WW>;
     const unsigned grid = grid_for(k, n, GG);
-      hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, t, work_for(n, GG, grid), keys, n, values_out, found_out);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, t, work_for(n, GG, grid, stream), keys, n, values_out, found_out);
     return check_launch("retrieve");
   });
 }
@@ -22,11 +22,11 @@ hc_err launch_erase(const TableView& t, int kind, uint32_t G, uint32_t W, const 
     if (kind == KIND_MULTI) {
       auto k = k_erase<GG, WW, KIND_MULTI>;
       const unsigned grid = grid_for(k, n, GG);
-      hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, t, work_for(n, GG, grid), keys, n, status);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, t, work_for(n, GG, grid, stream), keys, n, status);
     } else {
       auto k = k_erase<GG, WW, KIND_SINGLE>;
       const unsigned grid = grid_for(k, n, GG);
-      hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, t, work_for(n, GG, grid), keys, n, status);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, t, work_for(n, GG, grid, stream), keys, n, status);
     }
     return check_launch("erase");
   });

@@ -446,9 +446,13 @@ struct InsertUnique {
     if (status != nullptr && ln.g.glane == 0) status[i] = st;
     return true;
   }
-  __device__ __forceinline__ void update(uint64_t idx) {  // the key is present at idx
+  // The key is present at idx, whose word was seen as `seen`.  An upsert whose value is the one
+  // seen leaves the line clean: the result is that of this write ordered before any other write
+  // of the call to the key (any order of one call's writes is valid), and a hot key rewritten
+  // with its own value costs no atomics.
+  __device__ __forceinline__ void update(uint64_t idx, uint64_t seen) {
     if constexpr (KIND == KIND_COUNT) atomicAdd((unsigned long long*)&t.slots[idx], (unsigned long long)v << 32);
-    else atomicExch((unsigned long long*)&t.slots[idx], (unsigned long long)make_slot(k, v));
+    else if (slot_value(seen) != v) atomicExch((unsigned long long*)&t.slots[idx], (unsigned long long)make_slot(k, v));
   }
   // CAS a reusable slot: 1 claimed, 2 found the key there (updated), 3 lost to another key.
   __device__ __forceinline__ uint32_t claim(uint64_t idx, uint64_t expect) {
@@ -456,7 +460,7 @@ struct InsertUnique {
                                  (unsigned long long)make_slot(k, v));
     if (r == expect) { ++added; return 1; }
     ++fails;
-    if (slot_key(r) == k) { update(idx); return 2; }
+    if (slot_key(r) == k) { update(idx, r); return 2; }
     return 3;
   }
   __device__ __forceinline__ bool step() {
@@ -466,7 +470,8 @@ struct InsertUnique {
     load_step<G, W>(t, ln, s, lbase, k, win);
     const uint64_t b_match = g.bits(win.match != 0);
     if (b_match) {  // key present: update in place (Sec. IV-B3 duplicate warning)
-      if (g.glane == (uint32_t)ffs64(b_match)) update(win.first + lowbit(win.match));
+      if (g.glane == (uint32_t)ffs64(b_match))
+        update(win.first + lowbit(win.match), pick_lowest<SPL>(win.word, win.match));
       return done(ST_DUPLICATE);
     }
     const bool any_empty = g.bits(win.empty != 0) != 0;

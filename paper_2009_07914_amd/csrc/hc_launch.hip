@@ -63,16 +63,20 @@ int blocks_per_cu_threads(const void* kernel, int threads) {
 
 int blocks_per_cu(const void* kernel) { return blocks_per_cu_threads(kernel, BLOCK); }
 
-// Launch-slot ring: per device, LAUNCH_SLOTS pairs of work counters, one pair per
-// launch in round-robin order.  A launch's last wavefront resets its pair, so a
-// pair is free again once its launch has finished; launches that run
-// concurrently on one device (at most LAUNCH_SLOTS of them) use distinct pairs.
+// Launch slots: per device, LAUNCH_SLOTS pairs of work counters.  A launch's last
+// wavefront resets its pair, and the launches of one stream run one after another,
+// so every stream gets a pair of its own (the first LAUNCH_SLOTS streams that launch
+// on the device; the per-thread default stream counts once per thread): launches of
+// different streams never share a pair, however many of them are in flight.  Beyond
+// that many streams, pairs are handed out round-robin over the whole ring.
 constexpr uint32_t LAUNCH_SLOTS = 1024;
 constexpr uint32_t SLOT_WORDS = 16;  // 128 bytes per pair: no two pairs share a cache line
 
 struct DeviceRing {
   unsigned long long* d_ring = nullptr;
-  std::atomic<uint32_t> next{0};
+  std::mutex mu;
+  std::unordered_map<uint64_t, uint32_t> of_stream;  // stream key -> pair
+  uint32_t next = 0;                                 // round-robin once every pair is taken
 };
 static DeviceRing g_rings[64];
 static std::mutex g_ring_mu;
@@ -140,11 +144,33 @@ void ws_release(void* p, hipStream_t s) {
   if (p != nullptr && hipFreeAsync(p, s) != hipSuccess) (void)hipGetLastError();
 }
 
-WorkCtl work_for(uint64_t n, int G, unsigned grid) {
+// A key per stream: the handle, or for the per-thread default stream the calling thread
+// (each thread has its own such stream).
+static uint64_t stream_key(hipStream_t s) {
+  if (s != hipStreamPerThread) return (uint64_t)(uintptr_t)s;
+  static std::atomic<uint64_t> threads{0};
+  thread_local const uint64_t mine = (1ull << 63) | threads.fetch_add(1);
+  return mine;
+}
+
+WorkCtl work_for(uint64_t n, int G, unsigned grid, hipStream_t s) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   DeviceRing& r = g_rings[dev];
-  const uint32_t slot = r.next.fetch_add(1, std::memory_order_relaxed) % LAUNCH_SLOTS;
+  uint32_t slot;
+  {
+    std::lock_guard<std::mutex> lock(r.mu);
+    const uint64_t key = stream_key(s);
+    auto it = r.of_stream.find(key);
+    if (it != r.of_stream.end()) {
+      slot = it->second;
+    } else if (r.of_stream.size() < LAUNCH_SLOTS) {
+      slot = (uint32_t)r.of_stream.size();
+      r.of_stream.emplace(key, slot);
+    } else {
+      slot = r.next++ % LAUNCH_SLOTS;
+    }
+  }
   WorkCtl c;
   c.counters = r.d_ring + (size_t)slot * SLOT_WORDS;
   const uint64_t gpw = 64 / G;  // groups per wavefront

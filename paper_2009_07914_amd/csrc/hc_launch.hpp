@@ -67,10 +67,10 @@ inline unsigned grid_for(Kernel kernel, uint64_t n, int G) {
   return (unsigned)(g == 0 ? 1 : g);
 }
 
-// Work control of one launch: counters from the device's launch-slot ring and a
-// chunk size giving every wavefront about two chunks, between one element per
-// group and 64 elements per group.
-WorkCtl work_for(uint64_t n, int G, unsigned grid);
+// Work control of one launch on stream s: the stream's counter pair from the device's
+// launch slots and a chunk size giving every wavefront about two chunks, between one
+// element per group and 64 elements per group.
+WorkCtl work_for(uint64_t n, int G, unsigned grid, hipStream_t s);
 
 hc_err check_launch(const char* what);
 

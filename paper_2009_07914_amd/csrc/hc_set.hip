@@ -274,15 +274,15 @@ hc_err launch_set(int op, const TableView& t, uint32_t G, uint32_t W, const uint
       if (op == SET_INSERT) {
         auto k = k_set_insert<GG, WW>;
         const unsigned grid = grid_for(k, n, GG);
-        hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid), keys, n, flags);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid, s), keys, n, flags);
       } else if (op == SET_CONTAINS) {
         auto k = k_set_contains<GG, WW>;
         const unsigned grid = grid_for(k, n, GG);
-        hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid), keys, n, flags);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid, s), keys, n, flags);
       } else {
         auto k = k_set_erase<GG, WW>;
         const unsigned grid = grid_for(k, n, GG);
-        hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid), keys, n, flags);
+        hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid, s), keys, n, flags);
       }
       return check_launch("hash set");
     }

@@ -364,15 +364,15 @@ static hc_err launch_wide_layout(int op, const TableView& t, uint32_t G, uint32_
     if (op == WIDE_INSERT) {
       auto k = k_wide_insert<GG, WW, SOA>;
       const unsigned grid = grid_for(k, n, GG);
-      hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid), keys, values, n, flags);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid, s), keys, values, n, flags);
     } else if (op == WIDE_RETRIEVE) {
       auto k = k_wide_retrieve<GG, WW, SOA>;
       const unsigned grid = grid_for(k, n, GG);
-      hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid), keys, n, values_out, flags);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid, s), keys, n, values_out, flags);
     } else {
       auto k = k_wide_erase<GG, WW, SOA>;
       const unsigned grid = grid_for(k, n, GG);
-      hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid), keys, n, flags);
+      hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid, s), keys, n, flags);
     }
     return check_launch("64-bit table");
   });

@@ -147,3 +147,43 @@ def test_cas_fails_counter(hc):
     assert 0 < fails
     t.clear()
     assert t.stats()["cas_fails"] == 0 and t.size() == 0
+
+
+def test_many_launches_beside_a_long_one(hc):
+    """Each stream has work counters of its own: while long retrieves run on one stream, more small
+    launches than the device has counter pairs run on another, and both stay exact."""
+    big = hc.Table("single", 1 << 25, scheme="double", window=16, group=4)
+    w = gen.single_value_workload(big.capacity, 0.9, 61)
+    big.insert(d(w["keys"]), d(w["values"]))
+    small = hc.Table("single", 1 << 12, scheme="linear", window=8, group=2)
+    ws = gen.single_value_workload(small.capacity, 0.8, 62)
+    small.insert(d(ws["keys"]), d(ws["values"]))
+    torch.cuda.synchronize()
+    q = d(np.concatenate([w["queries"]] * 4))
+    qs = d(ws["queries"])
+    a, b = torch.cuda.Stream(), torch.cuda.Stream()
+    outs_a, outs_b = [], []
+    for rep in range(3):
+        v = torch.empty(q.numel(), dtype=torch.uint32, device="cuda")
+        f = torch.empty(q.numel(), dtype=torch.uint8, device="cuda")
+        hc.hc_retrieve(big.handle, q, v, f, 0, a)
+        outs_a.append((v, f))
+    for j in range(1200):
+        v = torch.empty(qs.numel(), dtype=torch.uint32, device="cuda")
+        f = torch.empty(qs.numel(), dtype=torch.uint8, device="cuda")
+        hc.hc_retrieve(small.handle, qs, v, f, 0, b)
+        if j % 200 == 199:
+            outs_b.append((v, f))
+    torch.cuda.synchronize()
+    src = w["query_src"]
+    present = src < w["n"]
+    for v, f in outs_a:
+        v, f = h(v).reshape(4, -1), h(f).reshape(4, -1)
+        for r in range(4):
+            assert np.array_equal(f[r].astype(bool), present)
+            assert np.array_equal(v[r][present], w["values"][src[present].astype(np.int64)])
+    o = oracle.OracleTable(oracle.SINGLE, small.capacity)
+    o.insert(ws["keys"], ws["values"])
+    vo, fo = o.retrieve(ws["queries"])
+    for v, f in outs_b:
+        assert np.array_equal(h(v), vo) and np.array_equal(h(f), fo)

@@ -124,6 +124,42 @@ def test_in_batch_duplicates_and_upsert(hc):
     check_layout(t, oracle.SINGLE)
 
 
+@pytest.mark.parametrize("group", [1, 4, 16])
+def test_upsert_of_the_stored_value(hc, group):
+    """Upserts that rewrite a key's stored value leave it (no write needed), the others replace it:
+    re-inserting every pair with half the values changed gives exactly the new values, all DUPLICATE;
+    2^21 copies of hot keys rewriting their own values beside a few copies with new values end on one
+    of the call's values per key (any order of one call's writes is valid), with exact statuses."""
+    t = hc.Table("single", 1 << 15, scheme="double", window=16, group=group)
+    w = gen.single_value_workload(t.capacity, 0.8, 31)
+    keys, vals = w["keys"], w["values"]
+    orc = oracle.OracleTable(oracle.SINGLE, t.capacity)
+    assert np.array_equal(h(t.insert(d(keys), d(vals), status=True)), orc.insert(keys, vals))
+    nv = vals.copy()
+    nv[::2] = gen.values(32, nv[::2].size)
+    st = h(t.insert(d(keys), d(nv), status=True))
+    assert np.array_equal(st, orc.insert(keys, nv)) and (st == hc.S_DUPLICATE).all()
+    q = w["queries"]
+    vo, fo = orc.retrieve(q)
+    v, f = t.retrieve(d(q))
+    assert np.array_equal(h(v), vo) and np.array_equal(h(f), fo)
+    # hot keys: 2^21 copies of 8 stored keys with their own values, 64 copies with new values
+    hot, hot_v = keys[:8], nv[:8]
+    pick = gen.uniform(33, 0, 7, 1 << 21).astype(np.int64)
+    hk, hv = hot[pick], hot_v[pick].copy()
+    fresh = gen.values(34, 64)
+    hv[:64] = fresh
+    perm = gen.permutation(35, hk.size).astype(np.int64)
+    hk, hv = hk[perm], hv[perm]
+    st = h(t.insert(d(hk), d(hv), status=True))
+    assert (st == hc.S_DUPLICATE).all() and t.size() == orc.size()
+    v, f = t.retrieve(d(hot))
+    assert h(f).all()
+    for i, k in enumerate(hot):
+        assert h(v)[i] in set(hv[hk == k].tolist())
+    check_layout(t, oracle.SINGLE)
+
+
 def test_reserved_keys_and_empty_batch(hc):
     t = hc.Table("single", 1024, window=16)
     keys = np.array([0, 5, 0xFFFFFFFF, 6], dtype=np.uint32)
