@@ -717,16 +717,24 @@ def bench_bucket(args):
             assert np.array_equal(np.sort(o[off[qi]:off[qi + 1]]), sv[lo:hi]), "segment disagrees"
 
     res = {}
-    cases = [(f"uniform_r{r}", gen.multi_value_uniform_r_workload(n, r, gen.SEED_BASE + 20 + r), n // r)
-             for r in (1, 4, 16, 64)]
-    cases.append(("zipf", gen.multi_value_zipf_workload(n, 1 << 22, 1.1, gen.SEED_BASE + 3), 1 << 22))
-    for name, w, distinct in cases:
+    grow2 = dict(s0=1, growth=2.0, smax=1 << 16)
+    cases = [(f"uniform_r{r}", r, grow2) for r in (1, 4, 16, 64)]
+    cases.append(("zipf", 0, grow2))
+    # the paper's two settings: its default (growth 1.1 from s0 = 1) and its best case (one bucket of
+    # s0 = the values per key, growth 1)
+    cases += [(f"paper_default_r{r}", r, dict(s0=1, growth=1.1, smax=1 << 16)) for r in (1, 4, 16, 64)]
+    cases += [(f"paper_optimal_r{r}", r, dict(s0=r, growth=1.0, smax=r)) for r in (4, 16, 64)]
+    for name, r, bparams in cases:
+        if r:
+            w, distinct = gen.multi_value_uniform_r_workload(n, r, gen.SEED_BASE + 20 + r), n // r
+        else:
+            w, distinct = gen.multi_value_zipf_workload(n, 1 << 22, 1.1, gen.SEED_BASE + 3), 1 << 22
         keys = torch.from_numpy(w["keys"]).to(dev)
         vals = torch.from_numpy(w["values"]).to(dev)
         q = torch.from_numpy(w["queries"]).to(dev)
         cap = int(distinct / 0.8)
         t = hc.Table("bucket", cap, scheme="double", window=16, group=4, device=dev,
-                     bucket=dict(s0=1, growth=2.0, smax=1 << 16, pool_values=3 * n))
+                     bucket=dict(bparams, pool_values=3 * n))
         row = {}
         if name != "zipf":  # per pair: the Zipf batch's hottest key would take 8 M atomics on one slot
             ins = ev_time((t.clear, lambda: hc.hc_insert(t.handle, keys, vals, None, 4, s)), reps)[args.warmup:]
@@ -751,6 +759,7 @@ def bench_bucket(args):
                     "retrieve_all_gops": round(n / (statistics.mean(cnt) + statistics.mean(wr)) / 1e6, 4),
                     "keys": int(st["live"]), "pool_used_words": int(u["pool_used"]),
                     "storage_density": round(density, 4)})
+        row["bucket"] = f"s0 {bparams['s0']}, growth {bparams['growth']}, smax {bparams['smax']}"
         res[name] = row
         print("# " + json.dumps({name: row}), flush=True)
         del t, keys, vals, q, offs, out, w
@@ -760,8 +769,9 @@ def bench_bucket(args):
         "value": res["zipf"]["retrieve_all_gops"], "unit": "G ops/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": "bucket list tables (s0 1, growth 2, cap 2^16) for 2^26 uint32 pairs: keys uniform on "
-                               "1..2^26/r, and Zipf(1.1) over 2^22 keys; key table at load 0.8 of the distinct keys",
+        "config": {"workload": "bucket list tables (s0 1, growth 2, cap 2^16; and the paper's default growth 1.1 "
+                               "and its one-bucket setting) for 2^26 uint32 pairs: keys uniform on 1..2^26/r, and "
+                               "Zipf(1.1) over 2^22 keys; key table at load 0.8 of the distinct keys",
                    "pairs": n},
         "modes": res,
     }

@@ -83,7 +83,8 @@ def _parity(t, orc, queries):
 
 
 @pytest.mark.parametrize("bucket", [dict(s0=1, growth=2.0, smax=1 << 16), dict(s0=4, growth=1.5, smax=64),
-                                    dict(s0=8, growth=1.0, smax=8), dict(s0=2, growth=3.0, smax=1000)])
+                                    dict(s0=8, growth=1.0, smax=8), dict(s0=2, growth=3.0, smax=1000),
+                                    dict(s0=1, growth=1.1, smax=1 << 16)])
 @pytest.mark.parametrize("group", [1, 4, 16])
 def test_bucket_list_batches_match_oracle(hc, bucket, group):
     """Zipf(1.1) pairs in four batches (lists grow across batches and within one)."""
