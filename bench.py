@@ -47,6 +47,8 @@ def _parse():
     ap.add_argument("--requests", type=int, default=1500)
     ap.add_argument("--max-log2-request", type=int, default=24)
     ap.add_argument("--zipf", action="store_true", help="serving: Zipf(1.1) keys instead of uniform")
+    ap.add_argument("--max-group-ops", type=int, default=1 << 22, help="serving: most elements per launch group (0: any)")
+    ap.add_argument("--server-streams", type=int, default=3, help="serving: streams of the server")
     ap.add_argument("--tables", type=int, default=256)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
@@ -1179,7 +1181,8 @@ def bench_serving(args):
     def run(serial, rate):
         """Submit the stream at Poisson times of `rate` requests/s (0: all at once)."""
         reset()
-        srv = hc.Server(staging_bytes=4 << 30, serial=serial)
+        srv = hc.Server(staging_bytes=4 << 30, serial=serial, max_group_ops=args.max_group_ops,
+                        streams=args.server_streams)
         gaps = rng.exponential(1.0 / rate, len(host)) if rate > 0 else np.zeros(len(host))
         arrivals = np.cumsum(gaps)
         tickets = []
@@ -1235,7 +1238,8 @@ def bench_serving(args):
                                + ("Zipf(1.1) insert and retrieve keys (over each table's first 2^22 keys)"
                                   if args.zipf else "uniform keys (inserts of fresh keys)")
                                + "; Poisson arrivals",
-                   "requests": len(host), "ops": total_ops, "host_buffers": "pinned"},
+                   "requests": len(host), "ops": total_ops, "host_buffers": "pinned",
+                   "max_group_ops": args.max_group_ops, "server_streams": args.server_streams},
         "modes": {k: fmt(v) for k, v in res.items()},
         "serial_rate_req_per_s": round(base_rate, 2),
     }

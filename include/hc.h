@@ -529,7 +529,8 @@ typedef struct hc_server_s* hc_server;
 typedef struct {
   uint64_t staging_bytes;       /* device staging ring = admission budget (>= 1 MiB); at most half
                                    the HBM free at creation (a larger request is cut to that) */
-  uint64_t max_group_ops;       /* most elements coalesced into one launch group; 0 = no limit */
+  uint64_t max_group_ops;       /* most elements coalesced into one launch group (a larger request
+                                   forms a group alone); 0 = no limit */
   uint32_t max_group_requests;  /* most requests per launch group; 0 = 1024 */
   uint32_t streams;             /* streams rotated over launch groups; 0 = 3 */
   uint32_t serial;              /* 1: one request at a time, each waiting for the previous one */
@@ -552,7 +553,7 @@ typedef struct {
   uint64_t staging_bytes;       /* the admission budget in use (staging ring size) */
 } hc_server_counts;
 
-/* Defaults: 1 GiB staging, no element limit, 1024 requests per group, 3 streams. */
+/* Defaults: 1 GiB staging, 2^22 elements and 1024 requests per group, 3 streams. */
 void hc_default_server_params(hc_server_params* params);
 
 /* Create a server on the current device (allocates its staging ring, streams and a

@@ -574,7 +574,7 @@ def hc_server_destroy(server: int):
 class Server:
     """Continuous-batching server; keeps each request's host tensors alive until it completes."""
 
-    def __init__(self, staging_bytes=1 << 30, max_group_ops=0, max_group_requests=1024, streams=3, serial=False):
+    def __init__(self, staging_bytes=1 << 30, max_group_ops=1 << 22, max_group_requests=1024, streams=3, serial=False):
         p = hc_default_server_params()
         p.staging_bytes, p.max_group_ops = staging_bytes, max_group_ops
         p.max_group_requests, p.streams, p.serial = max_group_requests, streams, int(serial)

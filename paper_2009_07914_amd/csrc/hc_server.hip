@@ -323,7 +323,7 @@ extern "C" {
 void hc_default_server_params(hc_server_params* p) {
   if (!p) return;
   p->staging_bytes = 1ull << 30;
-  p->max_group_ops = 0;
+  p->max_group_ops = 1ull << 22;  // a small request waits behind at most about 4 M elements
   p->max_group_requests = 1024;
   p->streams = 3;
   p->serial = 0;
