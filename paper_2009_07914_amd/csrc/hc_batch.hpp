@@ -85,10 +85,13 @@ struct PlanHost {
 // phase in one gated launch (every operation must have the same group size and window).
 hc_err build_plan(const hc_batch_op* ops, uint32_t count, int dev, PlanHost* out, bool one_launch = false);
 
-// Words of a plan's counter block: the launches' counter pairs, then (one-launch plans) a
-// line holding the abandoned-wait count, then the completion counters.
+// Words of a plan's counter block: the launches' counter pairs, then (one-launch plans, with
+// or without completion counters) a line holding the abandoned-wait count, then the
+// completion counters.
 inline uint64_t plan_counter_words(const PlanHost& p) {
-  return (uint64_t)p.launches.size() * PLAN_COUNTER_STRIDE + (p.gates ? PLAN_COUNTER_STRIDE + p.gates : 0);
+  bool one = false;
+  for (const PlanLaunch& L : p.launches) one |= L.op == BATCH_ALL;
+  return (uint64_t)p.launches.size() * PLAN_COUNTER_STRIDE + (one ? PLAN_COUNTER_STRIDE + p.gates : 0);
 }
 
 // Enqueue a plan whose descriptors and chunk starts are in device memory.  counters:

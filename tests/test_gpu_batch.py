@@ -470,3 +470,31 @@ def test_one_launch_argument_errors(hc):
     hc.hc_batch_launch(b)
     assert hc.hc_batch_abandoned_waits(b) == 0
     hc.hc_batch_destroy(b)
+
+
+def test_one_launch_single_phase(hc):
+    """A one-launch plan with one phase has no completion counters to wait on: inserts into two
+    tables, then the same plan relaunched after a clear, against the oracle."""
+    tabs, ops = [], []
+    for j in range(2):
+        t = hc.Table("single", 1 << 13, scheme="double", window=16, group=4)
+        w = gen.single_value_workload(t.capacity, 0.9, 700 + j)
+        k, v = d(w["keys"]), d(w["values"])
+        st = torch.empty(k.numel(), dtype=torch.uint8, device="cuda")
+        ops.append((hc.hc_batch_op(t, hc.OP_INSERT, k, v, flags=st), [k, v, st]))
+        tabs.append((t, w, st))
+    b = hc.Batch(ops, one_launch=True)
+    assert b.phases == 1 and b.launches == 1
+    for rep in range(2):
+        for t, _, _ in tabs:
+            t.clear()
+        b.launch()
+        torch.cuda.synchronize()
+        assert b.abandoned_waits() == 0
+        for t, w, st in tabs:
+            orc = oracle.OracleTable(oracle.SINGLE, t.capacity)
+            assert np.array_equal(h(st), orc.insert(w["keys"], w["values"]))
+            v, f = t.retrieve(d(w["queries"]))
+            vo, fo = orc.retrieve(w["queries"])
+            assert np.array_equal(h(v), vo) and np.array_equal(h(f), fo)
+    b.close()
