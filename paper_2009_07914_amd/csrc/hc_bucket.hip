@@ -13,28 +13,28 @@
 // waiting, and leaves the same lists:
 //   1. every pair probes for its key (claiming a slot with count 1 if absent,
 //      else adding 1 to the count with one 64-bit atomic): the count before the
-//      add is the pair's ticket, its rank among all values of the key.  The first
-//      ticket of each key in the batch is recorded with an atomic minimum on a
-//      per-slot stamp tagged with the batch number (a 16-byte per-slot record
-//      holds the stamp and the batch's bucket offsets, so phases 2 and 3 find
-//      both in one line);
-//   2. the pair holding that first ticket takes the buckets the key's new tickets
-//      need from the pool in one allocation (one pool atomic per block),
-//      links them (previous-bucket offsets) and moves the last-bucket offset in the
-//      same record; if the pool is
-//      exhausted the count is cut back to what bucket 0 and the existing buckets
-//      hold;
+//      add is the pair's ticket, its rank among all values of the key;
+//   2. the pair holding the key's last ticket of the batch (its ticket is the
+//      count after the batch minus one, read from the slot) takes the buckets the
+//      batch's tickets need from the pool in one allocation (one pool atomic per
+//      block), links them (previous-bucket offsets) and updates the slot's 16-byte
+//      record: buckets held, buckets held before the batch, last bucket and first
+//      new bucket.  If the pool is exhausted the record says so, and the key keeps
+//      what its existing buckets hold;
 //   3. every pair writes its value where its ticket falls: ticket t lies in the
-//      bucket i with S(i) <= t < S(i+1), S(i) = s_0 + ... + s_{i-1}.
-// Values of a key therefore appear in its list in ticket order.
+//      bucket i with S(i) <= t < S(i+1), S(i) = s_0 + ... + s_{i-1}; the record
+//      of its slot gives the bucket's offset.
+// Values of a key therefore appear in its list in ticket order.  A record says
+// "no buckets yet" after hc_clear and after the key in its slot is erased, so a
+// key that claims a slot finds it so without writing it.
 //
 // Bucket 0 of the key in slot p is never allocated: it is the s_0 pool words at
 // p * s_0 (the first C * s_0 words of the pool are reserved for them; later buckets
-// come from the rest of the pool), and the last-bucket offset is only read for keys
-// with more than one bucket.  So a pair of the per-pair insert that claims a new slot for its key --
-// it holds ticket 0 -- stores its value right away and skips phases 2 and 3: for keys
-// seen once per batch (the common case at low multiplicity) the insert is one probe,
-// one claim and one store.  Later tickets of the same key find bucket 0 at p * s_0.
+// come from the rest of the pool), and the record is only read for keys with more
+// than one bucket.  So a pair of the per-pair insert that claims a new slot for its
+// key -- it holds ticket 0 -- stores its value right away and skips phases 2 and 3:
+// for keys seen once per batch (the common case at low multiplicity) the insert is
+// one probe, one claim and one store.
 #include <cmath>
 
 #include "hc_bucket.hpp"
@@ -115,9 +115,7 @@ struct BlTicket {
   __device__ __forceinline__ void record(uint64_t idx, uint32_t tk) {
     pos[i] = idx;
     ticket[i] = tk;
-    const unsigned long long mine = ((unsigned long long)(~b.epoch) << 32) | tk;  // older batches compare larger
-    // a smaller stamp already there is a smaller ticket of this batch: not the key's allocator
-    st[i] = atomicMin(&b.meta[idx].x, mine) < mine ? BL_FOLLOW : ST_OK;
+    st[i] = ST_OK;
   }
   __device__ __forceinline__ void add_one(uint64_t idx) {  // `inc` more values (tickets old .. old + inc - 1)
     const uint64_t old = atomicAdd((unsigned long long*)&t.slots[idx], (unsigned long long)inc << 32);
@@ -226,8 +224,8 @@ __global__ __launch_bounds__(BLOCK) void k_bl_ticket(TableView t, WorkCtl ctl, B
 }
 
 // Pair j of a sorted batch takes the ticket of its run plus its rank in the run; the
-// pairs after the first of a run only place their values (BL_FOLLOW), so the allocation
-// pass does the key's work once.
+// pairs before the last of a run only place their values (BL_FOLLOW), so the allocation
+// pass reads the key's slot once, for the pair holding its last ticket.
 // scan: exclusive scan of the run-start flags (scan[j + 1] - 1 = run of j).
 __global__ __launch_bounds__(256) void k_bl_expand(const uint64_t* __restrict__ scan,
                                                    const uint64_t* __restrict__ starts, uint64_t n,
@@ -239,7 +237,7 @@ __global__ __launch_bounds__(256) void k_bl_expand(const uint64_t* __restrict__ 
   for (uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += stride) {
     const uint64_t r = scan[j + 1] - 1;
     const uint8_t c = rst[r];
-    st[j] = (c == ST_OK && j != starts[r]) ? BL_FOLLOW : c;
+    st[j] = (c == ST_OK && j + 1 != starts[r + 1]) ? BL_FOLLOW : c;
     pos[j] = rpos[r];
     ticket[j] = rticket[r] + (uint32_t)(j - starts[r]);
   }
@@ -256,7 +254,7 @@ constexpr int ALLOC_BLOCK = 1024;
 __global__ __launch_bounds__(ALLOC_BLOCK) void k_bl_alloc(TableView t, BucketView b, uint64_t n,
                                                           const uint64_t* __restrict__ pos,
                                                           const uint32_t* __restrict__ ticket,
-                                                          const uint8_t* __restrict__ st) {
+                                                          uint8_t* __restrict__ st) {
   constexpr int NW = ALLOC_BLOCK / 64;
   __shared__ unsigned long long wave_off[NW];
   __shared__ unsigned long long block_base;
@@ -265,21 +263,21 @@ __global__ __launch_bounds__(ALLOC_BLOCK) void k_bl_alloc(TableView t, BucketVie
   // the trip count depends only on blockIdx, so every thread of a block reaches each barrier
   for (uint64_t i0 = (uint64_t)blockIdx.x * ALLOC_BLOCK; i0 < n; i0 += stride) {
     const uint64_t i = i0 + threadIdx.x;
-    uint64_t p = 0, word = 0, b0 = 0, b1 = 0, a0 = 1, words = 0;
+    uint64_t p = 0, b1 = 0, bp = 1, words = 0;
+    uint32_t old_last = 0;
     bool mine = false;
-    uint32_t rec_last = 0;
     if (i < n && st[i] == ST_OK) {
       p = pos[i];
-      const ulonglong2 rec = b.meta[p];
-      const uint64_t c0 = (uint32_t)rec.x;  // first ticket of this batch = count before it
-      rec_last = (uint32_t)rec.y;
-      mine = ticket[i] == c0;
+      // the count after phase 1 (nothing changes it before phase 3): its last ticket allocates
+      const uint64_t c1 = slot_value(t.slots[p]);
+      mine = (uint64_t)ticket[i] + 1 == c1;
       if (mine) {
-        word = t.slots[p];
-        b0 = bl_buckets(b, c0);
-        b1 = bl_buckets(b, slot_value(word));  // count after phase 1
-        a0 = b0 > 1 ? b0 : 1;                   // bucket 0 is the slot's own, never allocated
-        words = b1 > a0 ? bl_words(b, a0, b1) : 0;
+        const ulonglong2 rec = b.meta[p];
+        const uint32_t held = (uint32_t)rec.x;  // buckets before this batch (0 or 1: bucket 0 only)
+        bp = held > 1 ? held : 1;                // bucket 0 is the slot's own, never allocated
+        old_last = held > 1 ? (uint32_t)rec.y : (uint32_t)(p * b.s0);
+        b1 = bl_buckets(b, c1);
+        words = b1 > bp ? bl_words(b, bp, b1) : 0;
       }
     }
     // inclusive scan of the words over the wavefront, then over the block's wavefronts
@@ -304,29 +302,25 @@ __global__ __launch_bounds__(ALLOC_BLOCK) void k_bl_alloc(TableView t, BucketVie
     }
     __syncthreads();
     if (mine) {
-      const uint64_t home = p * b.s0;                                // bucket 0
-      const uint32_t old_last = b0 <= 1 ? (uint32_t)home : rec_last;  // bucket a0 - 1
-      uint32_t first_new = 0xFFFFFFFFu, new_last = old_last;
-      if (b1 > a0) {
+      uint32_t first_new = BL_NONE, new_last = old_last, held = (uint32_t)bp;
+      if (b1 > bp) {
         const uint64_t base = b.bump + block_base + wave_off[wv] + incl - words;
         if (base + words > b.pool_cap || base + words > 0xFFFFFFFFull) {
-          // pool exhausted: keep what bucket 0 and the existing buckets hold
-          atomicExch((unsigned long long*)&t.slots[p],
-                     (unsigned long long)make_slot(slot_key(word), (uint32_t)bl_S(b, a0)));
-          atomicOr(t.size + CTR_BL_CUT, 1ull);  // placement must check tickets against the counts
+          first_new = BL_CUT;  // pool exhausted: the key keeps what its bp buckets hold (phase 3)
         } else {
           uint64_t o = base, prev = old_last;
-          for (uint64_t j = a0; j < b1; ++j) {  // every allocated bucket starts with its link
+          for (uint64_t j = bp; j < b1; ++j) {  // every allocated bucket starts with its link
             b.pool[o] = (uint32_t)prev;
             prev = o;
             o += bl_S(b, j + 1) - bl_S(b, j) + 1;
           }
           new_last = (uint32_t)prev;
           first_new = (uint32_t)base;
+          held = (uint32_t)b1;
         }
       }
-      // placement finds the old last bucket as the link word of the first new one
-      b.meta[p].y = (uint64_t)new_last | ((uint64_t)first_new << 32);
+      b.meta[p] = make_ulonglong2((uint64_t)held | (bp << 32), (uint64_t)new_last | ((uint64_t)first_new << 32));
+      st[i] = BL_ALLOC;
     }
     __syncthreads();  // wave_off and block_base are rewritten by the next round
   }
@@ -340,30 +334,34 @@ __global__ __launch_bounds__(256) void k_bl_place(TableView t, BucketView b, con
                                                   uint8_t* __restrict__ status) {
   const uint64_t stride = (uint64_t)gridDim.x * 256;
   long long stored = 0;
-  // counts were only cut back (and tickets past them refused) if the allocation ran out of pool
-  const bool cut = *(volatile unsigned long long*)(t.size + CTR_BL_CUT) != 0;
   for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
     uint8_t code = st[i];
     if (code == BL_PLACED) {  // stored in phase 1 (and counted there)
       code = ST_OK;
-    } else if (code == ST_OK || code == BL_FOLLOW) {
+    } else if (code == ST_OK || code == BL_FOLLOW || code == BL_ALLOC) {
+      const bool allocator = code == BL_ALLOC;
       code = ST_OK;
       const uint64_t p = pos[i], tk = ticket[i];
-      if (cut && tk >= slot_value(t.slots[p])) {
-        code = ST_FULL;
-      } else {
-        // bucket 0 is the slot's own; a ticket below the batch's first new bucket lies in the key's
-        // last bucket before the batch (the link of the first new bucket, or the record's last
-        // bucket if the batch allocated none); the others in the buckets allocated in phase 2
-        const uint64_t bi = bl_bucket_of(b, tk);
-        uint64_t o = p * b.s0;
-        if (bi >= 1) {
-          const ulonglong2 mt = b.meta[p];
-          const uint64_t b0 = bl_buckets(b, (uint32_t)mt.x);
-          const uint32_t first_new = (uint32_t)(mt.y >> 32);
-          if (bi >= b0) o = first_new + bl_words(b, b0 > 1 ? b0 : 1, bi);
-          else o = first_new != 0xFFFFFFFFu ? b.pool[first_new] : (uint32_t)mt.y;
+      // bucket 0 is the slot's own; a later bucket's offset comes from the slot's record: one the
+      // batch allocated lies at a known distance from the first new one, the key's last bucket
+      // before the batch is the one the first new bucket links to (or the record's last bucket)
+      const uint64_t bi = bl_bucket_of(b, tk);
+      uint64_t o = p * b.s0;
+      if (bi >= 1) {
+        const ulonglong2 rec = b.meta[p];
+        const uint32_t held = (uint32_t)rec.x, bp = (uint32_t)(rec.x >> 32), fn = (uint32_t)(rec.y >> 32);
+        if (fn == BL_CUT) {  // the pool ran out: the key keeps the values its held buckets take
+          const uint64_t keep = bl_S(b, held);
+          if (allocator) {
+            const uint64_t w = t.slots[p];
+            atomicExch((unsigned long long*)&t.slots[p], (unsigned long long)make_slot(slot_key(w), (uint32_t)keep));
+          }
+          if (tk >= keep) code = ST_FULL;
         }
+        if (code == ST_OK)
+          o = bi >= bp ? fn + bl_words(b, bp, bi) : (fn < BL_CUT ? b.pool[fn] : (uint32_t)rec.y);
+      }
+      if (code == ST_OK) {
         b.pool[o + (bi >= 1 ? 1 : 0) + (tk - bl_S(b, bi))] = values[i];
         ++stored;
       }
@@ -546,6 +544,7 @@ struct BlErase {
   static constexpr int SPL = L::SPL;
   L ln;
   TableView t;
+  ulonglong2* meta;
   const uint32_t* __restrict__ keys;
   uint8_t* __restrict__ status;
   uint64_t i = 0;
@@ -578,6 +577,7 @@ struct BlErase {
         if (slot_key(res) == k) {  // else erased by another group of this launch
           ok = 1;
           added -= (long long)slot_value(res);
+          meta[idx].x = 0ull;  // no buckets recorded: a key that claims this slot later starts afresh
         }
       }
       return done(g.bcast(ok, r) ? ST_OK : ST_NOT_FOUND);
@@ -590,10 +590,12 @@ struct BlErase {
 };
 
 template <int G, int W>
-__global__ __launch_bounds__(BLOCK) void k_bl_erase(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys,
-                                                    uint64_t n, uint8_t* __restrict__ status) {
+__global__ __launch_bounds__(BLOCK) void k_bl_erase(TableView t, WorkCtl ctl, ulonglong2* meta,
+                                                    const uint32_t* __restrict__ keys, uint64_t n,
+                                                    uint8_t* __restrict__ status) {
   BlErase<G, W> op;
   op.t = t;
+  op.meta = meta;
   op.keys = keys;
   op.status = status;
   drive<G>(n, ctl, op);
@@ -605,7 +607,7 @@ __global__ __launch_bounds__(64) void k_bl_zero1(unsigned long long* p) {
 
 __global__ __launch_bounds__(256) void k_bl_reset(ulonglong2* meta, uint64_t C) {
   const uint64_t stride = (uint64_t)gridDim.x * 256;
-  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < C; i += stride) meta[i].x = ~0ull;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < C; i += stride) meta[i].x = 0ull;
 }
 
 __global__ __launch_bounds__(256) void k_bl_dump_last(const ulonglong2* __restrict__ meta, uint64_t C,
@@ -680,9 +682,8 @@ hc_err launch_bl_finish(const TableView& t, const BucketView& b, const uint32_t*
   uint64_t ga = (n + ALLOC_BLOCK - 1) / ALLOC_BLOCK;
   const uint64_t cap = (uint64_t)device_cu_count() * 2;
   if (ga > cap) ga = cap;
-  hipLaunchKernelGGL(k_bl_zero1, dim3(1), dim3(64), 0, s, t.size + CTR_BL_CUT);
-  if (hc_err r = check_launch("bucket list flag"); r != HC_OK) return r;
-  hipLaunchKernelGGL(k_bl_alloc, dim3((unsigned)(ga ? ga : 1)), dim3(ALLOC_BLOCK), 0, s, t, b, n, pos, ticket, st);
+  hipLaunchKernelGGL(k_bl_alloc, dim3((unsigned)(ga ? ga : 1)), dim3(ALLOC_BLOCK), 0, s, t, b, n, pos, ticket,
+                     const_cast<uint8_t*>(st));
   if (hc_err r = check_launch("bucket list allocation"); r != HC_OK) return r;
   hipLaunchKernelGGL(k_bl_place, dim3(stream_grid(n)), dim3(256), 0, s, t, b, values, n, pos, ticket,
                      const_cast<uint8_t*>(st), status);
@@ -727,13 +728,13 @@ hc_err launch_bl_write(const TableView& t, const BucketView& b, uint32_t G, uint
   return check_launch("bucket list long write");
 }
 
-hc_err launch_bl_erase(const TableView& t, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n, uint8_t* status,
-                       hipStream_t s) {
+hc_err launch_bl_erase(const TableView& t, const BucketView& b, uint32_t G, uint32_t W, const uint32_t* keys,
+                       uint64_t n, uint8_t* status, hipStream_t s) {
   return dispatch_gw(G, W, [&](auto g, auto w) -> hc_err {
     constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
     auto k = k_bl_erase<GG, WW>;
     const unsigned grid = grid_for(k, n, GG);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid, s), keys, n, status);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, s, t, work_for(n, GG, grid, s), b.meta, keys, n, status);
     return check_launch("bucket list erase");
   });
 }

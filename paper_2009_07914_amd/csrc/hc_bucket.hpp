@@ -24,14 +24,18 @@ struct BucketView {
   uint64_t s0;                     // size of bucket 0: slot p's bucket 0 is the words [p * s0, (p + 1) * s0)
   uint64_t bump;                   // C * s0: later buckets are allocated from here on
   unsigned long long* pool_next;   // words allocated after `bump`
-  // per key slot, one 16-byte record (the allocation reads and writes it, placement and the
-  // list walks read it: one line each):
-  //   stamp = (~batch << 32) | first ticket of the key in the latest batch that added to it
+  // per key slot, one 16-byte record, written by the allocation pass of a batch that gives the
+  // key more than bucket 0 can hold, read by placement and the list walks (one line each):
+  //   x = buckets the key holds (low 32; 0 after hc_clear or an erase: none recorded)
+  //       | buckets it held before that batch (high 32)
   //   y = pool offset of the key's last bucket (low 32; meaningful once the key has more than
-  //       one bucket) | first bucket that batch allocated (high 32, ~0 if none)
+  //       one bucket) | first bucket that batch allocated (high 32: BL_NONE if none, BL_CUT if
+  //       the pool ran out)
   ulonglong2* meta;
-  uint32_t epoch;                  // batch number (1 ..)
 };
+
+constexpr uint32_t BL_NONE = 0xFFFFFFFFu;
+constexpr uint32_t BL_CUT = 0xFFFFFFFEu;  // never a bucket offset: a bucket takes >= 2 words below 2^32
 
 // Bucket sizes s_0 = s0, s_i = min(ceil(growth * s_{i-1}), smax): the ramp up to
 // the cap, as cumulative sums (host side).  Returns false if the ramp is longer
@@ -62,20 +66,19 @@ hc_err launch_bl_count(const TableView& t, uint32_t G, uint32_t W, const uint32_
 // Values of keys into out[offsets[i] .. offsets[i+1]); lists longer than BL_LONG_LIST
 // values are copied by whole blocks.  Workspace: bl_write_workspace(n) bytes.
 constexpr uint64_t BL_LONG_LIST = 1024;
-// Phase-1 states beside ST_OK (a candidate for allocating its key's new buckets): BL_PLACED, the
-// value is already stored (the pair claimed its key's slot and bucket 0); BL_FOLLOW, a pair of the
-// same key held a smaller ticket of the batch first, so this one only places its value.
+// Phase states beside ST_OK (a candidate for allocating its key's new buckets): BL_PLACED, the
+// value is already stored (the pair claimed its key's slot and bucket 0); BL_FOLLOW, the pair
+// only places its value (a pair of a sorted run other than the run's last); BL_ALLOC, the pair
+// held its key's last ticket and allocated (it also fixes the count if the pool ran out).
 constexpr uint8_t BL_PLACED = 0x80;
-// Word of the table's counter block set while a bucket list insert runs once the pool ran out and
-// a key's count was cut back (placement then checks tickets against the counts).
-constexpr int CTR_BL_CUT = 3;
 constexpr uint8_t BL_FOLLOW = 0x81;
+constexpr uint8_t BL_ALLOC = 0x82;
 uint64_t bl_write_workspace(uint64_t n);
 hc_err launch_bl_write(const TableView& t, const BucketView& b, uint32_t G, uint32_t W, const uint32_t* keys,
                        uint64_t n, const uint64_t* offsets, uint32_t* out, void* ws, hipStream_t s);
-hc_err launch_bl_erase(const TableView& t, uint32_t G, uint32_t W, const uint32_t* keys, uint64_t n, uint8_t* status,
-                       hipStream_t s);
-// stamp of every slot = ~0 (a fill kernel); the last-bucket offsets stay.
+hc_err launch_bl_erase(const TableView& t, const BucketView& b, uint32_t G, uint32_t W, const uint32_t* keys,
+                       uint64_t n, uint8_t* status, hipStream_t s);
+// Every slot's record says "no buckets" (a fill kernel).
 hc_err launch_bl_reset(const BucketView& b, uint64_t C, hipStream_t s);
 // Last-bucket offset of every slot (the low words of the records) into dst[0..C).
 hc_err launch_bl_dump_last(const BucketView& b, uint64_t C, uint32_t* dst, hipStream_t s);

@@ -54,8 +54,7 @@ struct hc_table_s {
   uint32_t bl_m = 0, bl_smax = 0, bl_s0 = 1;
   uint32_t* d_pool = nullptr;
   uint64_t pool_cap = 0;
-  ulonglong2* d_meta = nullptr;  // per slot: batch stamp, batch bucket offsets
-  uint32_t epoch = 0;
+  ulonglong2* d_meta = nullptr;  // per slot: buckets held (and before the latest batch), last and first new bucket
 };
 
 namespace hc {
@@ -233,18 +232,7 @@ static BucketView bview_of(const hc_table_s* t) {
   b.bump = t->C * t->bl_s0;     // the first C * s0 words hold the slots' first buckets
   b.pool_next = t->d_size + 1;  // the size counter and the pool counter share one allocation
   b.meta = t->d_meta;
-  b.epoch = t->epoch;
   return b;
-}
-
-// A new insert batch of a bucket list table: the next batch number.
-static hc_err next_bucket_batch(hc_table_s* t, hipStream_t s) {
-  if (t->epoch == 0xFFFFFFFEu) {  // batch numbers run out: restart them on fresh stamps
-    if (hc_err r = launch_bl_reset(bview_of(t), t->C, s); r != HC_OK) return r;
-    t->epoch = 0;
-  }
-  ++t->epoch;
-  return HC_OK;
 }
 
 // 32-bit entry points on a 64-bit table.
@@ -838,10 +826,9 @@ hc_err hc_clear(hc_table t, void* stream) {
   hipLaunchKernelGGL(k_fill_empty, dim3((unsigned)blocks), dim3(BLOCK), 0, (hipStream_t)stream,
                      reinterpret_cast<ulonglong2*>(t->slots), pairs, t->d_size);
   if ((r = check_launch("clear")) != HC_OK) return r;
-  if (t->kind == HC_BUCKET_LIST && t->d_meta != nullptr) {  // empty pool, fresh batch stamps (once allocated)
+  if (t->kind == HC_BUCKET_LIST && t->d_meta != nullptr) {  // empty pool, records of no buckets (once allocated)
     if ((r = launch_zero_u64(t->d_size + 1, 1, (hipStream_t)stream)) != HC_OK) return r;
     if ((r = launch_bl_reset(bview_of(t), t->C, (hipStream_t)stream)) != HC_OK) return r;
-    t->epoch = 0;
   }
   return HC_OK;
 }
@@ -871,7 +858,6 @@ hc_err hc_insert(hc_table t, const uint32_t* d_keys, const uint32_t* d_values, u
     CallWs ws(s);
     if ((r = ws.get(bl_insert_workspace(n))) != HC_OK) return r;
     if ((r = order_begin(t, s)) != HC_OK) return r;
-    if ((r = next_bucket_batch(t, s)) != HC_OK) return r;
     return order_end(t, s, launch_bl_insert(view_of(t), bview_of(t), g, t->window, d_keys, d_values, n, d_status,
                                             ws.p, s));
   }
@@ -909,7 +895,8 @@ hc_err hc_erase(hc_table t, const uint32_t* d_keys, uint64_t n, uint8_t* d_statu
   if (n == 0) return HC_OK;
   if (d_keys == nullptr) return fail(HC_E_ARG, "keys is NULL");
   if ((r = set_device(t)) != HC_OK) return r;
-  if (t->kind == HC_BUCKET_LIST) return launch_bl_erase(view_of(t), g, t->window, d_keys, n, d_status, (hipStream_t)stream);
+  if (t->kind == HC_BUCKET_LIST)
+    return launch_bl_erase(view_of(t), bview_of(t), g, t->window, d_keys, n, d_status, (hipStream_t)stream);
   if (t->kind == HC_HASH_SET)
     return launch_set(SET_ERASE, view_of(t), g, t->window, d_keys, n, d_status, (hipStream_t)stream);
   return launch_erase(view_of(t), (int)t->kind, g, t->window, d_keys, n, d_status, (hipStream_t)stream);
@@ -1041,7 +1028,6 @@ hc_err hc_insert_grouped(hc_table t, const uint32_t* d_keys, const uint32_t* d_v
   if (t->kind == HC_BUCKET_LIST) {
     if ((r = ws.get(bl_grouped_workspace_bytes(n))) != HC_OK) return r;
     if ((r = order_begin(t, s)) != HC_OK) return r;
-    if ((r = next_bucket_batch(t, s)) != HC_OK) return r;
     return order_end(t, s, launch_bl_grouped(view_of(t), bview_of(t), t->group, t->window, d_keys, d_values, n,
                                              ws.p, s));
   }
