@@ -268,15 +268,16 @@ __global__ __launch_bounds__(ALLOC_BLOCK) void k_bl_alloc(TableView t, BucketVie
     bool mine = false;
     if (i < n && st[i] == ST_OK) {
       p = pos[i];
-      // the count after phase 1 (nothing changes it before phase 3): its last ticket allocates
+      // the count after phase 1 (nothing changes it before phase 3): its last ticket allocates,
+      // unless bucket 0 still holds every value (then the record is neither read nor written)
       const uint64_t c1 = slot_value(t.slots[p]);
-      mine = (uint64_t)ticket[i] + 1 == c1;
+      mine = (uint64_t)ticket[i] + 1 == c1 && c1 > b.s0;  // more than bucket 0 (s_0 values) holds
       if (mine) {
+        b1 = bl_buckets(b, c1);
         const ulonglong2 rec = b.meta[p];
         const uint32_t held = (uint32_t)rec.x;  // buckets before this batch (0 or 1: bucket 0 only)
         bp = held > 1 ? held : 1;                // bucket 0 is the slot's own, never allocated
         old_last = held > 1 ? (uint32_t)rec.y : (uint32_t)(p * b.s0);
-        b1 = bl_buckets(b, c1);
         words = b1 > bp ? bl_words(b, bp, b1) : 0;
       }
     }
