@@ -20,11 +20,15 @@
 
 namespace hc {
 
+// 512 threads per block: a 2048-key tile (half the atomics per hot key of a 1024-key tile)
+// with the LDS per wavefront and the registers per lane of 1024 keys over 256 threads; the
+// kernel is held to 80 VGPRs (6 wavefronts per SIMD, 3 blocks per CU by LDS), spilling a few.
+constexpr int AGG_BLOCK = 512;
 constexpr int AGG_PER_THREAD = 4;
-constexpr int AGG_TILE = BLOCK * AGG_PER_THREAD;  // keys per tile
-constexpr int AGG_HASH = 2 * AGG_TILE;            // LDS hash slots: load at most 1/2
-constexpr int AGG_HASH_BITS = 11;
-constexpr int AGG_SLOTS_PER_THREAD = AGG_HASH / BLOCK;
+constexpr int AGG_TILE = AGG_BLOCK * AGG_PER_THREAD;  // keys per tile
+constexpr int AGG_HASH = 2 * AGG_TILE;                // LDS hash slots: load at most 1/2
+constexpr int AGG_HASH_BITS = 12;
+constexpr int AGG_SLOTS_PER_THREAD = AGG_HASH / AGG_BLOCK;
 static_assert((1 << AGG_HASH_BITS) == AGG_HASH, "hash size");
 constexpr uint32_t AGG_NONE = 0xFFFFu;
 
@@ -35,7 +39,7 @@ struct AggUpsert : InsertUnique<G, W, KIND_COUNT> {
   __device__ __forceinline__ void end() {}
 };
 
-// Block-wide exclusive scan of one value per thread (BLOCK threads).
+// Block-wide exclusive scan of one value per thread (AGG_BLOCK threads).
 __device__ __forceinline__ uint32_t agg_block_scan(uint32_t x, uint32_t* total, uint32_t* wsum) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   uint32_t incl = x;
@@ -48,7 +52,7 @@ __device__ __forceinline__ uint32_t agg_block_scan(uint32_t x, uint32_t* total, 
   __syncthreads();
   uint32_t before = 0, all = 0;
 #pragma unroll
-  for (int w = 0; w < BLOCK / 64; ++w) {
+  for (int w = 0; w < AGG_BLOCK / 64; ++w) {
     const uint32_t v = wsum[w];
     before += (w < wave) ? v : 0u;
     all += v;
@@ -59,13 +63,13 @@ __device__ __forceinline__ uint32_t agg_block_scan(uint32_t x, uint32_t* total, 
 }
 
 template <int G, int W>
-__global__ __launch_bounds__(BLOCK) void k_count_agg(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys,
+__global__ __launch_bounds__(AGG_BLOCK, 6) void k_count_agg(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys,
                                                      uint64_t n, uint8_t* __restrict__ status) {
   __shared__ uint32_t hkey[AGG_HASH];  // tile keys; after compaction the distinct keys in [0, m)
   __shared__ uint32_t hcnt[AGG_HASH];  // multiplicities, compacted likewise
   __shared__ uint16_t hpos[AGG_HASH];  // compact index of each used hash slot
   __shared__ uint8_t cres[AGG_TILE];   // upsert status of each distinct key
-  __shared__ uint32_t wsum[BLOCK / 64];
+  __shared__ uint32_t wsum[AGG_BLOCK / 64];
   __shared__ unsigned long long s_tile;
 
   AggUpsert<G, W> op;
@@ -79,8 +83,8 @@ __global__ __launch_bounds__(BLOCK) void k_count_agg(TableView t, WorkCtl ctl, c
     if (threadIdx.x == 0) s_tile = atomicAdd(ctl.counters, 1ull);
 #pragma unroll
     for (int j = 0; j < AGG_SLOTS_PER_THREAD; ++j) {
-      hkey[j * BLOCK + threadIdx.x] = 0u;
-      hcnt[j * BLOCK + threadIdx.x] = 0u;
+      hkey[j * AGG_BLOCK + threadIdx.x] = 0u;
+      hcnt[j * AGG_BLOCK + threadIdx.x] = 0u;
     }
     __syncthreads();
     const uint64_t tile = s_tile;
@@ -93,7 +97,7 @@ __global__ __launch_bounds__(BLOCK) void k_count_agg(TableView t, WorkCtl ctl, c
     uint32_t creator = 0;  // bit j: this thread's j-th key created its entry
 #pragma unroll
     for (int j = 0; j < AGG_PER_THREAD; ++j) {
-      const uint64_t i = base + (uint64_t)j * BLOCK + threadIdx.x;
+      const uint64_t i = base + (uint64_t)j * AGG_BLOCK + threadIdx.x;
       slot[j] = AGG_NONE;
       if (i >= n) continue;
       const uint32_t k = keys[i];
@@ -138,8 +142,8 @@ __global__ __launch_bounds__(BLOCK) void k_count_agg(TableView t, WorkCtl ctl, c
     }
     __syncthreads();
 
-    // 3. upsert the m distinct keys: each wavefront a quarter of them, groups in order
-    const uint64_t lo = (uint64_t)m * wave / (BLOCK / 64), hi = (uint64_t)m * (wave + 1) / (BLOCK / 64);
+    // 3. upsert the m distinct keys: each wavefront an eighth of them, groups in order
+    const uint64_t lo = (uint64_t)m * wave / (AGG_BLOCK / 64), hi = (uint64_t)m * (wave + 1) / (AGG_BLOCK / 64);
     drive_range<G>(lo, hi, op);
     __syncthreads();
 
@@ -148,7 +152,7 @@ __global__ __launch_bounds__(BLOCK) void k_count_agg(TableView t, WorkCtl ctl, c
 #pragma unroll
       for (int j = 0; j < AGG_PER_THREAD; ++j) {
         if (slot[j] == AGG_NONE) continue;
-        const uint64_t i = base + (uint64_t)j * BLOCK + threadIdx.x;
+        const uint64_t i = base + (uint64_t)j * AGG_BLOCK + threadIdx.x;
         const uint8_t r = cres[hpos[slot[j]]];
         status[i] = (r == ST_OK && !((creator >> j) & 1u)) ? (uint8_t)ST_DUPLICATE : r;
       }
@@ -170,10 +174,11 @@ hc_err launch_count_insert(const TableView& t, uint32_t G, uint32_t W, const uin
     constexpr int GG = decltype(g)::value, WW = decltype(w)::value;
     auto k = k_count_agg<GG, WW>;
     const uint64_t ntiles = (n + AGG_TILE - 1) / AGG_TILE;
-    const uint64_t cap = (uint64_t)device_cu_count() * (uint64_t)blocks_per_cu(reinterpret_cast<const void*>(k));
+    const uint64_t per_cu = (uint64_t)blocks_per_cu_threads(reinterpret_cast<const void*>(k), AGG_BLOCK);
+    const uint64_t cap = (uint64_t)device_cu_count() * per_cu;
     const unsigned grid = (unsigned)(ntiles < cap ? (ntiles ? ntiles : 1) : cap);
     WorkCtl ctl = work_for(0, GG, grid, stream);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(BLOCK), 0, stream, t, ctl, keys, n, status);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(AGG_BLOCK), 0, stream, t, ctl, keys, n, status);
     return check_launch("counting insert");
   });
 }
