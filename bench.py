@@ -557,7 +557,7 @@ def bench_multi(args):
     pos = np.searchsorted(u, w["queries"])
     hit = (pos < u.size) & (u[np.minimum(pos, u.size - 1)] == w["queries"])
     expect[hit] = c[pos[hit]]
-    # per-key insert: equal keys of each 1024-key tile are combined in LDS, then one upsert per
+    # per-key insert: equal keys of each 2048-key tile are combined in LDS, then one upsert per
     # distinct key of the tile (the hottest key costs one atomic per tile, not one per occurrence)
     st_ct = torch.empty(n, dtype=torch.uint8, device=dev)
     ins = ev_time((ct.clear, lambda: hc.hc_insert(ct.handle, keys, None, None, args.group_insert, s)), reps)[args.warmup:]
