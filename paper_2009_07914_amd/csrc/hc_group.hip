@@ -55,6 +55,10 @@ constexpr uint64_t SMALL_RUN = 128;   // shorter runs are claimed by one group o
 constexpr int IROUNDS = 10;           // claim rounds of heavy runs
 constexpr uint64_t ROUND_MIN = 4ull * GB * GB_SPL;  // heavy runs with fewer values left finish in one block
 constexpr int QROUNDS_MAX = 16;       // long-query rounds; round r gives each open query 4^r segments
+// Slots per lane of a long-query segment: a segment item costs a chain of dependent
+// loads and atomics (item, entry, query, key; completion) whatever its size, so
+// segments are made twice the block-mode width (512 windows of 16 slots per item).
+constexpr int LQ_SPL = 8;
 
 struct KeySeq {
   uint32_t w0, step;
@@ -694,17 +698,17 @@ __global__ __launch_bounds__(256) void k_zero_u64(unsigned long long* p, uint32_
 }
 
 // Scan windows [l, l + 1 window of this thread) ... of one segment: the thread's
-// GB_SPL slots of window l (if l < lend), its match mask and whether the window
+// LQ_SPL slots of window l (if l < lend), its match mask and whether the window
 // part holds an empty slot.
 template <int W>
 __device__ __forceinline__ uint32_t seg_slots(const TableView& t, const KeySeq& q, uint32_t k, uint64_t l,
-                                              uint64_t lend, uint32_t j0, uint64_t (&word)[GB_SPL], bool& empty) {
+                                              uint64_t lend, uint32_t j0, uint64_t (&word)[LQ_SPL], bool& empty) {
   uint32_t mm = 0;
   empty = false;
   if (l < lend) {
-    load_slots<GB_SPL>(t.slots, (uint64_t)window_at(t, q, l) * W + j0, word);
+    load_slots<LQ_SPL>(t.slots, (uint64_t)window_at(t, q, l) * W + j0, word);
 #pragma unroll
-    for (int j = 0; j < GB_SPL; ++j) {
+    for (int j = 0; j < LQ_SPL; ++j) {
       mm |= (uint32_t)(slot_key(word[j]) == k) << j;
       empty |= slot_key(word[j]) == KEY_EMPTY;
     }
@@ -721,11 +725,11 @@ __device__ __forceinline__ bool seg_visit(const TableView& t, const KeySeq& q, u
                                           uint64_t i, unsigned long long* cursor, uint64_t* __restrict__ offsets,
                                           uint32_t* __restrict__ out, uint64_t base, uint64_t limit, uint32_t* lds,
                                           unsigned long long* s_base) {
-  const uint32_t widx = (threadIdx.x * GB_SPL) / W, j0 = (threadIdx.x * GB_SPL) % W;
-  uint64_t word[GB_SPL];
+  const uint32_t widx = (threadIdx.x * LQ_SPL) / W, j0 = (threadIdx.x * LQ_SPL) % W;
+  uint64_t word[LQ_SPL];
   bool empty;
   const uint32_t mm = seg_slots<W>(t, q, k, l0 + widx, lend, j0, word, empty);
-  // matches (< 2^13 per block) in the low 16 bits, windows with an empty slot above
+  // matches (at most GB * LQ_SPL = 2^13 per block) in the low 16 bits, windows with an empty slot above
   uint32_t tot;
   const uint32_t ex = block_scan((uint32_t)__popc(mm) | ((uint32_t)empty << 16), &tot, lds) & 0xFFFFu;
   const uint32_t nm = tot & 0xFFFFu;
@@ -738,7 +742,7 @@ __device__ __forceinline__ bool seg_visit(const TableView& t, const KeySeq& q, u
     const uint64_t b = *s_base;
     uint64_t rank = b + ex;
 #pragma unroll
-    for (int j = 0; j < GB_SPL; ++j) {
+    for (int j = 0; j < LQ_SPL; ++j) {
       if ((mm >> j) & 1u) {
         if (rank < limit) out[base + rank] = slot_value(word[j]);
         ++rank;
@@ -752,17 +756,22 @@ __device__ __forceinline__ bool seg_visit(const TableView& t, const KeySeq& q, u
 
 // One round: every open entry gets S segments of SEGW windows from its next
 // window on.  The last segment of an entry to finish decides whether it goes on.
+// Items are latency chains (see LQ_SPL), so the kernel is held to the registers of
+// two blocks per CU (8 wavefronts per SIMD).
 template <int W, int MODE>
-__global__ __launch_bounds__(GB) void k_long_round(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys,
-                                                   LongState ls, uint32_t round, uint64_t* __restrict__ offsets,
-                                                   uint32_t* __restrict__ out) {
-  constexpr uint64_t SEGW = GB * GB_SPL / W;
+__global__ __launch_bounds__(GB, 8) void k_long_round(TableView t, WorkCtl ctl, const uint32_t* __restrict__ keys,
+                                                      LongState ls, uint32_t round, uint64_t* __restrict__ offsets,
+                                                      uint32_t* __restrict__ out) {
+  constexpr uint64_t SEGW = GB * LQ_SPL / W;
   __shared__ uint32_t lds[GB_WAVES];
   __shared__ unsigned long long s_item, s_base;
   const uint64_t S = 1ull << (2 * round);
   const uint32_t* lin = ls.lists[round & 1];
   uint32_t* lout = ls.lists[(round + 1) & 1];
   const uint64_t N = ls.nopen[round] * S;
+  // no open entry (every later round of a pass with no long query): no block takes an
+  // item, so the work counters stay at zero and nothing is left to reset
+  if (N == 0) return;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(ctl.counters, 1ull);
     __syncthreads();
@@ -1072,7 +1081,7 @@ hc_err launch_long_queries(const TableView& t, uint32_t W, int mode, const uint3
       auto kr = k_long_round<WW, MODE>;
       const unsigned grid = block_grid(reinterpret_cast<const void*>(kr), ~0ull);
       // rounds 0..R-1 give an entry (4^R - 1) / 3 segments in all: enough for the whole sequence
-      const uint32_t rounds = rounds_to_cover(t.P, GB * GB_SPL / WW);
+      const uint32_t rounds = rounds_to_cover(t.P, GB * LQ_SPL / WW);
       if (rounds > (uint32_t)QROUNDS_MAX) return fail(HC_E_ARG, "sequence too long for the long-query rounds");
       for (uint32_t round = 0; round < rounds; ++round) {
         WorkCtl ctl = work_for(0, 64, grid * (GB / 256), s);
