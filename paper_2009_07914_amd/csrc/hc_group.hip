@@ -392,6 +392,7 @@ __global__ __launch_bounds__(GB) void k_walk_round(TableView t, WorkCtl ctl, con
   const uint32_t* lin = ws.lists[round & 1];
   uint32_t* lout = ws.lists[(round + 1) & 1];
   const uint64_t N = ws.nopen[round] * S;
+  if (N == 0) return;  // no open walk: no item is taken and the work counters stay at zero
   const uint32_t widx = (threadIdx.x * GB_SPL) / W, j0 = (threadIdx.x * GB_SPL) % W;
   for (;;) {
     if (threadIdx.x == 0) {
@@ -460,6 +461,7 @@ __global__ __launch_bounds__(GB) void k_walk_claim(TableView t, WorkCtl ctl, con
   __shared__ uint32_t lds[GB_WAVES];
   __shared__ unsigned long long s_item;
   const uint64_t L = *ws.nwalk < ws.cap ? *ws.nwalk : ws.cap;
+  if (L == 0) return;  // no handed-over run: no item is taken and the work counters stay at zero
   uint64_t added = 0;
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(ctl.counters, 1ull);
@@ -545,6 +547,7 @@ __global__ __launch_bounds__(GB) void k_heavy_round(TableView t, WorkCtl ctl, co
   __shared__ unsigned long long s_item, s_base;
   __shared__ uint32_t s_h;
   const uint64_t H = *nheavy, T = hs.seg[H];
+  if (T == 0) return;  // no segment this round: no item is taken and the work counters stay at zero
   const uint32_t widx = (threadIdx.x * GB_SPL) / W, j0 = (threadIdx.x * GB_SPL) % W;
   uint64_t added = 0;
   for (;;) {
