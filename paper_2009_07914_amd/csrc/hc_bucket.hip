@@ -245,8 +245,8 @@ __global__ __launch_bounds__(256) void k_bl_expand(const uint64_t* __restrict__ 
 
 // ---- phase 2: buckets per key -----------------------------------------------------------
 
-// Run by every pair; the pair whose ticket is its key's first of the batch
-// allocates.  Pool words are taken with one atomic per block of 1024 pairs (a
+// Run by every pair; the pair holding its key's last ticket of the batch (ticket + 1
+// equals the slot's count after phase 1) allocates.  Pool words are taken with one atomic per block of 1024 pairs (a
 // scan over the block's wavefronts in LDS): every pool atomic hits the same
 // word, so their number, not their bytes, bounds this kernel.
 constexpr int ALLOC_BLOCK = 1024;
