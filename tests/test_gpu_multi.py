@@ -236,7 +236,7 @@ def test_grouped_counting_reserved_and_full(hc):
     check_layout(t2, oracle.COUNT)
 
 
-@pytest.mark.parametrize("window", [16, 64])
+@pytest.mark.parametrize("window", [8, 16, 32, 64])
 def test_grouped_many_rounds_against_grouping(hc, window):
     """A hot key with ~430 K copies (2^21 pairs, Zipf(1.1) over 2^8 keys, table 2^22 slots): heavy runs go
     through several claim rounds and the long queries through several segment rounds.  The per-pair
